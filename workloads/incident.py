@@ -1,0 +1,93 @@
+"""Seeded, synthetic inputs: incident plane waves and their azimuthal modes.
+
+The plane wave of Section 6 (eq:pw): E = (d x p) x d exp(i k0 d.x) and
+H = sqrt(eps0/mu0) (d x p) exp(i k0 d.x) (H as printed for eps0 = mu0 = 1,
+scaled so that curl E = i omega mu0 H for any eps0, mu0).  The right-hand side
+of the Mueller system is handed to the solver as azimuthal Fourier modes
+f_m = (1/2pi) int f(theta) e^{-i m theta} d theta of the tangential traces, in
+(t, e_theta) components at every node of the generating curve (Section 3):
+
+    row 4j+0: i omega mu0 (n x H_inc)_t      row 4j+2: i omega eps0 (n x E_inc)_t
+    row 4j+1: i omega mu0 (n x H_inc)_theta  row 4j+3: i omega eps0 (n x E_inc)_theta
+
+with (n x V)_t = V_theta and (n x V)_theta = -(r' V_r + z' V_z).  Modes are
+computed with an FFT of the sampled traces; this is input preparation, not
+part of the method.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def paper_default_direction():
+    """d and p at the angles used throughout Section 6 (eq. incidentdirection)."""
+    th1, ph1, th2, ph2 = np.pi / 3, 2 * np.pi / 3, np.pi / 2, np.pi / 3
+    d = np.array([np.cos(th1) * np.sin(ph1), np.sin(th1) * np.sin(ph1), np.cos(ph1)])
+    p = np.array([np.cos(th2) * np.sin(ph2), np.sin(th2) * np.sin(ph2), np.cos(ph2)])
+    return d, p
+
+
+def tilted_direction(deg: float):
+    """d at `deg` from +z in the x-z plane, p perpendicular to d in that plane."""
+    a = np.deg2rad(deg)
+    return np.array([np.sin(a), 0.0, np.cos(a)]), np.array([np.cos(a), 0.0, -np.sin(a)])
+
+
+def random_directions(seed: int, count: int):
+    """Directions uniform on S^2 (normalized Gaussians) and polarizations p with
+    |p x d| >= 0.1 so that (d x p) x d never degenerates."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        p = rng.standard_normal(3)
+        p /= np.linalg.norm(p)
+        if np.linalg.norm(np.cross(d, p)) < 0.1:
+            continue
+        out.append((d, p))
+    return out
+
+
+def plane_wave(d, p, k0, eps0=1.0, mu0=1.0):
+    """Callables E(x), H(x) for x of shape [..., 3]."""
+    d = np.asarray(d, float)
+    p = np.asarray(p, float)
+    q = np.cross(d, p)
+    e = np.cross(q, d)
+    h = np.sqrt(eps0 / mu0) * q
+
+    def ph(x):
+        return np.exp(1j * k0 * (x @ d))[..., None]
+    return (lambda x: e * ph(x)), (lambda x: h * ph(x))
+
+
+def rhs_modes(curve, waves, k0, m_lo, m_hi, eps0=1.0, mu0=1.0, n_theta=None):
+    """Right-hand-side modes [m_hi - m_lo + 1, len(waves), 4N] (complex128)."""
+    N = curve.n
+    omega = k0 / np.sqrt(eps0 * mu0)
+    rmax = float(np.max(curve.r))
+    mmax = max(abs(m_lo), abs(m_hi))
+    if n_theta is None:
+        n_theta = 1 << int(np.ceil(np.log2(2 * (mmax + k0 * rmax) + 64)))
+    th = 2 * np.pi * np.arange(n_theta) / n_theta
+    ct, st = np.cos(th), np.sin(th)
+    x = np.stack([curve.r[:, None] * ct[None, :], curve.r[:, None] * st[None, :],
+                  np.broadcast_to(curve.z[:, None], (N, n_theta))], axis=-1)
+    rp = -curve.nz  # r' = -n_z
+    zp = curve.nr   # z' = n_r
+    out = np.zeros((m_hi - m_lo + 1, len(waves), 4 * N), dtype=complex)
+    ms = np.arange(m_lo, m_hi + 1)
+    for w, (d, p) in enumerate(waves):
+        Ef, Hf = plane_wave(d, p, k0, eps0, mu0)
+        for fld, base, coef in ((Hf, 0, 1j * omega * mu0), (Ef, 2, 1j * omega * eps0)):
+            V = fld(x)
+            Vr = V[..., 0] * ct + V[..., 1] * st
+            Vt = -V[..., 0] * st + V[..., 1] * ct
+            Vz = V[..., 2]
+            tr_t = Vt
+            tr_th = -(rp[:, None] * Vr + zp[:, None] * Vz)
+            for comp, tr in ((0, tr_t), (1, tr_th)):
+                F = np.fft.fft(tr, axis=1) / n_theta  # F[k] = (1/L) sum f e^{-i k theta}
+                out[:, w, 4 * np.arange(N) + base + comp] = coef * F[:, ms % n_theta].T
+    return out
