@@ -1,0 +1,151 @@
+/*
+ * msv: modal-kernel tabulation, Mueller-Nystrom assembly and per-mode solves
+ * for electromagnetic scattering from a penetrable body of revolution, on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lai & O'Neil, "An FFT-accelerated direct solver for electromagnetic
+ * scattering from penetrable axisymmetric objects".  Section numbers below
+ * refer to that paper.
+ *
+ * Conventions shared by every call
+ *  - Complex numbers are {re, im} pairs of doubles (msv_c128) or floats.
+ *  - Pointers named h_* are host memory, d_* device memory.  The caller owns
+ *    every buffer it passes; the library never frees them.  The plan owns its
+ *    own device workspace and the LU factors until msv_plan_destroy.
+ *  - `stream` is a hipStream_t passed as void*; every call except
+ *    msv_plan_create and msv_plan_destroy is stream-ordered and returns before
+ *    the work finishes.  Calls on one plan must use one stream at a time.
+ *  - Every call returns an msv_status; on failure msv_last_error(plan) holds a
+ *    message (msv_last_error(NULL) for a failed msv_plan_create).  A failed
+ *    call leaves the plan usable unless it returned MSV_EHIP.
+ *  - Units: omega = k0 / sqrt(eps0 mu0), k1 = omega sqrt(eps1 mu1) with
+ *    Im k1 >= 0 (time dependence e^{-i omega t}, Section 1).
+ */
+#ifndef MSV_H
+#define MSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } msv_c128;
+
+typedef enum {
+  MSV_OK = 0,
+  MSV_EINVAL = 1,     /* invalid argument; nothing was launched */
+  MSV_ENOMEM = 2,     /* device allocation failed */
+  MSV_EHIP = 3,       /* a HIP runtime call failed; destroy the plan */
+  MSV_ESINGULAR = 4,  /* zero pivot in a per-mode LU */
+  MSV_ENOCONV = 5     /* iterative refinement did not reach the tolerance */
+} msv_status;
+
+typedef struct msv_plan msv_plan;
+
+/* Discretized generating curve gamma(t) = (r, z) (Sections 3 and 5).
+ * N = n_panels * order nodes, panel-major: node j = order*p + k lies at the k-th
+ * Gauss-Legendre point (ascending) of panel p's local coordinate u in [-1, 1].
+ * The curve runs counterclockwise in the (r, z) half-plane; an open curve
+ * starts and ends on the axis (south pole to north pole).  Per node: r > 0, z,
+ * the outward unit normal (nr, nz) = (z', -r') (' = d/ds), and ds/du > 0.
+ * Panels p and p+1 are adjacent; for closed != 0 so are n_panels-1 and 0.
+ * Adjacent panels must differ in arclength by at most a factor 2.2. */
+typedef struct {
+  int32_t n_panels;
+  int32_t order;            /* must be 16 */
+  int32_t closed;
+  const double *h_r, *h_z, *h_nr, *h_nz, *h_dsdu;  /* [N] each, host */
+} msv_curve;
+
+/* Near-panel quadrature rules (Section 5, eq_nyslike): for a target at
+ * Gauss-Legendre node k of its panel, the panel itself is integrated with the
+ * n_self nodes h_self_u[k*n_self + q] and weights h_self_w[...] (in u), and each
+ * adjacent panel with the n_adj nodes/weights h_adj_u, h_adj_w.  Host arrays. */
+typedef struct {
+  int32_t n_self;
+  const double *h_self_u, *h_self_w;   /* [order * n_self] */
+  int32_t n_adj;
+  const double *h_adj_u, *h_adj_w;     /* [n_adj] */
+} msv_rules;
+
+/* Physical and discretization parameters (Sections 1, 2.1, 4). */
+typedef struct {
+  double k0;                 /* exterior wavenumber, > 0 (omega -> 0 excluded) */
+  msv_c128 eps0, mu0;        /* exterior: real and positive */
+  msv_c128 eps1, mu1;        /* interior: Re > 0, Im >= 0 (eq. materials) */
+  int32_t m_max;             /* M: modes |m| <= M are assembled and solved */
+  int32_t fft_len;           /* L: azimuthal FFT length, a power of two; the
+                                plan refuses L too short for M and k (the
+                                discrete convolution of eq. discA needs
+                                M + 1 + N_f <= L/2 - 1) */
+  int32_t precision;         /* 0: complex128 LU; 1: complex64 LU with
+                                complex128 iterative refinement */
+  double ir_tol;             /* precision 1: stop when ||b - A x|| <= ir_tol ||b|| */
+  int32_t ir_max_iter;       /* precision 1: at most this many refinement steps */
+} msv_desc;
+
+/* Validate the inputs, upload the geometry, build the near-panel support
+ * nodes and the pair classification.  Synchronizes `stream` once. */
+msv_status msv_plan_create(msv_plan **out, const msv_curve *curve, const msv_rules *rules,
+                           const msv_desc *desc, void *stream);
+void msv_plan_destroy(msv_plan *plan);
+const char *msv_last_error(const msv_plan *plan);
+
+/* Sizes: N nodes, S support slots per target (n_self + 2 n_adj), the number
+ * of complex entries of the modal-kernel table, and the 4N x 4N matrix order. */
+int32_t msv_num_nodes(const msv_plan *plan);
+int32_t msv_num_support(const msv_plan *plan);
+size_t msv_table_entries(const msv_plan *plan);
+int32_t msv_matrix_order(const msv_plan *plan);
+
+/* Modal Green's functions (Section 4): for every target node t, every source
+ * point s (the N nodes, then the S support nodes of t) and every mode
+ * m = 0..M+1, the nine quantities
+ *   0 g^{k0}  1 d_r g^{k0}  2 d_z g^{k0}  3 g^{k1}  4 d_r g^{k1}  5 d_z g^{k1}
+ *   6 d_rr(g^{k0}-g^{k1})  7 d_rz(g^{k0}-g^{k1})  8 d_zz(g^{k0}-g^{k1})
+ * with g^k_m = int_0^{2pi} e^{ik rho}/(4 pi rho) e^{-i m phi} dphi (eq. green11)
+ * and derivatives with respect to the target coordinates.
+ * d_kern: device, [M+2][9][N][N+S] complex128, written in full (coincident
+ * pairs t = s and unused support slots are 0).  kern_elems must equal
+ * msv_table_entries(plan). */
+msv_status msv_tabulate(msv_plan *plan, msv_c128 *d_kern, size_t kern_elems, void *stream);
+
+/* Per-mode Mueller-Nystrom matrices (eq. mullerrep with Lemma 1 and the N, K
+ * expansions of Section 3; quadrature of Section 5) for 0 <= m_lo <= m <= m_hi
+ * <= M, from a table written by msv_tabulate on this plan.
+ * d_A: device, [m_hi-m_lo+1][4N][4N] complex128, row-major.  Row 4i+a is the
+ * equation at node i: a = 0,1 the t and theta components of the magnetic
+ * equation, a = 2,3 of the electric one; column 4j+b the unknown at node j:
+ * b = 0..3 for J^1, J^2, M^1, M^2 (J = n x H, M = n x E in (t, e_theta)).
+ * The stored matrix is the L^2-weighted one, sqrt(w_i/w_j) A_ij (Section 6). */
+msv_status msv_assemble(msv_plan *plan, const msv_c128 *d_kern, int32_t m_lo, int32_t m_hi,
+                        msv_c128 *d_A, void *stream);
+
+/* LU with partial pivoting of each matrix of d_A (as written by msv_assemble
+ * for the same m_lo..m_hi).  precision 0: in place in d_A; precision 1: the plan
+ * keeps complex64 factors and d_A is left intact for the refinement residual.
+ * The plan keeps the pivots (and remembers d_A, which must stay valid and
+ * unchanged until the last msv_solve).  Returns MSV_ESINGULAR after the stream
+ * completes if a zero pivot was met (checked lazily by msv_solve). */
+msv_status msv_factor(msv_plan *plan, msv_c128 *d_A, int32_t m_lo, int32_t m_hi, void *stream);
+
+/* Solve A_m x = b for modes m in [m_lo, m_hi] with -M <= m, |m| factored.
+ * Negative modes use A_{-m} = D A_m D, D = diag(1, -1, -1, 1) per node.
+ * d_rhs, d_x: device, [m_hi-m_lo+1][n_rhs][4N] complex128 in physical
+ * (unweighted) form; rows as above: i w mu0 (n x H_inc)_{t,theta} then
+ * i w eps0 (n x E_inc)_{t,theta}, Fourier modes (1/2pi) int f e^{-i m theta}.
+ * d_x may not alias d_rhs.  Synchronizes `stream` when precision is 1 (the
+ * refinement loop checks convergence on the host). */
+msv_status msv_solve(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_rhs,
+                     const msv_c128 *d_rhs, msv_c128 *d_x, void *stream);
+
+/* Iterations used by the last precision-1 msv_solve (max over modes). */
+int32_t msv_last_ir_iterations(const msv_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSV_H */

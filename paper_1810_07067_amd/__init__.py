@@ -1,0 +1,199 @@
+"""Python binding of the msv C-ABI (include/msv.h): argument marshalling only.
+
+Every step of the method runs in the HIP library libmsv.so built from csrc/
+(see build.py); PyTorch provides device memory and streams.  Importing this
+package does not load the library; the first Plan does, and fails loudly if it
+has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsv.so")
+
+MSV_OK, MSV_EINVAL, MSV_ENOMEM, MSV_EHIP, MSV_ESINGULAR, MSV_ENOCONV = range(6)
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESINGULAR", 5: "ENOCONV"}
+
+EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nodes",
+           "msv_num_support", "msv_table_entries", "msv_matrix_order", "msv_tabulate",
+           "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations"]
+
+
+class MsvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"msv {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Curve(ctypes.Structure):
+    _fields_ = [("n_panels", ctypes.c_int32), ("order", ctypes.c_int32), ("closed", ctypes.c_int32),
+                ("h_r", ctypes.c_void_p), ("h_z", ctypes.c_void_p), ("h_nr", ctypes.c_void_p),
+                ("h_nz", ctypes.c_void_p), ("h_dsdu", ctypes.c_void_p)]
+
+
+class Rules(ctypes.Structure):
+    _fields_ = [("n_self", ctypes.c_int32), ("h_self_u", ctypes.c_void_p), ("h_self_w", ctypes.c_void_p),
+                ("n_adj", ctypes.c_int32), ("h_adj_u", ctypes.c_void_p), ("h_adj_w", ctypes.c_void_p)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("k0", ctypes.c_double), ("eps0", c128), ("mu0", c128), ("eps1", c128), ("mu1", c128),
+                ("m_max", ctypes.c_int32), ("fft_len", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmsv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run `python -m paper_1810_07067_amd.build` first")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.msv_plan_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Curve), ctypes.POINTER(Rules),
+                                    ctypes.POINTER(Desc), P]
+    lib.msv_plan_create.restype = ctypes.c_int
+    lib.msv_plan_destroy.argtypes = [P]
+    lib.msv_plan_destroy.restype = None
+    lib.msv_last_error.argtypes = [P]
+    lib.msv_last_error.restype = ctypes.c_char_p
+    for f in ("msv_num_nodes", "msv_num_support", "msv_matrix_order", "msv_last_ir_iterations"):
+        getattr(lib, f).argtypes = [P]
+        getattr(lib, f).restype = ctypes.c_int32
+    lib.msv_table_entries.argtypes = [P]
+    lib.msv_table_entries.restype = ctypes.c_size_t
+    lib.msv_tabulate.argtypes = [P, P, ctypes.c_size_t, P]
+    lib.msv_tabulate.restype = ctypes.c_int
+    lib.msv_assemble.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, P]
+    lib.msv_assemble.restype = ctypes.c_int
+    lib.msv_factor.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P]
+    lib.msv_factor.restype = ctypes.c_int
+    lib.msv_solve.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    lib.msv_solve.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _c(z):
+    z = complex(z)
+    return c128(z.real, z.imag)
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A body, its discretization and physical parameters (msv_plan_create)."""
+
+    def __init__(self, r, z, nr, nz, dsdu, n_panels, closed, self_u, self_w, adj_u, adj_w,
+                 k0, eps1, mu1=1.0, eps0=1.0, mu0=1.0, m_max=16, fft_len=64, precision=0,
+                 ir_tol=1e-13, ir_max_iter=10, stream=None, lib=None):
+        self.lib = lib or load_library()
+        f64 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        self._keep = [f64(a) for a in (r, z, nr, nz, dsdu, self_u, self_w, adj_u, adj_w)]
+        a = self._keep
+        ptr = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+        curve = Curve(int(n_panels), 16, int(bool(closed)), ptr(a[0]), ptr(a[1]), ptr(a[2]), ptr(a[3]), ptr(a[4]))
+        ns = a[5].size // 16
+        rules = Rules(int(ns), ptr(a[5]), ptr(a[6]), int(a[7].size), ptr(a[7]), ptr(a[8]))
+        desc = Desc(float(k0), _c(eps0), _c(mu0), _c(eps1), _c(mu1), int(m_max), int(fft_len),
+                    int(precision), float(ir_tol), int(ir_max_iter))
+        self._h = ctypes.c_void_p()
+        st = self.lib.msv_plan_create(ctypes.byref(self._h), ctypes.byref(curve), ctypes.byref(rules),
+                                      ctypes.byref(desc), None)
+        if st != MSV_OK:
+            raise MsvError(st, self.lib.msv_last_error(None).decode())
+        self.M = int(m_max)
+        self.N = self.lib.msv_num_nodes(self._h)
+        self.S = self.lib.msv_num_support(self._h)
+        self.n = self.lib.msv_matrix_order(self._h)
+        self.precision = int(precision)
+        self._factored = None
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.msv_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != MSV_OK:
+            raise MsvError(st, self.lib.msv_last_error(self._h).decode())
+
+    @property
+    def table_entries(self) -> int:
+        return int(self.lib.msv_table_entries(self._h))
+
+    @property
+    def table_shape(self):
+        return (self.M + 2, 9, self.N, self.N + self.S)
+
+    def last_ir_iterations(self) -> int:
+        return int(self.lib.msv_last_ir_iterations(self._h))
+
+    def tabulate(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.table_shape, dtype=torch.complex128, device="cuda")
+        assert out.dtype == torch.complex128 and out.is_cuda and out.is_contiguous()
+        self._check(self.lib.msv_tabulate(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                          _stream_handle(stream)))
+        return out
+
+    def assemble(self, kern, m_lo, m_hi, out=None, stream=None):
+        import torch
+        nm = m_hi - m_lo + 1
+        if out is None:
+            out = torch.empty((nm, self.n, self.n), dtype=torch.complex128, device="cuda")
+        assert out.dtype == torch.complex128 and out.is_contiguous() and out.shape == (nm, self.n, self.n)
+        assert kern.is_contiguous() and tuple(kern.shape) == self.table_shape
+        self._check(self.lib.msv_assemble(self._h, ctypes.c_void_p(kern.data_ptr()), int(m_lo), int(m_hi),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def factor(self, A, m_lo, m_hi, stream=None):
+        assert A.is_contiguous() and A.shape == (m_hi - m_lo + 1, self.n, self.n)
+        self._check(self.lib.msv_factor(self._h, ctypes.c_void_p(A.data_ptr()), int(m_lo), int(m_hi),
+                                        _stream_handle(stream)))
+        self._factored = A  # the library keeps using this buffer
+        return A
+
+    def solve(self, m_lo, m_hi, rhs, out=None, stream=None):
+        import torch
+        nm = m_hi - m_lo + 1
+        assert rhs.dtype == torch.complex128 and rhs.is_contiguous() and rhs.shape[0] == nm
+        assert rhs.shape[2] == self.n
+        if out is None:
+            out = torch.empty_like(rhs)
+        self._check(self.lib.msv_solve(self._h, int(m_lo), int(m_hi), int(rhs.shape[1]),
+                                       ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                       _stream_handle(stream)))
+        return out
+
+
+def plan_from_curve(curve, rules, k0, eps1, mu1=1.0, m_max=16, fft_len=64, precision=0, **kw):
+    """Convenience: a Plan from a workloads.geometry.Curve and loaded rules."""
+    (ys, ws), (ya, wa) = rules
+    return Plan(curve.r, curve.z, curve.nr, curve.nz, curve.dsdu, curve.n_panels, curve.closed,
+                ys.ravel(), ws.ravel(), ya, wa, k0, eps1, mu1, m_max=m_max, fft_len=fft_len,
+                precision=precision, **kw)

@@ -1,0 +1,569 @@
+// Batched dense complex LU with partial pivoting and triangular solves on
+// gfx950, for the per-mode Mueller systems (one matrix per azimuthal mode; the
+// paper factors each mode with LAPACK, Section 6).
+//
+// Storage: row-major, matrices of order n, `nb` matrices `stride` elements
+// apart; all kernels index the matrix by blockIdx.z.
+//
+// Factorization (right-looking, recursive panels):
+//   for each outer panel of NB = 128 columns:
+//     factor the (n-k) x NB panel recursively: halves down to 8-column strips
+//       factored by one workgroup per matrix with the strip in registers,
+//       the right half updated by swaps + TRSM + GEMM
+//     apply the panel's swaps left and right of it, TRSM the row block,
+//     and update the trailing matrix with an MFMA GEMM.
+// The GEMM computes C -= A B in complex arithmetic from four real MFMA
+// products per k-step (f64 16x16x4 for complex128, f32 16x16x4 for complex64).
+#include <hip/hip_runtime.h>
+
+#include "msv_internal.h"
+
+namespace msv {
+namespace {
+
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+constexpr int kBaseW = 8;      // strip width of the base panel
+constexpr int kPanelThreads = 1024;
+constexpr int kRowsPerThread = 8;  // n <= kPanelThreads * kRowsPerThread
+
+// ---------------------------------------------------------------------------
+// base panel: rows [c0, n) x columns [c0, c0 + w), w <= 8, pivoting in column
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kPanelThreads) void base_panel(typename V2<R>::T* A, int32_t* ipiv,
+                                                            int32_t* info, int n, long long stride,
+                                                            int c0, int w) {
+  using T = typename V2<R>::T;
+  T* M = A + (size_t)blockIdx.z * stride;
+  int32_t* piv = ipiv + (size_t)blockIdx.z * n;
+  __shared__ R red_v[kPanelThreads / 64];
+  __shared__ int red_i[kPanelThreads / 64];
+  __shared__ T prow[kBaseW];
+  __shared__ T oldj[kBaseW];
+  __shared__ int s_p;
+  const int tid = threadIdx.x;
+  const int rows = n - c0;
+  // rows owned: r = c0 + tid + i * kPanelThreads
+  T v[kRowsPerThread][kBaseW];
+#pragma unroll
+  for (int i = 0; i < kRowsPerThread; ++i) {
+    int r = tid + i * kPanelThreads;
+#pragma unroll
+    for (int c = 0; c < kBaseW; ++c) {
+      T z;
+      z.x = 0;
+      z.y = 0;
+      v[i][c] = (r < rows && c < w) ? M[(size_t)(c0 + r) * n + c0 + c] : z;
+    }
+  }
+  for (int j = 0; j < w; ++j) {
+    // pivot search over local rows >= j
+    R best = -1;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+      int r = tid + i * kPanelThreads;
+      if (r >= j && r < rows) {
+        R a = fabs(v[i][j].x) + fabs(v[i][j].y);
+        if (a > best || (a == best && r < bi)) {
+          best = a;
+          bi = r;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      R ob = __shfl_xor(best, off);
+      int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      red_v[tid >> 6] = best;
+      red_i[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      R b = red_v[0];
+      int ii = red_i[0];
+      for (int q = 1; q < kPanelThreads / 64; ++q)
+        if (red_v[q] > b || (red_v[q] == b && red_i[q] < ii)) {
+          b = red_v[q];
+          ii = red_i[q];
+        }
+      if (b == (R)0 || ii >= rows) {
+        if (info[blockIdx.z] == 0) info[blockIdx.z] = c0 + j + 1;
+        ii = j;
+      }
+      s_p = ii;
+      piv[c0 + j] = c0 + ii;
+    }
+    __syncthreads();
+    const int p = s_p;
+    // swap local rows j and p through LDS: prow <- row p, oldj <- row j
+    const int oj = j % kPanelThreads, ij = j / kPanelThreads;
+    const int op = p % kPanelThreads, ip = p / kPanelThreads;
+    if (tid == op) {
+#pragma unroll
+      for (int i = 0; i < kRowsPerThread; ++i)
+        if (i == ip) {
+#pragma unroll
+          for (int c = 0; c < kBaseW; ++c) prow[c] = v[i][c];
+        }
+    }
+    if (tid == oj) {
+#pragma unroll
+      for (int i = 0; i < kRowsPerThread; ++i)
+        if (i == ij) {
+#pragma unroll
+          for (int c = 0; c < kBaseW; ++c) oldj[c] = v[i][c];
+        }
+    }
+    __syncthreads();
+    if (p != j) {
+      if (tid == op) {
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i)
+          if (i == ip) {
+#pragma unroll
+            for (int c = 0; c < kBaseW; ++c) v[i][c] = oldj[c];
+          }
+      }
+      if (tid == oj) {
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i)
+          if (i == ij) {
+#pragma unroll
+            for (int c = 0; c < kBaseW; ++c) v[i][c] = prow[c];
+          }
+      }
+    }
+    // pivot and multipliers
+    T pv = prow[j];
+    R den = pv.x * pv.x + pv.y * pv.y;
+    T inv;
+    inv.x = den != 0 ? pv.x / den : (R)0;
+    inv.y = den != 0 ? -pv.y / den : (R)0;
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+      int r = tid + i * kPanelThreads;
+      if (r > j && r < rows) {
+        T a = v[i][j];
+        T l;
+        l.x = a.x * inv.x - a.y * inv.y;
+        l.y = a.x * inv.y + a.y * inv.x;
+        v[i][j] = l;
+#pragma unroll
+        for (int c = 0; c < kBaseW; ++c)
+          if (c > j && c < w) {
+            T u = prow[c];
+            v[i][c].x -= l.x * u.x - l.y * u.y;
+            v[i][c].y -= l.x * u.y + l.y * u.x;
+          }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < kRowsPerThread; ++i) {
+    int r = tid + i * kPanelThreads;
+    if (r < rows)
+#pragma unroll
+      for (int c = 0; c < kBaseW; ++c)
+        if (c < w) M[(size_t)(c0 + r) * n + c0 + c] = v[i][c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row interchanges for pivots [k1, k2) applied to columns [cb, ce)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void laswp(T* A, const int32_t* ipiv, int n, long long stride, int k1,
+                                             int k2, int cb, int ce) {
+  T* M = A + (size_t)blockIdx.z * stride;
+  const int32_t* piv = ipiv + (size_t)blockIdx.z * n;
+  int c = cb + blockIdx.x * 256 + threadIdx.x;
+  if (c >= ce) return;
+  for (int k = k1; k < k2; ++k) {
+    int p = piv[k];
+    if (p != k) {
+      T a = M[(size_t)k * n + c];
+      M[(size_t)k * n + c] = M[(size_t)p * n + c];
+      M[(size_t)p * n + c] = a;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X <- L^{-1} X, L = unit lower A[k:k+h, k:k+h], X = A[k:k+h, cb:ce]
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void trsm_lu(typename V2<R>::T* A, int n, long long stride, int k,
+                                               int h, int cb, int ce) {
+  using T = typename V2<R>::T;
+  extern __shared__ char smem_raw[];
+  T* Ls = reinterpret_cast<T*>(smem_raw);  // [h][h]
+  T* M = A + (size_t)blockIdx.z * stride;
+  for (int e = threadIdx.x; e < h * h; e += 256) {
+    int i = e / h, j = e % h;
+    Ls[e] = M[(size_t)(k + i) * n + k + j];
+  }
+  __syncthreads();
+  int c = cb + blockIdx.x * 256 + threadIdx.x;
+  if (c >= ce) return;
+  constexpr int kMaxH = 64;
+  T x[kMaxH];
+#pragma unroll
+  for (int i = 0; i < kMaxH; ++i)
+    if (i < h) x[i] = M[(size_t)(k + i) * n + c];
+#pragma unroll
+  for (int i = 0; i < kMaxH; ++i) {
+    if (i >= h) break;
+    T s = x[i];
+#pragma unroll
+    for (int j = 0; j < kMaxH; ++j) {
+      if (j >= i) break;
+      T l = Ls[i * h + j];
+      s.x -= l.x * x[j].x - l.y * x[j].y;
+      s.y -= l.x * x[j].y + l.y * x[j].x;
+    }
+    x[i] = s;
+    M[(size_t)(k + i) * n + c] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C[r0:r0+Mr, c0:c0+Nc] -= A[r0:, k0:k0+K] * A[k0:k0+K, c0:] on MFMA
+// Workgroup: 256 threads = 4 waves (2 x 2), tile 64 x 64, K chunk 16.
+// ---------------------------------------------------------------------------
+constexpr int kGT = 64, kGK = 16;
+
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+  using C4 = __attribute__((ext_vector_type(4))) double;
+  static __device__ __forceinline__ C4 op(double a, double b, C4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using C4 = __attribute__((ext_vector_type(4))) float;
+  static __device__ __forceinline__ C4 op(float a, float b, C4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, long long stride, int r0,
+                                                   int Mr, int c0, int Nc, int k0, int K) {
+  using T = typename V2<R>::T;
+  using C4 = typename Mfma<R>::C4;
+  __shared__ R As_re[kGK][kGT + 1], As_im[kGK][kGT + 1];  // [k][row]
+  __shared__ R Bs_re[kGK][kGT + 1], Bs_im[kGK][kGT + 1];  // [k][col]
+  T* M = A + (size_t)blockIdx.z * stride;
+  const int tr = r0 + blockIdx.y * kGT;
+  const int tc = c0 + blockIdx.x * kGT;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  C4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = C4{0, 0, 0, 0};
+      cim[a][b] = C4{0, 0, 0, 0};
+    }
+  const int rend = r0 + Mr, cend = c0 + Nc, kend = k0 + K;
+  for (int kc = k0; kc < kend; kc += kGK) {
+    // load A tile [64 rows][16 k] and B tile [16 k][64 cols]
+    for (int e = tid; e < kGT * kGK; e += 256) {
+      int rr = e / kGK, kk = e % kGK;
+      int gr = tr + rr, gk = kc + kk;
+      T a;
+      a.x = 0;
+      a.y = 0;
+      if (gr < rend && gk < kend) a = M[(size_t)gr * n + gk];
+      As_re[kk][rr] = -a.x;
+      As_im[kk][rr] = a.y;
+      int kb = e / kGT, cc = e % kGT;
+      int gkb = kc + kb, gc = tc + cc;
+      T b;
+      b.x = 0;
+      b.y = 0;
+      if (gkb < kend && gc < cend) b = M[(size_t)gkb * n + gc];
+      Bs_re[kb][cc] = b.x;
+      Bs_im[kb][cc] = b.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kGK; k4 += 4) {
+      const int kk = k4 + (lane >> 4);
+      const int li = lane & 15;
+      R are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        are[a] = As_re[kk][wr + 16 * a + li];  // = -Re A
+        aim[a] = As_im[kk][wr + 16 * a + li];  // = +Im A
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bre[b] = Bs_re[kk][wc + 16 * b + li];
+        bim[b] = Bs_im[kk][wc + 16 * b + li];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          // C -= A B:  Re += (-Ar) Br + Ai Bi,  Im += (-Ar) Bi + (-Ai) Br
+          cre[a][b] = Mfma<R>::op(are[a], bre[b], cre[a][b]);
+          cre[a][b] = Mfma<R>::op(aim[a], bim[b], cre[a][b]);
+          cim[a][b] = Mfma<R>::op(are[a], bim[b], cim[a][b]);
+          cim[a][b] = Mfma<R>::op(-aim[a], bre[b], cim[a][b]);
+        }
+    }
+    __syncthreads();
+  }
+  // accumulate into C: lane holds rows 4*(lane/16)+i, column lane%16
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int gr = tr + wr + 16 * a + 4 * (lane >> 4) + i;
+        int gc = tc + wc + 16 * b + (lane & 15);
+        if (gr < rend && gc < cend) {
+          T* p = M + (size_t)gr * n + gc;
+          T v = *p;
+          v.x += cre[a][b][i];
+          v.y += cim[a][b][i];
+          *p = v;
+        }
+      }
+}
+
+template <typename R>
+hipError_t gemm(typename V2<R>::T* A, const LuBatch& b, int r0, int Mr, int c0, int Nc, int k0, int K,
+                hipStream_t s) {
+  if (Mr <= 0 || Nc <= 0 || K <= 0) return hipSuccess;
+  dim3 g((Nc + kGT - 1) / kGT, (Mr + kGT - 1) / kGT, b.nb);
+  hipLaunchKernelGGL(gemm_update<R>, g, dim3(256), 0, s, A, b.n, b.stride, r0, Mr, c0, Nc, k0, K);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t swaps(typename V2<R>::T* A, const int32_t* ipiv, const LuBatch& b, int k1, int k2, int cb,
+                 int ce, hipStream_t s) {
+  if (ce <= cb || k2 <= k1) return hipSuccess;
+  dim3 g((ce - cb + 255) / 256, 1, b.nb);
+  hipLaunchKernelGGL(laswp<typename V2<R>::T>, g, dim3(256), 0, s, A, ipiv, b.n, b.stride, k1, k2, cb, ce);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t trsm(typename V2<R>::T* A, const LuBatch& b, int k, int h, int cb, int ce, hipStream_t s) {
+  if (ce <= cb || h <= 0) return hipSuccess;
+  dim3 g((ce - cb + 255) / 256, 1, b.nb);
+  size_t lds = sizeof(typename V2<R>::T) * (size_t)h * h;
+  hipLaunchKernelGGL(trsm_lu<R>, g, dim3(256), lds, s, A, b.n, b.stride, k, h, cb, ce);
+  return hipGetLastError();
+}
+
+#define MSV_TRY(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+// Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
+template <typename R>
+hipError_t panel_rec(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& b, int c0, int w,
+                     hipStream_t s) {
+  if (w <= kBaseW) {
+    hipLaunchKernelGGL(base_panel<R>, dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
+                       b.stride, c0, w);
+    return hipGetLastError();
+  }
+  int h = w / 2;
+  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0, h, s));
+  MSV_TRY(swaps<R>(A, ipiv, b, c0, c0 + h, c0 + h, c0 + w, s));
+  MSV_TRY(trsm<R>(A, b, c0, h, c0 + h, c0 + w, s));
+  MSV_TRY(gemm<R>(A, b, c0 + h, b.n - c0 - h, c0 + h, w - h, c0, h, s));
+  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0 + h, w - h, s));
+  // swaps of the right half also apply to the left half of the panel
+  MSV_TRY(swaps<R>(A, ipiv, b, c0 + h, c0 + w, c0, c0 + h, s));
+  return hipSuccess;
+}
+
+__global__ void zero_info(int32_t* info, int nb) {
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) info[i] = 0;
+}
+
+template <typename R>
+hipError_t factor(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
+  const int n = b.n;
+  if (n > kPanelThreads * kRowsPerThread) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_info, dim3(1), dim3(256), 0, s, info, b.nb);
+  MSV_TRY(hipGetLastError());
+  const int NB = 128;
+  for (int k = 0; k < n; k += NB) {
+    int w = n - k < NB ? n - k : NB;
+    MSV_TRY(panel_rec<R>(A, ipiv, info, b, k, w, s));
+    MSV_TRY(swaps<R>(A, ipiv, b, k, k + w, 0, k, s));
+    MSV_TRY(swaps<R>(A, ipiv, b, k, k + w, k + w, n, s));
+    // U12 = L11^{-1} A12 in blocks of 64 rows (TRSM register limit), then A22
+    for (int kk = k; kk < k + w; kk += 64) {
+      int h = k + w - kk < 64 ? k + w - kk : 64;
+      MSV_TRY(trsm<R>(A, b, kk, h, k + w, n, s));
+      if (kk + h < k + w) MSV_TRY(gemm<R>(A, b, kk + h, k + w - kk - h, k + w, n - k - w, kk, h, s));
+    }
+    MSV_TRY(gemm<R>(A, b, k + w, n - k - w, k + w, n - k - w, k, w, s));
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// solves: X[nb][nrhs][n] (each right-hand side contiguous); one workgroup per
+// (matrix, group of kNQ right-hand sides) reads the factors once per group:
+// pivots, then forward (unit L) and backward (U) substitution in row blocks
+// of 64: a blocked dot product against the solved part (4 threads per row),
+// then the 64 x 64 triangle by one thread per right-hand side.
+// ---------------------------------------------------------------------------
+constexpr int kNQ = 8;
+
+template <typename R>
+__global__ __launch_bounds__(256) void trisolve(const typename V2<R>::T* LU, const int32_t* ipiv,
+                                                const int* map, typename V2<R>::T* X, int n,
+                                                long long stride, int nrhs) {
+  using T = typename V2<R>::T;
+  const int mat = map[blockIdx.y];
+  const int q0 = blockIdx.x * kNQ;
+  const int nq = nrhs - q0 < kNQ ? nrhs - q0 : kNQ;
+  const T* M = LU + (size_t)mat * stride;
+  const int32_t* piv = ipiv + (size_t)mat * n;
+  T* xb = X + ((size_t)blockIdx.y * nrhs + q0) * n;
+  const int tid = threadIdx.x;
+  if (tid < nq) {
+    T* x = xb + (size_t)tid * n;
+    for (int k = 0; k < n; ++k) {
+      int p = piv[k];
+      if (p != k) {
+        T a = x[k];
+        x[k] = x[p];
+        x[p] = a;
+      }
+    }
+  }
+  __syncthreads();
+  __shared__ T xs[kNQ][64];
+  __shared__ R pr[4][64][kNQ], pim[4][64][kNQ];
+  const int nblk = (n + 63) / 64;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fwd = pass == 0;
+    for (int bb = 0; bb < nblk; ++bb) {
+      const int bi = fwd ? bb : nblk - 1 - bb;
+      const int rb = bi * 64;
+      const int h = n - rb < 64 ? n - rb : 64;
+      const int rl = tid >> 2, part = tid & 3;
+      const int row = rb + rl;
+      R sr[kNQ], si[kNQ];
+#pragma unroll
+      for (int q = 0; q < kNQ; ++q) {
+        sr[q] = 0;
+        si[q] = 0;
+      }
+      if (row < n) {
+        const int jb = fwd ? 0 : rb + h;
+        const int je = fwd ? rb : n;
+        for (int j = jb + part; j < je; j += 4) {
+          T l = M[(size_t)row * n + j];
+#pragma unroll
+          for (int q = 0; q < kNQ; ++q)
+            if (q < nq) {
+              T v = xb[(size_t)q * n + j];
+              sr[q] += l.x * v.x - l.y * v.y;
+              si[q] += l.x * v.y + l.y * v.x;
+            }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kNQ; ++q) {
+        pr[part][rl][q] = sr[q];
+        pim[part][rl][q] = si[q];
+      }
+      __syncthreads();
+      for (int e = tid; e < kNQ * 64; e += 256) {
+        int q = e / 64, r = e % 64;
+        if (q < nq && r < h) {
+          T v = xb[(size_t)q * n + rb + r];
+          v.x -= pr[0][r][q] + pr[1][r][q] + pr[2][r][q] + pr[3][r][q];
+          v.y -= pim[0][r][q] + pim[1][r][q] + pim[2][r][q] + pim[3][r][q];
+          xs[q][r] = v;
+        }
+      }
+      __syncthreads();
+      if (tid < nq) {
+        T* xq = xs[tid];
+        if (fwd) {
+          for (int i = 0; i < h; ++i) {
+            T s = xq[i];
+            for (int j = 0; j < i; ++j) {
+              T l = M[(size_t)(rb + i) * n + rb + j];
+              s.x -= l.x * xq[j].x - l.y * xq[j].y;
+              s.y -= l.x * xq[j].y + l.y * xq[j].x;
+            }
+            xq[i] = s;
+          }
+        } else {
+          for (int i = h - 1; i >= 0; --i) {
+            T s = xq[i];
+            for (int j = i + 1; j < h; ++j) {
+              T u = M[(size_t)(rb + i) * n + rb + j];
+              s.x -= u.x * xq[j].x - u.y * xq[j].y;
+              s.y -= u.x * xq[j].y + u.y * xq[j].x;
+            }
+            T d = M[(size_t)(rb + i) * n + rb + i];
+            R den = d.x * d.x + d.y * d.y;
+            T r;
+            r.x = (s.x * d.x + s.y * d.y) / den;
+            r.y = (s.y * d.x - s.x * d.y) / den;
+            xq[i] = r;
+          }
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < kNQ * 64; e += 256) {
+        int q = e / 64, r = e % 64;
+        if (q < nq && r < h) xb[(size_t)q * n + rb + r] = xs[q][r];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
+  return factor<double>(A, ipiv, info, b, s);
+}
+hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
+  return factor<float>(A, ipiv, info, b, s);
+}
+hipError_t lu_solve_z(const double2* LU, const int32_t* ipiv, const int* map, double2* X, int nrhs,
+                      const LuBatch& b, hipStream_t s) {
+  hipLaunchKernelGGL(trisolve<double>, dim3((nrhs + kNQ - 1) / kNQ, b.nb), dim3(256), 0, s, LU, ipiv, map,
+                     X, b.n, b.stride, nrhs);
+  return hipGetLastError();
+}
+hipError_t lu_solve_c(const float2* LU, const int32_t* ipiv, const int* map, float2* X, int nrhs,
+                      const LuBatch& b, hipStream_t s) {
+  hipLaunchKernelGGL(trisolve<float>, dim3((nrhs + kNQ - 1) / kNQ, b.nb), dim3(256), 0, s, LU, ipiv, map,
+                     X, b.n, b.stride, nrhs);
+  return hipGetLastError();
+}
+
+}  // namespace msv

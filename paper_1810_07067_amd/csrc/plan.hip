@@ -1,0 +1,573 @@
+// Host side of the msv C-ABI: validation, geometry, near-panel support nodes,
+// pair classification, workspace, and the per-mode factor/solve drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "msv_internal.h"
+
+using msv::kOrder;
+using cplx = std::complex<double>;
+
+struct msv_plan {
+  int N = 0, S = 0, NS = 0, npan = 0, closed = 0, n_self = 0, n_adj = 0;
+  int M = 0, L = 0, Mq = 0, Nf = 0, fwd_n = 0;
+  double a_min = 0, fwd_lim = 3.0, miller_extra = 20.0, tau = 36.0;
+  double k0 = 0, omega = 0;
+  cplx k1, eps0, mu0, eps1, mu1;
+  int precision = 0;
+  double ir_tol = 1e-13;
+  int ir_max_iter = 10;
+  int last_ir_iters = 0;
+  std::vector<double> h_r, h_w;
+  // device
+  double *d_r = nullptr, *d_z = nullptr, *d_tr = nullptr, *d_tz = nullptr, *d_w = nullptr, *d_sqw = nullptr;
+  double *d_sup = nullptr, *d_lag_self = nullptr, *d_lag_adj = nullptr;
+  int *d_left = nullptr, *d_right = nullptr;
+  uint8_t* d_cls = nullptr;
+  int2* d_near = nullptr;
+  int n_near = 0;
+  // factors
+  int fac_lo = -1, fac_hi = -1;
+  msv_c128* fac_A = nullptr;   // caller's matrices (FP64 factors or FP64 originals)
+  float2* d_fac32 = nullptr;   // complex64 factors (precision 1)
+  size_t fac32_elems = 0;
+  int32_t* d_ipiv = nullptr;
+  int32_t* d_info = nullptr;
+  size_t ipiv_elems = 0;
+  bool info_checked = false;
+  // solve workspace
+  double2* d_bw = nullptr;  // weighted right-hand sides
+  double2* d_xw = nullptr;  // weighted solution
+  double2* d_rw = nullptr;  // residual
+  float2* d_r32 = nullptr;  // complex64 residual / correction
+  double* d_nrm = nullptr;
+  int* d_map = nullptr;
+  size_t work_elems = 0;
+  size_t map_elems = 0;
+  std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+namespace {
+
+msv_status fail(msv_plan* p, msv_status st, const std::string& msg) {
+  if (p) p->err = msg;
+  else g_create_err = msg;
+  return st;
+}
+
+// Gauss-Legendre nodes (ascending) and weights by Newton's method on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Lagrange basis values l_k(y) on nodes xn (barycentric form).
+void lagrange_row(const std::vector<double>& xn, const std::vector<double>& bw, double y, double* out) {
+  const int n = (int)xn.size();
+  for (int k = 0; k < n; ++k)
+    if (y == xn[k]) {
+      for (int j = 0; j < n; ++j) out[j] = (j == k) ? 1.0 : 0.0;
+      return;
+    }
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    out[k] = bw[k] / (y - xn[k]);
+    s += out[k];
+  }
+  for (int k = 0; k < n; ++k) out[k] /= s;
+}
+
+template <typename T>
+msv_status upload(msv_plan* p, T** dst, const T* src, size_t count) {
+  if (count == 0) return MSV_OK;
+  if (hipMalloc(dst, sizeof(T) * count) != hipSuccess) return fail(p, MSV_ENOMEM, "hipMalloc failed");
+  if (hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(p, MSV_EHIP, "hipMemcpy failed");
+  return MSV_OK;
+}
+
+#define MSV_CHECK(x)                    \
+  do {                                  \
+    msv_status st_ = (x);               \
+    if (st_ != MSV_OK) return st_;      \
+  } while (0)
+
+#define MSV_HIP(p, x)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess) return fail(p, MSV_EHIP, std::string("HIP: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Azimuthal bandwidth of the analytic factors: smallest j with
+// (x/2)^(2j) / (2j)! <= 1e-16, x = 2 max|k| r_max (bound on J_{2j}(x)).
+int bandwidth(double kmax, double rmax) {
+  double x = 2.0 * kmax * rmax;
+  for (int j = 1;; ++j) {
+    double nu = 2.0 * j;
+    double lb = nu * std::log(std::max(x, 1e-300) / 2.0) - std::lgamma(nu + 1.0);
+    if (lb <= std::log(1e-16)) return j;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* msv_last_error(const msv_plan* p) { return p ? p->err.c_str() : g_create_err.c_str(); }
+int32_t msv_num_nodes(const msv_plan* p) { return p ? p->N : 0; }
+int32_t msv_num_support(const msv_plan* p) { return p ? p->S : 0; }
+int32_t msv_matrix_order(const msv_plan* p) { return p ? 4 * p->N : 0; }
+int32_t msv_last_ir_iterations(const msv_plan* p) { return p ? p->last_ir_iters : 0; }
+size_t msv_table_entries(const msv_plan* p) {
+  return p ? (size_t)(p->M + 2) * msv::kTypes * p->N * p->NS : 0;
+}
+
+void msv_plan_destroy(msv_plan* p) {
+  if (!p) return;
+  void* bufs[] = {p->d_r, p->d_z, p->d_tr, p->d_tz, p->d_w, p->d_sqw, p->d_sup, p->d_lag_self,
+                  p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
+                  p->d_info, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_nrm, p->d_map};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* ru, const msv_desc* d,
+                           void* stream) {
+  g_create_err.clear();
+  if (!out || !c || !ru || !d) return fail(nullptr, MSV_EINVAL, "null argument");
+  *out = nullptr;
+  if (c->order != kOrder) return fail(nullptr, MSV_EINVAL, "order must be 16");
+  if (c->n_panels < 1 || (c->closed && c->n_panels < 3))
+    return fail(nullptr, MSV_EINVAL, "need >= 1 panel (>= 3 for a closed curve)");
+  if (!c->h_r || !c->h_z || !c->h_nr || !c->h_nz || !c->h_dsdu)
+    return fail(nullptr, MSV_EINVAL, "curve arrays missing");
+  if (ru->n_self < 1 || ru->n_adj < 1 || !ru->h_self_u || !ru->h_self_w || !ru->h_adj_u || !ru->h_adj_w)
+    return fail(nullptr, MSV_EINVAL, "rules missing");
+  if (!(d->k0 > 0.0)) return fail(nullptr, MSV_EINVAL, "k0 must be > 0");
+  if (!(d->eps0.re > 0 && d->eps0.im == 0 && d->mu0.re > 0 && d->mu0.im == 0))
+    return fail(nullptr, MSV_EINVAL, "eps0, mu0 must be real and positive");
+  if (!(d->eps1.re > 0 && d->eps1.im >= 0 && d->mu1.re > 0 && d->mu1.im >= 0))
+    return fail(nullptr, MSV_EINVAL, "need Re eps1, Re mu1 > 0 and Im eps1, Im mu1 >= 0");
+  if (d->m_max < 0) return fail(nullptr, MSV_EINVAL, "m_max must be >= 0");
+  if (d->fft_len < 8 || (d->fft_len & (d->fft_len - 1)))
+    return fail(nullptr, MSV_EINVAL, "fft_len must be a power of two >= 8");
+  if (d->precision != 0 && d->precision != 1) return fail(nullptr, MSV_EINVAL, "precision must be 0 or 1");
+  const int N = c->n_panels * kOrder;
+  if (4 * N > 8192) return fail(nullptr, MSV_EINVAL, "4N > 8192 exceeds the LU panel kernel");
+  for (int i = 0; i < N; ++i) {
+    if (!(c->h_r[i] > 0.0)) return fail(nullptr, MSV_EINVAL, "r must be > 0 at every node");
+    if (!(c->h_dsdu[i] > 0.0)) return fail(nullptr, MSV_EINVAL, "ds/du must be > 0");
+    double nn = std::hypot(c->h_nr[i], c->h_nz[i]);
+    if (std::fabs(nn - 1.0) > 1e-12) return fail(nullptr, MSV_EINVAL, "normals must have unit length");
+  }
+
+  msv_plan* p = new msv_plan();
+  p->N = N;
+  p->npan = c->n_panels;
+  p->closed = c->closed ? 1 : 0;
+  p->n_self = ru->n_self;
+  p->n_adj = ru->n_adj;
+  p->S = ru->n_self + 2 * ru->n_adj;
+  p->NS = N + p->S;
+  p->M = d->m_max;
+  p->L = d->fft_len;
+  p->Mq = p->L / 2 - 1;
+  p->k0 = d->k0;
+  p->eps0 = cplx(d->eps0.re, d->eps0.im);
+  p->mu0 = cplx(d->mu0.re, d->mu0.im);
+  p->eps1 = cplx(d->eps1.re, d->eps1.im);
+  p->mu1 = cplx(d->mu1.re, d->mu1.im);
+  p->omega = d->k0 / std::sqrt(d->eps0.re * d->mu0.re);
+  p->k1 = p->omega * std::sqrt(p->eps1 * p->mu1);
+  if (p->k1.imag() < 0) p->k1 = -p->k1;
+  p->precision = d->precision;
+  p->ir_tol = d->ir_tol > 0 ? d->ir_tol : 1e-13;
+  p->ir_max_iter = d->ir_max_iter > 0 ? d->ir_max_iter : 10;
+
+  // geometry: arclength weights, tangents, panel lengths, neighbours
+  std::vector<double> ug, wg;
+  gauss_legendre(kOrder, ug, wg);
+  std::vector<double> bw(kOrder, 1.0);
+  for (int j = 0; j < kOrder; ++j)
+    for (int k = 0; k < kOrder; ++k)
+      if (k != j) bw[j] /= (ug[j] - ug[k]);
+  std::vector<double> w(N), sqw(N), tr(N), tz(N), plen(p->npan, 0.0);
+  double rmax = 0.0;
+  for (int i = 0; i < N; ++i) {
+    w[i] = wg[i % kOrder] * c->h_dsdu[i];
+    sqw[i] = std::sqrt(w[i]);
+    tr[i] = -c->h_nz[i];
+    tz[i] = c->h_nr[i];
+    plen[i / kOrder] += w[i];
+    rmax = std::max(rmax, c->h_r[i]);
+  }
+  std::vector<int> left(p->npan), right(p->npan);
+  for (int q = 0; q < p->npan; ++q) {
+    left[q] = q - 1;
+    right[q] = q + 1;
+  }
+  if (p->closed) {
+    left[0] = p->npan - 1;
+    right[p->npan - 1] = 0;
+  } else {
+    left[0] = -1;
+    right[p->npan - 1] = -1;
+  }
+  for (int q = 0; q < p->npan; ++q)
+    for (int nb : {left[q], right[q]})
+      if (nb >= 0) {
+        double ratio = plen[nb] / plen[q];
+        if (ratio > 2.2 || ratio < 1.0 / 2.2) {
+          msv_plan_destroy(p);
+          return fail(nullptr, MSV_EINVAL, "adjacent panels differ in length by more than 2.2x");
+        }
+      }
+  // kernel parameters (classification and recurrences)
+  p->Nf = bandwidth(std::max(p->k0, std::abs(p->k1)), rmax);
+  const int m_hi = p->M + 1;
+  if (m_hi + p->Nf > p->Mq) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "fft_len %d too short: need M+1+N_f = %d <= L/2-1 = %d", p->L, m_hi + p->Nf, p->Mq);
+    msv_plan_destroy(p);
+    return fail(nullptr, MSV_EINVAL, buf);
+  }
+  p->a_min = p->tau / (double)(p->L - m_hi - p->Nf);
+  p->fwd_n = m_hi + p->Nf;
+
+  // support slots: offsets from the target (interpolated nodal differences),
+  // source geometry and weights
+  const int S = p->S, NSf = msv::kSupFields;
+  std::vector<double> sup((size_t)N * S * NSf, 0.0);
+  std::vector<double> lag_self((size_t)kOrder * p->n_self * kOrder), lag_adj((size_t)p->n_adj * kOrder);
+  for (int k = 0; k < kOrder; ++k)
+    for (int q = 0; q < p->n_self; ++q)
+      lagrange_row(ug, bw, ru->h_self_u[k * p->n_self + q], &lag_self[((size_t)k * p->n_self + q) * kOrder]);
+  for (int q = 0; q < p->n_adj; ++q) lagrange_row(ug, bw, ru->h_adj_u[q], &lag_adj[(size_t)q * kOrder]);
+  auto fill = [&](int t, int slot0, int pan, int nq, const double* lagrows, const double* wts) {
+    const double* rp = c->h_r + pan * kOrder;
+    const double* zp = c->h_z + pan * kOrder;
+    for (int q = 0; q < nq; ++q) {
+      const double* l = lagrows + (size_t)q * kOrder;
+      double r = 0, dr = 0, dz = 0, drdu = 0, dzdu = 0;
+      for (int k = 0; k < kOrder; ++k) {
+        int j = pan * kOrder + k;
+        r += l[k] * rp[k];
+        dr += l[k] * (rp[k] - c->h_r[t]);
+        dz += l[k] * (zp[k] - c->h_z[t]);
+        drdu += l[k] * (-c->h_nz[j] * c->h_dsdu[j]);
+        dzdu += l[k] * (c->h_nr[j] * c->h_dsdu[j]);
+      }
+      double sp = std::hypot(drdu, dzdu);
+      double* o = &sup[((size_t)t * S + slot0 + q) * NSf];
+      o[msv::kSupDr] = dr;
+      o[msv::kSupDz] = dz;
+      o[msv::kSupR] = r;
+      o[msv::kSupTr] = drdu / sp;
+      o[msv::kSupTz] = dzdu / sp;
+      o[msv::kSupW] = wts[q] * sp;
+    }
+  };
+  for (int t = 0; t < N; ++t) {
+    int pan = t / kOrder, k = t % kOrder;
+    fill(t, 0, pan, p->n_self, &lag_self[(size_t)k * p->n_self * kOrder], ru->h_self_w + k * p->n_self);
+    if (left[pan] >= 0) fill(t, p->n_self, left[pan], p->n_adj, lag_adj.data(), ru->h_adj_w);
+    if (right[pan] >= 0) fill(t, p->n_self + p->n_adj, right[pan], p->n_adj, lag_adj.data(), ru->h_adj_w);
+  }
+  // pair classes: near iff acosh(chi) < a_min (split + convolution), else the
+  // plain L-point trapezoid; coincident pairs and unused slots are zero
+  std::vector<uint8_t> cls((size_t)N * p->NS);
+  std::vector<int2> nearv;
+  for (int t = 0; t < N; ++t) {
+    const double rt = c->h_r[t];
+    for (int col = 0; col < p->NS; ++col) {
+      double dr, dz;
+      uint8_t cl;
+      if (col < N) {
+        dr = c->h_r[col] - rt;
+        dz = c->h_z[col] - c->h_z[t];
+        if (col == t) {
+          cls[(size_t)t * p->NS + col] = msv::kZero;
+          continue;
+        }
+      } else {
+        const double* o = &sup[((size_t)t * S + (col - N)) * NSf];
+        if (o[msv::kSupW] == 0.0) {
+          cls[(size_t)t * p->NS + col] = msv::kZero;
+          continue;
+        }
+        dr = o[msv::kSupDr];
+        dz = o[msv::kSupDz];
+      }
+      double rs = rt + dr;
+      double eta = (dr * dr + dz * dz) / (2.0 * rt * rs);
+      double ach = std::log1p(eta + std::sqrt(eta * (2.0 + eta)));
+      cl = ach < p->a_min ? msv::kNear : msv::kFar;
+      if (eta == 0.0) cl = msv::kZero;
+      cls[(size_t)t * p->NS + col] = cl;
+      if (cl == msv::kNear) nearv.push_back(make_int2(t, col));
+    }
+  }
+  p->n_near = (int)nearv.size();
+  p->h_r.assign(c->h_r, c->h_r + N);
+  p->h_w = w;
+
+  msv_status st;
+#define UP(dst, vec) \
+  if ((st = upload(p, &dst, vec.data(), vec.size())) != MSV_OK) { msv_plan_destroy(p); return st; }
+  std::vector<double> vr(c->h_r, c->h_r + N), vz(c->h_z, c->h_z + N);
+  UP(p->d_r, vr);
+  UP(p->d_z, vz);
+  UP(p->d_tr, tr);
+  UP(p->d_tz, tz);
+  UP(p->d_w, w);
+  UP(p->d_sqw, sqw);
+  UP(p->d_sup, sup);
+  UP(p->d_lag_self, lag_self);
+  UP(p->d_lag_adj, lag_adj);
+  UP(p->d_left, left);
+  UP(p->d_right, right);
+  UP(p->d_cls, cls);
+  UP(p->d_near, nearv);
+#undef UP
+  (void)stream;
+  *out = p;
+  return MSV_OK;
+}
+
+msv_status msv_tabulate(msv_plan* p, msv_c128* d_kern, size_t kern_elems, void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  if (!d_kern) return fail(p, MSV_EINVAL, "null table");
+  if (kern_elems != msv_table_entries(p)) return fail(p, MSV_EINVAL, "table size mismatch");
+  msv::TabParams T{};
+  T.N = p->N;
+  T.S = p->S;
+  T.NS = p->NS;
+  T.M2 = p->M + 2;
+  T.L = p->L;
+  T.Mq = p->Mq;
+  T.fwd_n = p->fwd_n;
+  T.fwd_lim = p->fwd_lim;
+  T.miller_extra = p->miller_extra;
+  T.k0 = p->k0;
+  T.k1r = p->k1.real();
+  T.k1i = p->k1.imag();
+  T.r = p->d_r;
+  T.z = p->d_z;
+  T.sup = p->d_sup;
+  T.cls = p->d_cls;
+  T.near = p->d_near;
+  T.n_near = p->n_near;
+  T.out = reinterpret_cast<double2*>(d_kern);
+  MSV_HIP(p, msv::launch_tabulate(T, (hipStream_t)stream));
+  return MSV_OK;
+}
+
+msv_status msv_assemble(msv_plan* p, const msv_c128* d_kern, int32_t m_lo, int32_t m_hi, msv_c128* d_A,
+                        void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  if (!d_kern || !d_A) return fail(p, MSV_EINVAL, "null buffer");
+  if (m_lo < 0 || m_hi < m_lo || m_hi > p->M) return fail(p, MSV_EINVAL, "need 0 <= m_lo <= m_hi <= M");
+  msv::AsmParams A{};
+  A.N = p->N;
+  A.S = p->S;
+  A.NS = p->NS;
+  A.M2 = p->M + 2;
+  A.npan = p->npan;
+  A.n_self = p->n_self;
+  A.n_adj = p->n_adj;
+  A.m_lo = m_lo;
+  A.m_hi = m_hi;
+  A.k0 = p->k0;
+  A.k1r = p->k1.real();
+  A.k1i = p->k1.imag();
+  A.omega = p->omega;
+  A.eps0r = p->eps0.real();
+  A.eps0i = p->eps0.imag();
+  A.mu0r = p->mu0.real();
+  A.mu0i = p->mu0.imag();
+  A.eps1r = p->eps1.real();
+  A.eps1i = p->eps1.imag();
+  A.mu1r = p->mu1.real();
+  A.mu1i = p->mu1.imag();
+  A.r = p->d_r;
+  A.tr = p->d_tr;
+  A.tz = p->d_tz;
+  A.w = p->d_w;
+  A.sqw = p->d_sqw;
+  A.sup = p->d_sup;
+  A.left = p->d_left;
+  A.right = p->d_right;
+  A.lag_self = p->d_lag_self;
+  A.lag_adj = p->d_lag_adj;
+  A.kern = reinterpret_cast<const double2*>(d_kern);
+  A.A = reinterpret_cast<double2*>(d_A);
+  MSV_HIP(p, msv::launch_assemble(A, (hipStream_t)stream));
+  return MSV_OK;
+}
+
+msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  if (!d_A) return fail(p, MSV_EINVAL, "null matrix buffer");
+  if (m_lo < 0 || m_hi < m_lo || m_hi > p->M) return fail(p, MSV_EINVAL, "need 0 <= m_lo <= m_hi <= M");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = 4 * p->N, nb = m_hi - m_lo + 1;
+  const size_t nn = (size_t)n * n;
+  if ((size_t)nb * n > p->ipiv_elems) {
+    if (p->d_ipiv) (void)hipFree(p->d_ipiv);
+    if (p->d_info) (void)hipFree(p->d_info);
+    p->d_ipiv = nullptr;
+    p->d_info = nullptr;
+    p->ipiv_elems = 0;
+    if (hipMalloc(&p->d_ipiv, sizeof(int32_t) * (size_t)nb * n) != hipSuccess ||
+        hipMalloc(&p->d_info, sizeof(int32_t) * nb) != hipSuccess)
+      return fail(p, MSV_ENOMEM, "pivot allocation failed");
+    p->ipiv_elems = (size_t)nb * n;
+  }
+  msv::LuBatch b{n, nb, n, (long long)nn};
+  if (p->precision == 0) {
+    MSV_HIP(p, msv::lu_factor_z(reinterpret_cast<double2*>(d_A), p->d_ipiv, p->d_info, b, s));
+  } else {
+    if ((size_t)nb * nn > p->fac32_elems) {
+      if (p->d_fac32) (void)hipFree(p->d_fac32);
+      p->d_fac32 = nullptr;
+      p->fac32_elems = 0;
+      if (hipMalloc(&p->d_fac32, sizeof(float2) * (size_t)nb * nn) != hipSuccess)
+        return fail(p, MSV_ENOMEM, "complex64 factor allocation failed");
+      p->fac32_elems = (size_t)nb * nn;
+    }
+    MSV_HIP(p, msv::conv_c64(reinterpret_cast<const double2*>(d_A), p->d_fac32, (size_t)nb * nn, s));
+    MSV_HIP(p, msv::lu_factor_c(p->d_fac32, p->d_ipiv, p->d_info, b, s));
+  }
+  p->fac_lo = m_lo;
+  p->fac_hi = m_hi;
+  p->fac_A = d_A;
+  p->info_checked = false;
+  return MSV_OK;
+}
+
+msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, const msv_c128* d_rhs,
+                     msv_c128* d_x, void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  if (!d_rhs || !d_x || d_rhs == d_x) return fail(p, MSV_EINVAL, "need distinct rhs and x buffers");
+  if (n_rhs < 1 || m_hi < m_lo) return fail(p, MSV_EINVAL, "empty solve");
+  if (p->fac_lo < 0) return fail(p, MSV_EINVAL, "no factors: call msv_factor first");
+  for (int m = m_lo; m <= m_hi; ++m) {
+    int a = m < 0 ? -m : m;
+    if (a < p->fac_lo || a > p->fac_hi) return fail(p, MSV_EINVAL, "mode outside the factored range");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int n = 4 * p->N, nm = m_hi - m_lo + 1;
+  const int nfac = p->fac_hi - p->fac_lo + 1;
+  if (!p->info_checked) {
+    std::vector<int32_t> info(nfac);
+    MSV_HIP(p, hipMemcpyAsync(info.data(), p->d_info, sizeof(int32_t) * nfac, hipMemcpyDeviceToHost, s));
+    MSV_HIP(p, hipStreamSynchronize(s));
+    for (int i = 0; i < nfac; ++i)
+      if (info[i] != 0) {
+        char buf[120];
+        snprintf(buf, sizeof buf, "zero pivot in mode %d at column %d", p->fac_lo + i, info[i] - 1);
+        return fail(p, MSV_ESINGULAR, buf);
+      }
+    p->info_checked = true;
+  }
+  const size_t elems = (size_t)nm * n_rhs * n;
+  if (elems > p->work_elems) {
+    void* bufs[] = {p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_nrm};
+    for (void* bf : bufs)
+      if (bf) (void)hipFree(bf);
+    p->d_bw = p->d_xw = p->d_rw = nullptr;
+    p->d_r32 = nullptr;
+    p->d_nrm = nullptr;
+    p->work_elems = 0;
+    if (hipMalloc(&p->d_bw, sizeof(double2) * elems) != hipSuccess ||
+        hipMalloc(&p->d_xw, sizeof(double2) * elems) != hipSuccess ||
+        hipMalloc(&p->d_rw, sizeof(double2) * elems) != hipSuccess ||
+        hipMalloc(&p->d_r32, sizeof(float2) * elems) != hipSuccess ||
+        hipMalloc(&p->d_nrm, sizeof(double) * (size_t)nm * n_rhs) != hipSuccess)
+      return fail(p, MSV_ENOMEM, "solve workspace allocation failed");
+    p->work_elems = elems;
+  }
+  if ((size_t)nm > p->map_elems) {
+    if (p->d_map) (void)hipFree(p->d_map);
+    p->d_map = nullptr;
+    if (hipMalloc(&p->d_map, sizeof(int) * nm) != hipSuccess) return fail(p, MSV_ENOMEM, "map allocation failed");
+    p->map_elems = nm;
+  }
+  std::vector<int> map(nm);
+  for (int i = 0; i < nm; ++i) map[i] = std::abs(m_lo + i) - p->fac_lo;
+  MSV_HIP(p, hipMemcpy(p->d_map, map.data(), sizeof(int) * nm, hipMemcpyHostToDevice));
+  msv::LuBatch b{n, nm, n, (long long)n * n};
+  const double2* rhs = reinterpret_cast<const double2*>(d_rhs);
+  double2* x = reinterpret_cast<double2*>(d_x);
+  MSV_HIP(p, msv::solve_prep(rhs, p->d_bw, p->d_sqw, n, n_rhs, nm, m_lo, s));
+  if (p->precision == 0) {
+    MSV_HIP(p, hipMemcpyAsync(p->d_xw, p->d_bw, sizeof(double2) * elems, hipMemcpyDeviceToDevice, s));
+    MSV_HIP(p, msv::lu_solve_z(reinterpret_cast<const double2*>(p->fac_A), p->d_ipiv, p->d_map, p->d_xw, n_rhs,
+                               b, s));
+    p->last_ir_iters = 0;
+  } else {
+    const double2* Aref = reinterpret_cast<const double2*>(p->fac_A);
+    MSV_HIP(p, msv::zero_c128(p->d_xw, elems, s));
+    MSV_HIP(p, hipMemcpyAsync(p->d_rw, p->d_bw, sizeof(double2) * elems, hipMemcpyDeviceToDevice, s));
+    std::vector<double> rat((size_t)nm * n_rhs);
+    bool conv = false;
+    int it = 0;
+    for (it = 1; it <= p->ir_max_iter; ++it) {
+      MSV_HIP(p, msv::conv_c64(p->d_rw, p->d_r32, elems, s));
+      MSV_HIP(p, msv::lu_solve_c(p->d_fac32, p->d_ipiv, p->d_map, p->d_r32, n_rhs, b, s));
+      MSV_HIP(p, msv::accum_c64(p->d_xw, p->d_r32, elems, s));
+      MSV_HIP(p, msv::residual_z(Aref, p->d_map, p->d_bw, p->d_xw, p->d_rw, n, n_rhs, nm, s));
+      MSV_HIP(p, msv::ratios(p->d_rw, p->d_bw, p->d_nrm, n, nm * n_rhs, s));
+      MSV_HIP(p, hipMemcpyAsync(rat.data(), p->d_nrm, sizeof(double) * rat.size(), hipMemcpyDeviceToHost, s));
+      MSV_HIP(p, hipStreamSynchronize(s));
+      double mx = 0.0;
+      for (double v : rat) mx = std::max(mx, v);
+      if (mx <= p->ir_tol) {
+        conv = true;
+        break;
+      }
+    }
+    p->last_ir_iters = conv ? it : p->ir_max_iter;
+    MSV_HIP(p, msv::solve_finish(p->d_xw, x, p->d_sqw, n, n_rhs, nm, m_lo, s));
+    if (!conv) return fail(p, MSV_ENOCONV, "iterative refinement did not reach ir_tol");
+    return MSV_OK;
+  }
+  MSV_HIP(p, msv::solve_finish(p->d_xw, x, p->d_sqw, n, n_rhs, nm, m_lo, s));
+  return MSV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// Per-mode factorization and solve drivers (Section 6: LU per mode, further
+// right-hand sides reuse the factors), with the complex64-LU + complex128
+// iterative-refinement variant: x <- x + LU32^{-1} (b - A x), the residual in
+// complex128 with the complex128 matrix, until ||b - A x|| <= tol ||b||.
+//
+// Right-hand sides arrive unweighted; the stored matrices are the L^2-weighted
+// ones (A~ = W^{1/2} A W^{-1/2}), so b~ = W^{1/2} b and x = W^{-1/2} x~.
+// Negative modes reuse the factors of |m| through A_{-m} = D A_m D,
+// D = diag(1, -1, -1, 1) per node.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "msv_internal.h"
+
+struct msv_plan;  // defined in plan.hip; accessed through the helpers below
+
+namespace msv {
+namespace {
+
+__device__ __forceinline__ double parity(int m, int row) {
+  if (m >= 0) return 1.0;
+  int c = row & 3;
+  return (c == 1 || c == 2) ? -1.0 : 1.0;
+}
+
+// xw[i][q][row] = D(m_i) sqrt(w[row/4]) rhs[i][q][row]
+__global__ void prep_rhs(const double2* rhs, double2* xw, const double* sqw, int n, int nrhs, int m_lo) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t tot = (size_t)gridDim.y * nrhs * n;
+  (void)tot;
+  int i = blockIdx.y;
+  if (e >= (size_t)nrhs * n) return;
+  int row = (int)(e % n);
+  double s = parity(m_lo + i, row) * sqw[row >> 2];
+  double2 v = rhs[(size_t)i * nrhs * n + e];
+  xw[(size_t)i * nrhs * n + e] = make_double2(s * v.x, s * v.y);
+}
+
+// x[i][q][row] = D(m_i) xw[i][q][row] / sqrt(w[row/4])
+__global__ void finish_x(const double2* xw, double2* x, const double* sqw, int n, int nrhs, int m_lo) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (e >= (size_t)nrhs * n) return;
+  int row = (int)(e % n);
+  double s = parity(m_lo + i, row) / sqw[row >> 2];
+  double2 v = xw[(size_t)i * nrhs * n + e];
+  x[(size_t)i * nrhs * n + e] = make_double2(s * v.x, s * v.y);
+}
+
+__global__ void to_c64(const double2* a, float2* b, size_t count) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) {
+    double2 v = a[e];
+    b[e] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+__global__ void add_c64(double2* x, const float2* d, size_t count) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) {
+    double2 v = x[e];
+    float2 u = d[e];
+    x[e] = make_double2(v.x + (double)u.x, v.y + (double)u.y);
+  }
+}
+
+__global__ void fill_zero(double2* x, size_t count) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) x[e] = make_double2(0.0, 0.0);
+}
+
+// r[i][q] = b[i][q] - A[map[i]] x[i][q], one wave per row, up to 8 rhs per block
+constexpr int kRQ = 8;
+__global__ __launch_bounds__(256) void residual(const double2* A, const int* map, const double2* b,
+                                                const double2* x, double2* r, int n, int nrhs) {
+  const int i = blockIdx.y;
+  const int q0 = blockIdx.z * kRQ;
+  const int nq = min(kRQ, nrhs - q0);
+  const double2* M = A + (size_t)map[i] * n * n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wave;
+  if (row >= n) return;
+  double ar[kRQ], ai[kRQ];
+#pragma unroll
+  for (int q = 0; q < kRQ; ++q) {
+    ar[q] = 0;
+    ai[q] = 0;
+  }
+  const double2* Ar = M + (size_t)row * n;
+  for (int j = lane; j < n; j += 64) {
+    double2 a = Ar[j];
+#pragma unroll
+    for (int q = 0; q < kRQ; ++q)
+      if (q < nq) {
+        double2 v = x[((size_t)i * nrhs + q0 + q) * n + j];
+        ar[q] += a.x * v.x - a.y * v.y;
+        ai[q] += a.x * v.y + a.y * v.x;
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < kRQ; ++q) {
+    for (int off = 32; off > 0; off >>= 1) {
+      ar[q] += __shfl_xor(ar[q], off);
+      ai[q] += __shfl_xor(ai[q], off);
+    }
+  }
+  if (lane < nq) {
+    int q = lane;
+    double sr = 0, si = 0;
+#pragma unroll
+    for (int k = 0; k < kRQ; ++k)
+      if (k == q) {
+        sr = ar[k];
+        si = ai[k];
+      }
+    size_t o = ((size_t)i * nrhs + q0 + q) * n + row;
+    double2 bb = b[o];
+    r[o] = make_double2(bb.x - sr, bb.y - si);
+  }
+}
+
+// ratio[i*nrhs+q] = max|r| / max|b| over the vector
+__global__ __launch_bounds__(256) void ratio_inf(const double2* r, const double2* b, double* out, int n) {
+  const size_t v = blockIdx.x;
+  __shared__ double sr[256], sb[256];
+  double mr = 0, mb = 0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    double2 a = r[v * n + j], c = b[v * n + j];
+    mr = fmax(mr, fabs(a.x) + fabs(a.y));
+    mb = fmax(mb, fabs(c.x) + fabs(c.y));
+  }
+  sr[threadIdx.x] = mr;
+  sb[threadIdx.x] = mb;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + s]);
+      sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sb[0] > 0 ? sr[0] / sb[0] : 0.0;
+}
+
+inline dim3 grid1(size_t count) { return dim3((unsigned)((count + 255) / 256)); }
+
+}  // namespace
+
+hipError_t solve_prep(const double2* rhs, double2* xw, const double* sqw, int n, int nrhs, int nm, int m_lo,
+                      hipStream_t s) {
+  dim3 g((unsigned)(((size_t)nrhs * n + 255) / 256), nm);
+  hipLaunchKernelGGL(prep_rhs, g, dim3(256), 0, s, rhs, xw, sqw, n, nrhs, m_lo);
+  return hipGetLastError();
+}
+hipError_t solve_finish(const double2* xw, double2* x, const double* sqw, int n, int nrhs, int nm, int m_lo,
+                        hipStream_t s) {
+  dim3 g((unsigned)(((size_t)nrhs * n + 255) / 256), nm);
+  hipLaunchKernelGGL(finish_x, g, dim3(256), 0, s, xw, x, sqw, n, nrhs, m_lo);
+  return hipGetLastError();
+}
+hipError_t conv_c64(const double2* a, float2* b, size_t count, hipStream_t s) {
+  hipLaunchKernelGGL(to_c64, grid1(count), dim3(256), 0, s, a, b, count);
+  return hipGetLastError();
+}
+hipError_t accum_c64(double2* x, const float2* d, size_t count, hipStream_t s) {
+  hipLaunchKernelGGL(add_c64, grid1(count), dim3(256), 0, s, x, d, count);
+  return hipGetLastError();
+}
+hipError_t zero_c128(double2* x, size_t count, hipStream_t s) {
+  hipLaunchKernelGGL(fill_zero, grid1(count), dim3(256), 0, s, x, count);
+  return hipGetLastError();
+}
+hipError_t residual_z(const double2* A, const int* map, const double2* b, const double2* x, double2* r, int n,
+                      int nrhs, int nm, hipStream_t s) {
+  dim3 g((n + 3) / 4, nm, (nrhs + kRQ - 1) / kRQ);
+  hipLaunchKernelGGL(residual, g, dim3(256), 0, s, A, map, b, x, r, n, nrhs);
+  return hipGetLastError();
+}
+hipError_t ratios(const double2* r, const double2* b, double* out, int n, int nvec, hipStream_t s) {
+  hipLaunchKernelGGL(ratio_inf, dim3(nvec), dim3(256), 0, s, r, b, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace msv

@@ -1,0 +1,77 @@
+"""CPU checks of the HIP library boundary: it loads, exports every entry point
+of include/msv.h, and rejects invalid input before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1810_07067_amd as msv
+from workloads import geometry, rules
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(msv.LIB_PATH):
+        from paper_1810_07067_amd import build
+        build.build()
+    return msv.load_library()
+
+
+def test_exports_match_header(lib):
+    header = open(os.path.join(ROOT, "include", "msv.h")).read()
+    declared = set(re.findall(r"\b(msv_[a-z_0-9]+)\s*\(", header))
+    assert declared == set(msv.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _args(curve, **over):
+    (ys, ws), (ya, wa) = rules.load_rules()
+    kw = dict(r=curve.r, z=curve.z, nr=curve.nr, nz=curve.nz, dsdu=curve.dsdu, n_panels=curve.n_panels,
+              closed=curve.closed, self_u=ys.ravel(), self_w=ws.ravel(), adj_u=ya, adj_w=wa, k0=1.0,
+              eps1=2.25, m_max=16, fft_len=64)
+    kw.update(over)
+    return kw
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(k0=0.0), "k0"),
+    (dict(eps1=-1.0), "eps1"),
+    (dict(eps1=2.0 - 0.1j), "eps1"),
+    (dict(fft_len=48), "power of two"),
+    (dict(fft_len=32), "too short"),
+    (dict(m_max=-1), "m_max"),
+])
+def test_invalid_inputs_rejected(lib, over, needle):
+    curve = geometry.sphere(8)
+    with pytest.raises(msv.MsvError) as ei:
+        msv.Plan(**_args(curve, **over), lib=lib)
+    assert ei.value.status == msv.MSV_EINVAL
+    assert needle in str(ei.value)
+
+
+def test_nonpositive_radius_rejected(lib):
+    curve = geometry.sphere(8)
+    r = curve.r.copy()
+    r[3] = 0.0
+    with pytest.raises(msv.MsvError) as ei:
+        msv.Plan(**_args(curve, r=r), lib=lib)
+    assert "r must be > 0" in str(ei.value)
+
+
+def test_bad_normals_and_panel_ratio_rejected(lib):
+    curve = geometry.sphere(8)
+    nr = curve.nr.copy()
+    nr[0] *= 1.01
+    with pytest.raises(msv.MsvError):
+        msv.Plan(**_args(curve, nr=nr), lib=lib)
+    c2 = geometry.polygon([(0.0, -1.0), (1.0, -1.0), (1.0, 1.0), (0.0, 1.0)], 8.0, 0, "p")
+    d = c2.dsdu.copy()
+    d[16:32] *= 3.0  # panel 1 three times longer than its neighbours
+    with pytest.raises(msv.MsvError) as ei:
+        msv.Plan(**_args(c2, dsdu=d), lib=lib)
+    assert "adjacent panels" in str(ei.value)
