@@ -128,11 +128,14 @@ def analytic_factors(x):
     return c, sinc, W, Y3, Wt, Ut, V5
 
 
-def sample_types(rt, dr, dz, cosphi, rho2, X1, X3, k0, k1):
+def sample_types(rt, dr, dz, cosphi, rho2, X1, X3, k0, k1, exact=False):
     """The nine integrands (times 4 pi) at azimuth samples.
 
     rt, dr = r_s - r_t, dz = z_s - z_t: [P, 1]; cosphi, rho2: [P, J] or [1, J];
-    X1, X3: [P, J] samples of 1/rho and 1/rho^3 (exact or band-limited).
+    X1, X3: [P, J] samples of 1/rho and 1/rho^3, band-limited for near pairs.
+    exact: X1, X3 are exactly 1/rho, 1/rho^3 (well separated pairs); then
+    r_d/rho^3 and r_d^2/rho^3 are formed from r_d directly, because the identity
+    r_d = (rho^2 + a)/(2 r_t) cancels badly when r_t is small and rho is not.
     Returns [9, P, J] complex.
     """
     rs = rt + dr
@@ -140,6 +143,12 @@ def sample_types(rt, dr, dz, cosphi, rho2, X1, X3, k0, k1):
     a = -dr * (2.0 * rt + dr) - dz * dz
     rd = rt - rs * cosphi
     rho = np.sqrt(rho2)
+    if exact:
+        Xa = rd * X3
+        Xaa = rd * rd * X3
+    else:
+        Xa = (X1 + a * X3) / (2.0 * rt)
+        Xaa = (rho2 * X1 + 2.0 * a * X1 + a * a * X3) / (4.0 * rt * rt)
     out = []
     fac = {}
     for key, k in (("0", k0), ("1", k1)):
@@ -147,7 +156,7 @@ def sample_types(rt, dr, dz, cosphi, rho2, X1, X3, k0, k1):
         fac[key] = (c, sinc, W, Y3, Wt, Ut, V5, k)
         g = c * X1 + 1j * k * sinc
         dz = zd * (-W * X3 + 1j * k ** 3 * Y3)
-        dr = -W * (X1 + a * X3) / (2.0 * rt) + 1j * k ** 3 * Y3 * rd
+        dr = -W * Xa + 1j * k ** 3 * Y3 * rd
         out += [g, dr, dz]
     c0, _, _, Y30, Wt0, Ut0, V50, k0_ = fac["0"]
     c1, _, _, Y31, Wt1, Ut1, V51, k1_ = fac["1"]
@@ -155,9 +164,8 @@ def sample_types(rt, dr, dz, cosphi, rho2, X1, X3, k0, k1):
     Wd = k0_ ** 2 * Wt0 - k1_ ** 2 * Wt1
     V5d = k0_ ** 5 * V50 - k1_ ** 5 * V51
     Y3d = k0_ ** 3 * Y30 - k1_ ** 3 * Y31
-    rr = Pd * (rho2 * X1 + 2.0 * a * X1 + a * a * X3) / (4.0 * rt * rt) - Wd * X1 \
-        + 1j * (V5d * rd * rd + Y3d)
-    rz = Pd * zd * (X1 + a * X3) / (2.0 * rt) + 1j * V5d * rd * zd
+    rr = Pd * Xaa - Wd * X1 + 1j * (V5d * rd * rd + Y3d)
+    rz = Pd * zd * Xa + 1j * V5d * rd * zd
     zz = Pd * zd * zd * X3 - Wd * X1 + 1j * (V5d * zd * zd + Y3d)
     out += [rr, rz, zz]
     return np.stack([np.broadcast_to(o, X1.shape).astype(complex) for o in out])
@@ -213,7 +221,7 @@ def modal_kernels(rt, zt, rs, zs, kp: KernelParams, force=None, offsets=None):
                 X1 = 1.0 / rho
                 X3 = 1.0 / (rho * rho2)
             K = sample_types(col(rt[idx]), col(dr[idx]), col(dz[idx]),
-                             cphi[None, :], rho2, X1, X3, kp.k0, kp.k1)
+                             cphi[None, :], rho2, X1, X3, kp.k0, kp.k1, exact=not is_near)
             F = np.fft.fft(K, axis=-1) * (2.0 * np.pi / L) / (4.0 * np.pi)
             out[idx] = F[..., : kp.M + 2].transpose(1, 0, 2)
     return out

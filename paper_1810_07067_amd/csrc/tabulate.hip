@@ -173,15 +173,24 @@ __device__ __forceinline__ Pair make_pair(double rt, double dr, double dz) {
 }
 
 // The nine integrands (times 4 pi) at one azimuth: o[2*type + {re, im}].
-template <bool K1C>
+// NEAR: X1, X3 are band-limited and r_d/rho^3, r_d^2/rho^3 go through
+// r_d = (rho^2 + a)/(2 r_t); far pairs have exact X and use r_d directly (the
+// identity cancels badly when r_t is small and rho is not).
+template <bool NEAR, bool K1C>
 __device__ __forceinline__ void sample(const Pair& g, double s2, double cphi, double X1, double X3,
                                        double k0, cd k1, double* o) {
   double rho2 = g.d2 + 4.0 * g.rt * g.rs * s2;
   double rho = sqrt(rho2);
   double rd = g.rt - g.rs * cphi;
   double zd = -g.dz;
-  double Xa = (X1 + g.a * X3) * g.inv2rt;           // r_d / rho^3
-  double Xaa = (rho2 * X1 + 2.0 * g.a * X1 + g.a * g.a * X3) * (g.inv2rt * g.inv2rt);  // r_d^2/rho^3
+  double Xa, Xaa;  // r_d / rho^3, r_d^2 / rho^3
+  if (NEAR) {
+    Xa = (X1 + g.a * X3) * g.inv2rt;
+    Xaa = (rho2 * X1 + 2.0 * g.a * X1 + g.a * g.a * X3) * (g.inv2rt * g.inv2rt);
+  } else {
+    Xa = rd * X3;
+    Xaa = rd * rd * X3;
+  }
   FacR f0 = factors(k0 * rho);
   double k02 = k0 * k0, k03 = k02 * k0, k05 = k03 * k02;
   o[0] = f0.c * X1;
@@ -441,7 +450,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
         X3b = X1b * X1b * X1b;
       }
       double fa[kSeq], fb[kSeq];
-      sample<K1C>(g, s2_tab[j], cos_tab[j], X1a, X3a, k0, k1, fa);
+      sample<NEAR, K1C>(g, s2_tab[j], cos_tab[j], X1a, X3a, k0, k1, fa);
       if (j == Lq) {
 #pragma unroll
         for (int k = 0; k < kSeq; ++k) {
@@ -449,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
           eo[kSeq + k] = 0.0;
         }
       } else {
-        sample<K1C>(g, s2_tab[jb], cos_tab[jb], X1b, X3b, k0, k1, fb);
+        sample<NEAR, K1C>(g, s2_tab[jb], cos_tab[jb], X1b, X3b, k0, k1, fb);
         double w = (j == 0) ? 1.0 : 2.0;
 #pragma unroll
         for (int k = 0; k < kSeq; ++k) {
