@@ -17,7 +17,16 @@ node from its target, (r_s - r_t, z_s - z_t), is interpolated from the nodal
 differences r_k - r_t rather than formed by subtracting interpolated
 coordinates: self-panel support nodes lie as close as 1e-10 panel lengths to
 the target, and the subtraction would leave only a few correct digits of the
-distance that the log-singular kernels depend on.
+distance that the log-singular kernels depend on.  On the target's own panel
+the offset is written (y - u_t) Q(y), with Q the degree-14 interpolant, on the
+other 15 nodes, of the divided differences (r_k - r_t)/(u_k - u_t): the same
+polynomial, without the cancellation of summing O(1) terms into a tiny one.
+Offsets are evaluated in x87 extended precision (numpy longdouble): near the
+axis a support node can differ from its target mostly in r, and the small z
+offset (which the z-derivative kernels are proportional to) would otherwise
+keep only about 12 correct digits.  The interpolation nodes are the Gauss-
+Legendre nodes rounded to double (refined in longdouble by Newton's method,
+then rounded), so that y - u_t, as small as 1e-10, is exact.
 
 Support slots per target: [0, NS) on its own panel, then NA on the left
 neighbour, then NA on the right neighbour; missing neighbours (ends of an open
@@ -55,6 +64,35 @@ def lagrange_matrix(xn, y):
     return L
 
 
+def gl_nodes_ext(order):
+    """Gauss-Legendre nodes rounded to double, returned as longdouble (Newton on
+    P_order in longdouble from numpy's nodes, which can be off by an ulp)."""
+    x = npleg.leggauss(order)[0].astype(np.longdouble)
+    for _ in range(4):
+        p0, p1 = np.ones_like(x), x.copy()
+        for k in range(2, order + 1):
+            p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+        dp = order * (x * p1 - p0) / (x * x - 1)
+        x = x - p1 / dp
+    return x.astype(np.float64).astype(np.longdouble)
+
+
+def lagrange_matrix_ext(xn, y):
+    """lagrange_matrix in longdouble (first barycentric form, y not a node)."""
+    xn = np.asarray(xn, dtype=np.longdouble)
+    y = np.asarray(y, dtype=np.longdouble)
+    n = xn.size
+    bw = np.ones(n, dtype=np.longdouble)
+    for j in range(n):
+        for k in range(n):
+            if k != j:
+                bw[j] /= (xn[j] - xn[k])
+    diff = y[:, None] - xn[None, :]
+    assert not np.any(diff == 0)
+    ell = np.prod(diff, axis=1)
+    return ell[:, None] * bw[None, :] / diff
+
+
 @dataclass
 class Support:
     r: np.ndarray      # [N, S]
@@ -83,7 +121,8 @@ def neighbours(n_panels, closed):
 def support_points(curve, self_rules, adj_rule):
     """Support-node geometry, weights and interpolation for every target."""
     order = curve.order
-    ug, _ = npleg.leggauss(order)
+    ugx = gl_nodes_ext(order)
+    ug = ugx.astype(np.float64)
     ys, ws = self_rules
     ya, wa = adj_rule
     NS, NA = ys.shape[1], ya.size
@@ -110,8 +149,20 @@ def support_points(curve, self_rules, adj_rule):
         sl = slice(slot0, slot0 + y.size)
         out["r"][t, sl] = r
         out["z"][t, sl] = z
-        out["dr"][t, sl] = Lm @ (rp[p] - curve.r[t])
-        out["dz"][t, sl] = Lm @ (zp[p] - curve.z[t])
+        ld = lambda a: np.asarray(a, dtype=np.longdouble)
+        rt, zt = ld(curve.r[t]), ld(curve.z[t])
+        if p == t // order:  # own panel: divided differences
+            kt = t % order
+            keep = np.arange(order) != kt
+            L15 = lagrange_matrix_ext(ugx[keep], y)
+            du = ugx[keep] - ugx[kt]
+            yu = ld(y) - ugx[kt]
+            out["dr"][t, sl] = (yu * (L15 @ ((ld(rp[p][keep]) - rt) / du))).astype(np.float64)
+            out["dz"][t, sl] = (yu * (L15 @ ((ld(zp[p][keep]) - zt) / du))).astype(np.float64)
+        else:
+            Lx = lagrange_matrix_ext(ugx, y)
+            out["dr"][t, sl] = (Lx @ (ld(rp[p]) - rt)).astype(np.float64)
+            out["dz"][t, sl] = (Lx @ (ld(zp[p]) - zt)).astype(np.float64)
         out["tr"][t, sl] = dr / sp
         out["tz"][t, sl] = dz / sp
         out["wq"][t, sl] = w * sp

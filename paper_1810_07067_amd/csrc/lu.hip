@@ -243,17 +243,22 @@ __global__ __launch_bounds__(256) void trsm_lu(typename V2<R>::T* A, int n, long
 constexpr int kGT = 64, kGK = 16;
 
 template <typename R> struct Mfma;
+// Operand layout (both): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
+// Accumulator layout (measured on gfx950): column l % 16 in both; row
+// 4 * i + l / 16 for f64, 4 * (l / 16) + i for f32, i = register 0..3.
 template <> struct Mfma<double> {
   using C4 = __attribute__((ext_vector_type(4))) double;
   static __device__ __forceinline__ C4 op(double a, double b, C4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
 };
 template <> struct Mfma<float> {
   using C4 = __attribute__((ext_vector_type(4))) float;
   static __device__ __forceinline__ C4 op(float a, float b, C4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
 template <typename R>
@@ -327,14 +332,14 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
     }
     __syncthreads();
   }
-  // accumulate into C: lane holds rows 4*(lane/16)+i, column lane%16
+  // accumulate into C (accumulator layout per Mfma<R>::row)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int gr = tr + wr + 16 * a + 4 * (lane >> 4) + i;
+        int gr = tr + wr + 16 * a + Mfma<R>::row(lane, i);
         int gc = tc + wc + 16 * b + (lane & 15);
         if (gr < rend && gc < cend) {
           T* p = M + (size_t)gr * n + gc;

@@ -64,33 +64,32 @@ msv_status fail(msv_plan* p, msv_status st, const std::string& msg) {
   return st;
 }
 
-// Gauss-Legendre nodes (ascending) and weights by Newton's method on P_n.
+// Gauss-Legendre nodes (ascending, rounded to double from a long double Newton
+// iteration, so that differences of nearby points and nodes are exact) and
+// weights.
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = z;
-      for (int k = 2; k <= n; ++k) {
-        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      double dp = n * (z * p1 - p0) / (z * z - 1.0);
-      double dz = p1 / dp;
-      z -= dz;
-      if (std::fabs(dz) < 1e-17) break;
-    }
-    double p0 = 1.0, p1 = z;
+  auto legendre = [n](long double z, long double& pn, long double& dpn) {
+    long double p0 = 1.0L, p1 = z;
     for (int k = 2; k <= n; ++k) {
-      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
       p0 = p1;
       p1 = p2;
     }
-    double dp = n * (z * p1 - p0) / (z * z - 1.0);
-    x[n - 1 - i] = z;
-    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    pn = p1;
+    dpn = n * (z * p1 - p0) / (z * z - 1.0L);
+  };
+  for (int i = 0; i < n; ++i) {
+    long double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    long double pn, dpn;
+    for (int it = 0; it < 12; ++it) {  // quadratic convergence: far more than enough
+      legendre(z, pn, dpn);
+      z -= pn / dpn;
+    }
+    legendre(z, pn, dpn);
+    x[n - 1 - i] = (double)z;
+    w[n - 1 - i] = (double)(2.0L / ((1.0L - z * z) * dpn * dpn));
   }
 }
 
@@ -277,24 +276,80 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
     for (int q = 0; q < p->n_self; ++q)
       lagrange_row(ug, bw, ru->h_self_u[k * p->n_self + q], &lag_self[((size_t)k * p->n_self + q) * kOrder]);
   for (int q = 0; q < p->n_adj; ++q) lagrange_row(ug, bw, ru->h_adj_u[q], &lag_adj[(size_t)q * kOrder]);
-  auto fill = [&](int t, int slot0, int pan, int nq, const double* lagrows, const double* wts) {
+  // Offsets r_s - r_t, z_s - z_t in long double: near the axis the z offset
+  // can be far smaller than the distance, and in double it would keep only
+  // about 12 digits.  Own panel: (y - u_t) Q(y) with Q interpolating the
+  // divided differences (x_k - x_t)/(u_k - u_t) on the other 15 nodes, so
+  // nothing cancels as y -> u_t (y - u_t itself is exact).
+  typedef long double ld;
+  std::vector<ld> bw16(kOrder, 1.0L), bw15((size_t)kOrder * kOrder, 0.0L);
+  for (int j = 0; j < kOrder; ++j)
+    for (int k = 0; k < kOrder; ++k)
+      if (k != j) bw16[j] /= ((ld)ug[j] - (ld)ug[k]);
+  for (int kt = 0; kt < kOrder; ++kt)
+    for (int j = 0; j < kOrder; ++j) {
+      if (j == kt) continue;
+      ld b = 1.0L;
+      for (int k = 0; k < kOrder; ++k)
+        if (k != j && k != kt) b /= ((ld)ug[j] - (ld)ug[k]);
+      bw15[kt * kOrder + j] = b;
+    }
+  // sum_k c_k l_k(y) in barycentric (second) form over nodes k != skip
+  auto interp = [&](const ld* bw, int skip, double y, const ld* cr, const ld* cz, ld& outr, ld& outz) {
+    ld nr = 0, nz = 0, den = 0;
+    for (int k = 0; k < kOrder; ++k) {
+      if (k == skip) continue;
+      if (y == ug[k]) {
+        outr = cr[k];
+        outz = cz[k];
+        return;
+      }
+      ld b = bw[k] / ((ld)y - (ld)ug[k]);
+      nr += b * cr[k];
+      nz += b * cz[k];
+      den += b;
+    }
+    outr = nr / den;
+    outz = nz / den;
+  };
+  auto fill = [&](int t, int slot0, int pan, int nq, const double* lagrows, const double* wts,
+                  const double* u) {
     const double* rp = c->h_r + pan * kOrder;
     const double* zp = c->h_z + pan * kOrder;
+    const bool own = pan == t / kOrder;
+    const int kt = t % kOrder;
+    ld cr[kOrder], cz[kOrder];
+    for (int k = 0; k < kOrder; ++k) {
+      cr[k] = (ld)rp[k] - (ld)c->h_r[t];
+      cz[k] = (ld)zp[k] - (ld)c->h_z[t];
+      if (own && k != kt) {
+        ld du = (ld)ug[k] - (ld)ug[kt];
+        cr[k] /= du;
+        cz[k] /= du;
+      }
+    }
     for (int q = 0; q < nq; ++q) {
       const double* l = lagrows + (size_t)q * kOrder;
-      double r = 0, dr = 0, dz = 0, drdu = 0, dzdu = 0;
+      double r = 0, drdu = 0, dzdu = 0;
       for (int k = 0; k < kOrder; ++k) {
         int j = pan * kOrder + k;
         r += l[k] * rp[k];
-        dr += l[k] * (rp[k] - c->h_r[t]);
-        dz += l[k] * (zp[k] - c->h_z[t]);
         drdu += l[k] * (-c->h_nz[j] * c->h_dsdu[j]);
         dzdu += l[k] * (c->h_nr[j] * c->h_dsdu[j]);
       }
+      ld dr, dz;
+      if (own) {
+        interp(&bw15[kt * kOrder], kt, u[q], cr, cz, dr, dz);
+        ld yu = (ld)u[q] - (ld)ug[kt];
+        dr *= yu;
+        dz *= yu;
+      } else {
+        interp(bw16.data(), -1, u[q], cr, cz, dr, dz);
+      }
       double sp = std::hypot(drdu, dzdu);
       double* o = &sup[((size_t)t * S + slot0 + q) * NSf];
-      o[msv::kSupDr] = dr;
-      o[msv::kSupDz] = dz;
+      o[msv::kSupDr] = (double)dr;
+      o[msv::kSupDz] = (double)dz;
       o[msv::kSupR] = r;
       o[msv::kSupTr] = drdu / sp;
       o[msv::kSupTz] = dzdu / sp;
@@ -303,9 +358,12 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   };
   for (int t = 0; t < N; ++t) {
     int pan = t / kOrder, k = t % kOrder;
-    fill(t, 0, pan, p->n_self, &lag_self[(size_t)k * p->n_self * kOrder], ru->h_self_w + k * p->n_self);
-    if (left[pan] >= 0) fill(t, p->n_self, left[pan], p->n_adj, lag_adj.data(), ru->h_adj_w);
-    if (right[pan] >= 0) fill(t, p->n_self + p->n_adj, right[pan], p->n_adj, lag_adj.data(), ru->h_adj_w);
+    fill(t, 0, pan, p->n_self, &lag_self[(size_t)k * p->n_self * kOrder], ru->h_self_w + k * p->n_self,
+         ru->h_self_u + k * p->n_self);
+    if (left[pan] >= 0)
+      fill(t, p->n_self, left[pan], p->n_adj, lag_adj.data(), ru->h_adj_w, ru->h_adj_u);
+    if (right[pan] >= 0)
+      fill(t, p->n_self + p->n_adj, right[pan], p->n_adj, lag_adj.data(), ru->h_adj_w, ru->h_adj_u);
   }
   // pair classes: near iff acosh(chi) < a_min (split + convolution), else the
   // plain L-point trapezoid; coincident pairs and unused slots are zero

@@ -1,8 +1,28 @@
 """GPU parity: the HIP library (through the C-ABI) against the FP64 oracle.
 
-Tolerances: modal kernels 1e-12 relative, normwise over modes per (type,
-target, source); matrices 1e-12 relative to the largest entry of the row
-block; surface currents and far fields 1e-10 relative.
+Each stage is checked on the oracle's own inputs, then the whole path end to
+end:
+
+  modal kernels   msv_tabulate vs oracle.modal.tabulate: 1e-12 relative,
+                  normwise over modes per (type, target, source); slots the
+                  oracle leaves zero must be exactly zero.
+  assembly        msv_assemble on the ORACLE table vs oracle.assemble on the
+                  same table.  Rows next to the axis carry the 1/r_t^2 terms
+                  of the modal operators (Section 3), and there a one-ulp
+                  perturbation of the table moves the oracle's own row by up
+                  to 1e-5 of its size.  Per row i the bound is therefore
+                  max(1e-12 * rowmax_i, 16 * sens_i), sens_i being the largest
+                  change of row i (over modes) when every table entry is
+                  scaled by an independent 1 + u 2^-53, u uniform in [-1, 1].
+                  Rows whose sensitivity is below the 1e-12 level (all rows
+                  away from the axis) are held to 1e-12.
+  factor + solve  msv_factor/msv_solve on the ORACLE matrices vs the oracle's
+                  dense solve: 1e-10 relative (max norm).
+  end to end      far fields and surface currents (the latter in the L2 norm
+                  of the discretization, weights sqrt(w_j), Section 6), each
+                  to max(1e-10, 16 * sens) relative, sens being the oracle's
+                  own change of that output under the same ulp perturbation
+                  of the table.
 """
 import numpy as np
 import pytest
@@ -17,109 +37,135 @@ pytestmark = pytest.mark.gpu
 
 import paper_1810_07067_amd as msv  # noqa: E402
 
-
-def make_plan(curve, k0, eps1, M, L, precision=0, mu1=1.0):
-    print(f"[case] {curve.name} N={curve.n} k0={k0} eps1={eps1} M={M} L={L} prec={precision}", flush=True)
-    return msv.plan_from_curve(curve, RULES, k0, eps1, mu1, m_max=M, fft_len=L, precision=precision)
+DIRS = np.array([[0.3, 0.4, np.sqrt(0.75)], [-0.6, 0.0, 0.8], [0.0, -1.0, 0.0], [0.0, 0.0, 1.0]])
 
 
-@pytest.fixture(scope="module")
-def sphere():
-    curve = geometry.sphere(8)
-    k0, eps1, M, L = 1.0, 2.25, 16, 64
-    sup, kp = oracle_setup(curve, k0, eps1, M, L)
+def _cylinder_small():
+    return geometry.polygon([(0.0, -1.0), (1.0, -1.0), (1.0, 1.0), (0.0, 1.0)], 1.0, 2, "cylinder_small")
+
+
+# name -> (curve builder, k0, eps1, mu1, M, L)
+CASES = {
+    "sphere": (lambda: geometry.sphere(8), 1.0, 2.25, 1.0, 16, 64),
+    "torus_magnetic": (lambda: geometry.torus(6), 2.0, 3.0, 2.0, 8, 128),
+    "cylinder_lossy": (_cylinder_small, 3.0, 4.0 + 0.1j, 1.0, 8, 128),
+    "spheroid_c3": (lambda: geometry.spheroid(6, 3.0), 2.0, 4.0, 1.0, 10, 128),
+}
+
+
+def make_plan(curve, k0, eps1, mu1, M, L, precision=0, **kw):
+    print(f"[case] {curve.name} N={curve.n} k0={k0} eps1={eps1} mu1={mu1} M={M} L={L} "
+          f"prec={precision}", flush=True)
+    return msv.plan_from_curve(curve, RULES, k0, eps1, mu1, m_max=M, fft_len=L, precision=precision, **kw)
+
+
+def l2w(curve):
+    return np.sqrt(np.repeat(geometry.gl_weights(curve), 4))
+
+
+def ulp_perturbed(tab, seed):
+    rng = np.random.default_rng(seed)
+    return tab * (1.0 + 2.0 ** -53 * rng.uniform(-1.0, 1.0, tab.shape))
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    build, k0, eps1, mu1, M, L = CASES[request.param]
+    curve = build()
+    sup, kp = oracle_setup(curve, k0, eps1, M, L, mu1=mu1)
     tab = oracle_table(curve, sup, kp)
-    plan = make_plan(curve, k0, eps1, M, L)
-    kern = plan.tabulate()
-    torch.cuda.synchronize()
-    return dict(curve=curve, k0=k0, eps1=eps1, M=M, L=L, sup=sup, kp=kp, tab=tab, plan=plan, kern=kern)
+    mats = np.array([oracle_matrix(curve, sup, tab, m, k0, kp.k1, eps1, mu1) for m in range(M + 1)])
+    tabp = ulp_perturbed(tab, 11)
+    matsp = np.array([oracle_matrix(curve, sup, tabp, m, k0, kp.k1, eps1, mu1) for m in range(M + 1)])
+    w = geometry.gl_weights(curve)
+    waves = [incident.tilted_direction(30.0), incident.tilted_direction(75.0)]
+    rhs = incident.rhs_modes(curve, waves, k0, -M, M, mu0=1.0)
+    x = osolve.solve_modes(list(mats), w, rhs, -M, M)
+    xp = osolve.solve_modes(list(matsp), w, rhs, -M, M)
+    E = farfield.far_field(curve, w, x[:, 0], -M, k0, k0, 1.0, DIRS)
+    Ep = farfield.far_field(curve, w, xp[:, 0], -M, k0, k0, 1.0, DIRS)
+    sw = l2w(curve)
+    return dict(name=request.param, curve=curve, k0=k0, eps1=eps1, mu1=mu1, M=M, L=L, sup=sup, kp=kp,
+                tab=tab, mats=mats, matsp=matsp, w=w, rhs=rhs, x=x, E=E,
+                sens_x=np.linalg.norm(sw * (x - xp)) / np.linalg.norm(sw * x),
+                sens_E=np.max(np.abs(E - Ep)) / np.max(np.abs(E)))
 
 
-def test_sphere_table_parity(sphere):
-    got = sphere["kern"].cpu().numpy()
-    ref = sphere["tab"]
-    assert got.shape == ref.shape
-    err, zero_bad = normwise_table_error(got, ref)
+def test_table_parity(case):
+    plan = make_plan(case["curve"], case["k0"], case["eps1"], case["mu1"], case["M"], case["L"])
+    got = plan.tabulate().cpu().numpy()
+    assert got.shape == case["tab"].shape
+    err, zero_bad = normwise_table_error(got, case["tab"])
+    print(f"[table] {case['name']} normwise err {err:.3e}", flush=True)
     assert zero_bad == 0.0
     assert err < 1e-12, err
 
 
-def test_sphere_matrix_parity(sphere):
-    s = sphere
-    A = s["plan"].assemble(s["kern"], 0, s["M"])
-    torch.cuda.synchronize()
-    Ag = A.cpu().numpy()
-    for m in (0, 1, 2, 7, s["M"]):
-        Ar = oracle_matrix(s["curve"], s["sup"], s["tab"], m, s["k0"], s["kp"].k1, s["eps1"])
-        scale = np.max(np.abs(Ar))
-        assert np.max(np.abs(Ag[m] - Ar)) < 1e-12 * scale, m
+def test_assembly_parity(case):
+    c = case
+    plan = make_plan(c["curve"], c["k0"], c["eps1"], c["mu1"], c["M"], c["L"])
+    A = plan.assemble(torch.from_numpy(c["tab"]).cuda(), 0, c["M"]).cpu().numpy()
+    ref = c["mats"]
+    diff = np.max(np.abs(A - ref), axis=(0, 2))
+    rowmax = np.max(np.abs(ref), axis=(0, 2))
+    sens = np.max(np.abs(c["matsp"] - ref), axis=(0, 2))
+    bound = np.maximum(1e-12 * rowmax, 16.0 * sens)
+    tight = sens < 1e-13 * rowmax
+    print(f"[assemble] {c['name']} max row err/rowmax {np.max(diff / rowmax):.3e}; rows held to 1e-12: "
+          f"{tight.sum()}/{tight.size}, their max {np.max((diff / rowmax)[tight]) if tight.any() else 0:.3e}",
+          flush=True)
+    assert np.all(diff <= bound), np.max(diff / bound)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_sphere_solution_and_far_field(sphere, precision):
-    s = sphere
-    curve, M, k0 = s["curve"], s["M"], s["k0"]
-    plan = make_plan(curve, k0, s["eps1"], M, s["L"], precision=precision)
-    kern = plan.tabulate()
-    A = plan.assemble(kern, 0, M)
-    Aref = [oracle_matrix(curve, s["sup"], s["tab"], m, k0, s["kp"].k1, s["eps1"]) for m in range(M + 1)]
+def test_factor_solve_parity(case, precision):
+    c = case
+    M = c["M"]
+    plan = make_plan(c["curve"], c["k0"], c["eps1"], c["mu1"], M, c["L"], precision=precision)
+    A = torch.from_numpy(c["mats"].copy()).cuda()
     plan.factor(A, 0, M)
-    d, p = incident.tilted_direction(30.0)
-    rhs = incident.rhs_modes(curve, [(d, p)], k0, -M, M)
-    x = plan.solve(-M, M, torch.from_numpy(rhs).cuda())
-    torch.cuda.synchronize()
-    xg = x.cpu().numpy()
-    w = geometry.gl_weights(curve)
-    xr = osolve.solve_modes(Aref, w, rhs, -M, M)
-    assert np.max(np.abs(xg - xr)) < 1e-10 * np.max(np.abs(xr))
-    dirs = np.array([[0.3, 0.4, np.sqrt(0.75)], [-0.6, 0.0, 0.8], [0.0, -1.0, 0.0]])
-    Eg = farfield.far_field(curve, w, xg[:, 0], -M, k0, k0, 1.0, dirs)
-    Er = farfield.far_field(curve, w, xr[:, 0], -M, k0, k0, 1.0, dirs)
-    assert np.max(np.abs(Eg - Er)) < 1e-10 * np.max(np.abs(Er))
+    x = plan.solve(-M, M, torch.from_numpy(c["rhs"]).cuda()).cpu().numpy()
+    err = np.max(np.abs(x - c["x"])) / np.max(np.abs(c["x"]))
+    print(f"[solve] {c['name']} prec {precision} err {err:.3e} ir {plan.last_ir_iterations()}", flush=True)
+    assert err < 1e-10, err
     if precision == 1:
         assert 1 <= plan.last_ir_iterations() <= 10
 
 
-def test_negative_modes_use_parity(sphere):
-    """Solving mode -m with the factors of m equals solving the directly
-    assembled A_{-m} (oracle)."""
-    s = sphere
-    curve, M, k0 = s["curve"], s["M"], s["k0"]
-    plan = s["plan"]
-    A = plan.assemble(s["kern"], 0, 3)
-    plan.factor(A, 0, 3)
-    rng = np.random.default_rng(7)
-    n = 4 * curve.n
-    b = rng.standard_normal((7, 2, n)) + 1j * rng.standard_normal((7, 2, n))
-    x = plan.solve(-3, 3, torch.from_numpy(b).cuda()).cpu().numpy()
-    w = geometry.gl_weights(curve)
-    mats = [oracle_matrix(curve, s["sup"], s["tab"], m, k0, s["kp"].k1, s["eps1"]) for m in range(4)]
-    xr = osolve.solve_modes(mats, w, b, -3, 3)
-    assert np.max(np.abs(x - xr)) < 1e-10 * np.max(np.abs(xr))
-
-
-@pytest.mark.parametrize("which", ["torus", "cylinder", "spheroid_c3"])
-def test_other_bodies_table_and_matrix(which):
-    """Closed curve, corners with dyadic refinement, complex k1, elongated body."""
-    if which == "torus":
-        curve, k0, eps1, M, L = geometry.torus(6), 2.0, 3.0, 8, 128
-    elif which == "cylinder":
-        curve, k0, eps1, M, L = geometry.polygon([(0.0, -1.0), (1.0, -1.0), (1.0, 1.0), (0.0, 1.0)],
-                                                 2.0, 6, "cylinder_small"), 3.0, 4.0 + 0.1j, 8, 128
-    else:
-        curve, k0, eps1, M, L = geometry.spheroid(6, 3.0), 2.0, 4.0, 10, 128
-    sup, kp = oracle_setup(curve, k0, eps1, M, L)
-    rows = np.array([0, 5, curve.n // 2, curve.n - 1])
-    tab = oracle_table(curve, sup, kp, rows=rows)
-    plan = make_plan(curve, k0, eps1, M, L)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_end_to_end(case, precision):
+    c = case
+    curve, M, k0 = c["curve"], c["M"], c["k0"]
+    plan = make_plan(curve, k0, c["eps1"], c["mu1"], M, c["L"], precision=precision)
     kern = plan.tabulate()
     A = plan.assemble(kern, 0, M)
-    torch.cuda.synchronize()
-    got = kern.cpu().numpy()[:, :, rows, :]
-    err, zero_bad = normwise_table_error(got, tab)
-    assert zero_bad == 0.0 and err < 1e-12, err
-    Ag = A.cpu().numpy()
-    for m in (0, 1, M):
-        Ar = oracle_matrix(curve, sup, tab, m, k0, kp.k1, eps1, rows=rows)
-        rsel = np.concatenate([np.arange(4 * t, 4 * t + 4) for t in rows])
-        assert np.max(np.abs(Ag[m][rsel] - Ar)) < 1e-12 * np.max(np.abs(Ar)), (which, m)
+    plan.factor(A, 0, M)
+    x = plan.solve(-M, M, torch.from_numpy(c["rhs"]).cuda()).cpu().numpy()
+    sw = l2w(curve)
+    xerr = np.linalg.norm(sw * (x - c["x"])) / np.linalg.norm(sw * c["x"])
+    E = farfield.far_field(curve, c["w"], x[:, 0], -M, k0, k0, 1.0, DIRS)
+    ferr = np.max(np.abs(E - c["E"])) / np.max(np.abs(c["E"]))
+    xtol = max(1e-10, 16.0 * c["sens_x"])
+    ftol = max(1e-10, 16.0 * c["sens_E"])
+    print(f"[e2e] {c['name']} prec {precision} far field {ferr:.3e} (oracle ulp sensitivity "
+          f"{c['sens_E']:.3e}); currents L2 {xerr:.3e} (oracle ulp sensitivity {c['sens_x']:.3e})", flush=True)
+    assert ferr < ftol, (ferr, ftol)
+    assert xerr < xtol, (xerr, xtol)
+
+
+def test_negative_modes_use_parity(case):
+    """Solving mode -m with the factors of mode m (msv_solve applies D) equals
+    solving the directly assembled A_{-m} of the oracle."""
+    c = case
+    if c["name"] != "sphere":
+        pytest.skip("one body suffices")
+    M = 3
+    plan = make_plan(c["curve"], c["k0"], c["eps1"], c["mu1"], c["M"], c["L"])
+    A = torch.from_numpy(c["mats"][: M + 1].copy()).cuda()
+    plan.factor(A, 0, M)
+    rng = np.random.default_rng(7)
+    n = 4 * c["curve"].n
+    b = rng.standard_normal((2 * M + 1, 3, n)) + 1j * rng.standard_normal((2 * M + 1, 3, n))
+    x = plan.solve(-M, M, torch.from_numpy(b).cuda()).cpu().numpy()
+    xr = osolve.solve_modes(list(c["mats"][: M + 1]), c["w"], b, -M, M)
+    assert np.max(np.abs(x - xr)) < 1e-10 * np.max(np.abs(xr))
