@@ -431,125 +431,6 @@ hipError_t factor(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBa
   return hipSuccess;
 }
 
-// ---------------------------------------------------------------------------
-// solves: X[nb][nrhs][n] (each right-hand side contiguous); one workgroup per
-// (matrix, group of kNQ right-hand sides) reads the factors once per group:
-// pivots, then forward (unit L) and backward (U) substitution in row blocks
-// of 64: a blocked dot product against the solved part (4 threads per row),
-// then the 64 x 64 triangle by one thread per right-hand side.
-// ---------------------------------------------------------------------------
-constexpr int kNQ = 8;
-
-template <typename R>
-__global__ __launch_bounds__(256) void trisolve(const typename V2<R>::T* LU, const int32_t* ipiv,
-                                                const int* map, typename V2<R>::T* X, int n,
-                                                long long stride, int nrhs) {
-  using T = typename V2<R>::T;
-  const int mat = map[blockIdx.y];
-  const int q0 = blockIdx.x * kNQ;
-  const int nq = nrhs - q0 < kNQ ? nrhs - q0 : kNQ;
-  const T* M = LU + (size_t)mat * stride;
-  const int32_t* piv = ipiv + (size_t)mat * n;
-  T* xb = X + ((size_t)blockIdx.y * nrhs + q0) * n;
-  const int tid = threadIdx.x;
-  if (tid < nq) {
-    T* x = xb + (size_t)tid * n;
-    for (int k = 0; k < n; ++k) {
-      int p = piv[k];
-      if (p != k) {
-        T a = x[k];
-        x[k] = x[p];
-        x[p] = a;
-      }
-    }
-  }
-  __syncthreads();
-  __shared__ T xs[kNQ][64];
-  __shared__ R pr[4][64][kNQ], pim[4][64][kNQ];
-  const int nblk = (n + 63) / 64;
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool fwd = pass == 0;
-    for (int bb = 0; bb < nblk; ++bb) {
-      const int bi = fwd ? bb : nblk - 1 - bb;
-      const int rb = bi * 64;
-      const int h = n - rb < 64 ? n - rb : 64;
-      const int rl = tid >> 2, part = tid & 3;
-      const int row = rb + rl;
-      R sr[kNQ], si[kNQ];
-#pragma unroll
-      for (int q = 0; q < kNQ; ++q) {
-        sr[q] = 0;
-        si[q] = 0;
-      }
-      if (row < n) {
-        const int jb = fwd ? 0 : rb + h;
-        const int je = fwd ? rb : n;
-        for (int j = jb + part; j < je; j += 4) {
-          T l = M[(size_t)row * n + j];
-#pragma unroll
-          for (int q = 0; q < kNQ; ++q)
-            if (q < nq) {
-              T v = xb[(size_t)q * n + j];
-              sr[q] += l.x * v.x - l.y * v.y;
-              si[q] += l.x * v.y + l.y * v.x;
-            }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kNQ; ++q) {
-        pr[part][rl][q] = sr[q];
-        pim[part][rl][q] = si[q];
-      }
-      __syncthreads();
-      for (int e = tid; e < kNQ * 64; e += 256) {
-        int q = e / 64, r = e % 64;
-        if (q < nq && r < h) {
-          T v = xb[(size_t)q * n + rb + r];
-          v.x -= pr[0][r][q] + pr[1][r][q] + pr[2][r][q] + pr[3][r][q];
-          v.y -= pim[0][r][q] + pim[1][r][q] + pim[2][r][q] + pim[3][r][q];
-          xs[q][r] = v;
-        }
-      }
-      __syncthreads();
-      if (tid < nq) {
-        T* xq = xs[tid];
-        if (fwd) {
-          for (int i = 0; i < h; ++i) {
-            T s = xq[i];
-            for (int j = 0; j < i; ++j) {
-              T l = M[(size_t)(rb + i) * n + rb + j];
-              s.x -= l.x * xq[j].x - l.y * xq[j].y;
-              s.y -= l.x * xq[j].y + l.y * xq[j].x;
-            }
-            xq[i] = s;
-          }
-        } else {
-          for (int i = h - 1; i >= 0; --i) {
-            T s = xq[i];
-            for (int j = i + 1; j < h; ++j) {
-              T u = M[(size_t)(rb + i) * n + rb + j];
-              s.x -= u.x * xq[j].x - u.y * xq[j].y;
-              s.y -= u.x * xq[j].y + u.y * xq[j].x;
-            }
-            T d = M[(size_t)(rb + i) * n + rb + i];
-            R den = d.x * d.x + d.y * d.y;
-            T r;
-            r.x = (s.x * d.x + s.y * d.y) / den;
-            r.y = (s.y * d.x - s.x * d.y) / den;
-            xq[i] = r;
-          }
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < kNQ * 64; e += 256) {
-        int q = e / 64, r = e % 64;
-        if (q < nq && r < h) xb[(size_t)q * n + rb + r] = xs[q][r];
-      }
-      __syncthreads();
-    }
-  }
-}
-
 }  // namespace
 
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
@@ -558,17 +439,4 @@ hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& 
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
   return factor<float>(A, ipiv, info, b, s);
 }
-hipError_t lu_solve_z(const double2* LU, const int32_t* ipiv, const int* map, double2* X, int nrhs,
-                      const LuBatch& b, hipStream_t s) {
-  hipLaunchKernelGGL(trisolve<double>, dim3((nrhs + kNQ - 1) / kNQ, b.nb), dim3(256), 0, s, LU, ipiv, map,
-                     X, b.n, b.stride, nrhs);
-  return hipGetLastError();
-}
-hipError_t lu_solve_c(const float2* LU, const int32_t* ipiv, const int* map, float2* X, int nrhs,
-                      const LuBatch& b, hipStream_t s) {
-  hipLaunchKernelGGL(trisolve<float>, dim3((nrhs + kNQ - 1) / kNQ, b.nb), dim3(256), 0, s, LU, ipiv, map,
-                     X, b.n, b.stride, nrhs);
-  return hipGetLastError();
-}
-
 }  // namespace msv

@@ -73,12 +73,34 @@ struct LuBatch {
 };
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s);
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s);
-// x <- A^{-1} x for nrhs right-hand sides stored [nvec][nrhs][n]; batch entry
-// i uses matrix map[i] of the factored batch (LuBatch::nb = nvec here).
-hipError_t lu_solve_z(const double2* LU, const int32_t* ipiv, const int* map, double2* X, int nrhs,
-                      const LuBatch& b, hipStream_t s);
-hipError_t lu_solve_c(const float2* LU, const int32_t* ipiv, const int* map, float2* X, int nrhs,
-                      const LuBatch& b, hipStream_t s);
+
+// Right-hand-side batches for the solves (trsv.hip): up to kVB vectors that
+// use factor `fac`; vector v is stored at element off[v] * n of the work
+// arrays ([modes][nrhs][n]).
+constexpr int kVB = 16;
+struct VecBatch {
+  int fac;
+  int nv;
+  int off[kVB];
+};
+// perm[f][i] = source row of row i under the interchanges ipiv[f]
+hipError_t lu_perm(const int32_t* ipiv, int32_t* perm, int n, int nfac, hipStream_t s);
+// out = P in for every vector of the batches (complex128 or rounded to complex64)
+hipError_t gather_z(const double2* in, double2* out, const int32_t* perm, const VecBatch* d_vb, int nvb, int n,
+                    hipStream_t s);
+hipError_t gather_c(const double2* in, float2* out, const int32_t* perm, const VecBatch* d_vb, int nvb, int n,
+                    hipStream_t s);
+// inverses of the 64 x 64 diagonal blocks of L and U: [nfac][ceil(n/64)][2][64][64]
+hipError_t lu_inv_diag_z(const double2* LU, long long stride, int n, int nfac, double2* inv, hipStream_t s);
+hipError_t lu_inv_diag_c(const float2* LU, long long stride, int n, int nfac, float2* inv, hipStream_t s);
+// X <- U^{-1} L^{-1} X (X already permuted); Y is scratch of the same layout
+hipError_t trsv_z(const double2* LU, const double2* inv, long long stride, int n, const VecBatch* d_vb, int nvb,
+                  double2* X, double2* Y, hipStream_t s);
+hipError_t trsv_c(const float2* LU, const float2* inv, long long stride, int n, const VecBatch* d_vb, int nvb,
+                  float2* X, float2* Y, hipStream_t s);
+// r = b - A[fac] x per vector, complex128
+hipError_t residual_batches(const double2* A, long long stride, int n, const VecBatch* d_vb, int nvb,
+                            const double2* b, const double2* x, double2* r, hipStream_t s);
 
 // solve-side helpers (solve.hip)
 hipError_t solve_prep(const double2* rhs, double2* xw, const double* sqw, int n, int nrhs, int nm,
@@ -88,8 +110,6 @@ hipError_t solve_finish(const double2* xw, double2* x, const double* sqw, int n,
 hipError_t conv_c64(const double2* a, float2* b, size_t count, hipStream_t s);
 hipError_t accum_c64(double2* x, const float2* d, size_t count, hipStream_t s);
 hipError_t zero_c128(double2* x, size_t count, hipStream_t s);
-hipError_t residual_z(const double2* A, const int* map, const double2* b, const double2* x, double2* r,
-                      int n, int nrhs, int nm, hipStream_t s);
 hipError_t ratios(const double2* r, const double2* b, double* out, int n, int nvec, hipStream_t s);
 
 }  // namespace msv

@@ -40,6 +40,9 @@ struct msv_plan {
   size_t fac32_elems = 0;
   int32_t* d_ipiv = nullptr;
   int32_t* d_info = nullptr;
+  int32_t* d_perm = nullptr;   // row permutation of each factor
+  void* d_inv = nullptr;       // inverses of the 64 x 64 diagonal blocks of L and U
+  size_t inv_bytes = 0;
   size_t ipiv_elems = 0;
   bool info_checked = false;
   // solve workspace
@@ -47,10 +50,11 @@ struct msv_plan {
   double2* d_xw = nullptr;  // weighted solution
   double2* d_rw = nullptr;  // residual
   float2* d_r32 = nullptr;  // complex64 residual / correction
+  float2* d_y32 = nullptr;  // complex64 sweep scratch
   double* d_nrm = nullptr;
-  int* d_map = nullptr;
+  msv::VecBatch* d_vb = nullptr;
   size_t work_elems = 0;
-  size_t map_elems = 0;
+  size_t vb_cap = 0;
   std::string err;
 };
 
@@ -158,7 +162,7 @@ void msv_plan_destroy(msv_plan* p) {
   if (!p) return;
   void* bufs[] = {p->d_r, p->d_z, p->d_tr, p->d_tz, p->d_w, p->d_sqw, p->d_sup, p->d_lag_self,
                   p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
-                  p->d_info, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_nrm, p->d_map};
+                  p->d_info, p->d_perm, p->d_inv, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm, p->d_vb};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -507,10 +511,13 @@ msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, vo
   if ((size_t)nb * n > p->ipiv_elems) {
     if (p->d_ipiv) (void)hipFree(p->d_ipiv);
     if (p->d_info) (void)hipFree(p->d_info);
+    if (p->d_perm) (void)hipFree(p->d_perm);
     p->d_ipiv = nullptr;
     p->d_info = nullptr;
+    p->d_perm = nullptr;
     p->ipiv_elems = 0;
     if (hipMalloc(&p->d_ipiv, sizeof(int32_t) * (size_t)nb * n) != hipSuccess ||
+        hipMalloc(&p->d_perm, sizeof(int32_t) * (size_t)nb * n) != hipSuccess ||
         hipMalloc(&p->d_info, sizeof(int32_t) * nb) != hipSuccess)
       return fail(p, MSV_ENOMEM, "pivot allocation failed");
     p->ipiv_elems = (size_t)nb * n;
@@ -530,6 +537,20 @@ msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, vo
     MSV_HIP(p, msv::conv_c64(reinterpret_cast<const double2*>(d_A), p->d_fac32, (size_t)nb * nn, s));
     MSV_HIP(p, msv::lu_factor_c(p->d_fac32, p->d_ipiv, p->d_info, b, s));
   }
+  MSV_HIP(p, msv::lu_perm(p->d_ipiv, p->d_perm, n, nb, s));
+  const size_t inv_bytes = (size_t)nb * ((n + 63) / 64) * 2 * 64 * 64 * (p->precision == 0 ? 16 : 8);
+  if (inv_bytes > p->inv_bytes) {
+    if (p->d_inv) (void)hipFree(p->d_inv);
+    p->d_inv = nullptr;
+    p->inv_bytes = 0;
+    if (hipMalloc(&p->d_inv, inv_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "block inverse allocation failed");
+    p->inv_bytes = inv_bytes;
+  }
+  if (p->precision == 0)
+    MSV_HIP(p, msv::lu_inv_diag_z(reinterpret_cast<const double2*>(d_A), (long long)nn, n, nb,
+                                  static_cast<double2*>(p->d_inv), s));
+  else
+    MSV_HIP(p, msv::lu_inv_diag_c(p->d_fac32, (long long)nn, n, nb, static_cast<float2*>(p->d_inv), s));
   p->fac_lo = m_lo;
   p->fac_hi = m_hi;
   p->fac_A = d_A;
@@ -564,38 +585,57 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
   }
   const size_t elems = (size_t)nm * n_rhs * n;
   if (elems > p->work_elems) {
-    void* bufs[] = {p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_nrm};
+    void* bufs[] = {p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm};
     for (void* bf : bufs)
       if (bf) (void)hipFree(bf);
     p->d_bw = p->d_xw = p->d_rw = nullptr;
-    p->d_r32 = nullptr;
+    p->d_r32 = p->d_y32 = nullptr;
     p->d_nrm = nullptr;
     p->work_elems = 0;
     if (hipMalloc(&p->d_bw, sizeof(double2) * elems) != hipSuccess ||
         hipMalloc(&p->d_xw, sizeof(double2) * elems) != hipSuccess ||
         hipMalloc(&p->d_rw, sizeof(double2) * elems) != hipSuccess ||
-        hipMalloc(&p->d_r32, sizeof(float2) * elems) != hipSuccess ||
+        (p->precision == 1 && (hipMalloc(&p->d_r32, sizeof(float2) * elems) != hipSuccess ||
+                               hipMalloc(&p->d_y32, sizeof(float2) * elems) != hipSuccess)) ||
         hipMalloc(&p->d_nrm, sizeof(double) * (size_t)nm * n_rhs) != hipSuccess)
       return fail(p, MSV_ENOMEM, "solve workspace allocation failed");
     p->work_elems = elems;
   }
-  if ((size_t)nm > p->map_elems) {
-    if (p->d_map) (void)hipFree(p->d_map);
-    p->d_map = nullptr;
-    if (hipMalloc(&p->d_map, sizeof(int) * nm) != hipSuccess) return fail(p, MSV_ENOMEM, "map allocation failed");
-    p->map_elems = nm;
+  // vector batches: every (mode, rhs) vector grouped by the factor it uses
+  std::vector<msv::VecBatch> vb;
+  for (int f = 0; f < nfac; ++f) {
+    msv::VecBatch cur{};
+    cur.fac = f;
+    for (int i = 0; i < nm; ++i) {
+      if (std::abs(m_lo + i) - p->fac_lo != f) continue;
+      for (int q = 0; q < n_rhs; ++q) {
+        cur.off[cur.nv++] = i * n_rhs + q;
+        if (cur.nv == msv::kVB) {
+          vb.push_back(cur);
+          cur.nv = 0;
+        }
+      }
+    }
+    if (cur.nv) vb.push_back(cur);
   }
-  std::vector<int> map(nm);
-  for (int i = 0; i < nm; ++i) map[i] = std::abs(m_lo + i) - p->fac_lo;
-  MSV_HIP(p, hipMemcpy(p->d_map, map.data(), sizeof(int) * nm, hipMemcpyHostToDevice));
-  msv::LuBatch b{n, nm, n, (long long)n * n};
+  const int nvb = (int)vb.size();
+  if ((size_t)nvb > p->vb_cap) {
+    if (p->d_vb) (void)hipFree(p->d_vb);
+    p->d_vb = nullptr;
+    p->vb_cap = 0;
+    if (hipMalloc(&p->d_vb, sizeof(msv::VecBatch) * nvb) != hipSuccess)
+      return fail(p, MSV_ENOMEM, "batch table allocation failed");
+    p->vb_cap = nvb;
+  }
+  MSV_HIP(p, hipMemcpy(p->d_vb, vb.data(), sizeof(msv::VecBatch) * nvb, hipMemcpyHostToDevice));
+  const long long nn = (long long)n * n;
   const double2* rhs = reinterpret_cast<const double2*>(d_rhs);
   double2* x = reinterpret_cast<double2*>(d_x);
   MSV_HIP(p, msv::solve_prep(rhs, p->d_bw, p->d_sqw, n, n_rhs, nm, m_lo, s));
   if (p->precision == 0) {
-    MSV_HIP(p, hipMemcpyAsync(p->d_xw, p->d_bw, sizeof(double2) * elems, hipMemcpyDeviceToDevice, s));
-    MSV_HIP(p, msv::lu_solve_z(reinterpret_cast<const double2*>(p->fac_A), p->d_ipiv, p->d_map, p->d_xw, n_rhs,
-                               b, s));
+    MSV_HIP(p, msv::gather_z(p->d_bw, p->d_xw, p->d_perm, p->d_vb, nvb, n, s));
+    MSV_HIP(p, msv::trsv_z(reinterpret_cast<const double2*>(p->fac_A), static_cast<const double2*>(p->d_inv), nn, n,
+                           p->d_vb, nvb, p->d_xw, p->d_rw, s));
     p->last_ir_iters = 0;
   } else {
     const double2* Aref = reinterpret_cast<const double2*>(p->fac_A);
@@ -605,10 +645,11 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
     bool conv = false;
     int it = 0;
     for (it = 1; it <= p->ir_max_iter; ++it) {
-      MSV_HIP(p, msv::conv_c64(p->d_rw, p->d_r32, elems, s));
-      MSV_HIP(p, msv::lu_solve_c(p->d_fac32, p->d_ipiv, p->d_map, p->d_r32, n_rhs, b, s));
+      MSV_HIP(p, msv::gather_c(p->d_rw, p->d_r32, p->d_perm, p->d_vb, nvb, n, s));
+      MSV_HIP(p, msv::trsv_c(p->d_fac32, static_cast<const float2*>(p->d_inv), nn, n, p->d_vb, nvb, p->d_r32,
+                             p->d_y32, s));
       MSV_HIP(p, msv::accum_c64(p->d_xw, p->d_r32, elems, s));
-      MSV_HIP(p, msv::residual_z(Aref, p->d_map, p->d_bw, p->d_xw, p->d_rw, n, n_rhs, nm, s));
+      MSV_HIP(p, msv::residual_batches(Aref, nn, n, p->d_vb, nvb, p->d_bw, p->d_xw, p->d_rw, s));
       MSV_HIP(p, msv::ratios(p->d_rw, p->d_bw, p->d_nrm, n, nm * n_rhs, s));
       MSV_HIP(p, hipMemcpyAsync(rat.data(), p->d_nrm, sizeof(double) * rat.size(), hipMemcpyDeviceToHost, s));
       MSV_HIP(p, hipStreamSynchronize(s));

@@ -73,56 +73,6 @@ __global__ void fill_zero(double2* x, size_t count) {
   if (e < count) x[e] = make_double2(0.0, 0.0);
 }
 
-// r[i][q] = b[i][q] - A[map[i]] x[i][q], one wave per row, up to 8 rhs per block
-constexpr int kRQ = 8;
-__global__ __launch_bounds__(256) void residual(const double2* A, const int* map, const double2* b,
-                                                const double2* x, double2* r, int n, int nrhs) {
-  const int i = blockIdx.y;
-  const int q0 = blockIdx.z * kRQ;
-  const int nq = min(kRQ, nrhs - q0);
-  const double2* M = A + (size_t)map[i] * n * n;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + wave;
-  if (row >= n) return;
-  double ar[kRQ], ai[kRQ];
-#pragma unroll
-  for (int q = 0; q < kRQ; ++q) {
-    ar[q] = 0;
-    ai[q] = 0;
-  }
-  const double2* Ar = M + (size_t)row * n;
-  for (int j = lane; j < n; j += 64) {
-    double2 a = Ar[j];
-#pragma unroll
-    for (int q = 0; q < kRQ; ++q)
-      if (q < nq) {
-        double2 v = x[((size_t)i * nrhs + q0 + q) * n + j];
-        ar[q] += a.x * v.x - a.y * v.y;
-        ai[q] += a.x * v.y + a.y * v.x;
-      }
-  }
-#pragma unroll
-  for (int q = 0; q < kRQ; ++q) {
-    for (int off = 32; off > 0; off >>= 1) {
-      ar[q] += __shfl_xor(ar[q], off);
-      ai[q] += __shfl_xor(ai[q], off);
-    }
-  }
-  if (lane < nq) {
-    int q = lane;
-    double sr = 0, si = 0;
-#pragma unroll
-    for (int k = 0; k < kRQ; ++k)
-      if (k == q) {
-        sr = ar[k];
-        si = ai[k];
-      }
-    size_t o = ((size_t)i * nrhs + q0 + q) * n + row;
-    double2 bb = b[o];
-    r[o] = make_double2(bb.x - sr, bb.y - si);
-  }
-}
-
 // ratio[i*nrhs+q] = max|r| / max|b| over the vector
 __global__ __launch_bounds__(256) void ratio_inf(const double2* r, const double2* b, double* out, int n) {
   const size_t v = blockIdx.x;
@@ -172,12 +122,6 @@ hipError_t accum_c64(double2* x, const float2* d, size_t count, hipStream_t s) {
 }
 hipError_t zero_c128(double2* x, size_t count, hipStream_t s) {
   hipLaunchKernelGGL(fill_zero, grid1(count), dim3(256), 0, s, x, count);
-  return hipGetLastError();
-}
-hipError_t residual_z(const double2* A, const int* map, const double2* b, const double2* x, double2* r, int n,
-                      int nrhs, int nm, hipStream_t s) {
-  dim3 g((n + 3) / 4, nm, (nrhs + kRQ - 1) / kRQ);
-  hipLaunchKernelGGL(residual, g, dim3(256), 0, s, A, map, b, x, r, n, nrhs);
   return hipGetLastError();
 }
 hipError_t ratios(const double2* r, const double2* b, double* out, int n, int nvec, hipStream_t s) {
