@@ -27,12 +27,14 @@ template <> struct V2<float> { using T = float2; };
 
 constexpr int kBaseW = 8;      // strip width of the base panel
 constexpr int kPanelThreads = 1024;
-constexpr int kRowsPerThread = 8;  // n <= kPanelThreads * kRowsPerThread
+constexpr int kMaxRowsPerThread = 8;  // n <= kPanelThreads * kMaxRowsPerThread
 
 // ---------------------------------------------------------------------------
-// base panel: rows [c0, n) x columns [c0, c0 + w), w <= 8, pivoting in column
+// base panel: rows [c0, n) x columns [c0, c0 + w), w <= 8, pivoting in column.
+// Thread tid owns rows c0 + tid + i * kPanelThreads, i < kRowsPerThread; the
+// column loop is unrolled so the strip is indexed with constants.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int kRowsPerThread>
 __global__ __launch_bounds__(kPanelThreads) void base_panel(typename V2<R>::T* A, int32_t* ipiv,
                                                             int32_t* info, int n, long long stride,
                                                             int c0, int w) {
@@ -59,7 +61,9 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(typename V2<R>::T* A
       v[i][c] = (r < rows && c < w) ? M[(size_t)(c0 + r) * n + c0 + c] : z;
     }
   }
-  for (int j = 0; j < w; ++j) {
+#pragma unroll
+  for (int j = 0; j < kBaseW; ++j) {
+    if (j >= w) break;
     // pivot search over local rows >= j
     R best = -1;
     int bi = 0x7fffffff;
@@ -199,41 +203,146 @@ __global__ __launch_bounds__(256) void laswp(T* A, const int32_t* ipiv, int n, l
 }
 
 // ---------------------------------------------------------------------------
-// X <- L^{-1} X, L = unit lower A[k:k+h, k:k+h], X = A[k:k+h, cb:ce]
+// X <- L^{-1} X, L = unit lower A[k:k+h, k:k+h] (h <= 64), X = A[k:k+h, cb:ce]:
+// linv_block forms L^{-1} (identity-padded to 64 x 64) once per matrix, then
+// trsm_inv multiplies each 64-column tile of X by it on MFMA, in place (a
+// workgroup reads its whole tile into LDS before writing it back).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void trsm_lu(typename V2<R>::T* A, int n, long long stride, int k,
-                                               int h, int cb, int ce) {
+__global__ __launch_bounds__(64) void linv_block(const typename V2<R>::T* A, int n, long long stride, int k,
+                                                 int h, typename V2<R>::T* linv) {
   using T = typename V2<R>::T;
-  extern __shared__ char smem_raw[];
-  T* Ls = reinterpret_cast<T*>(smem_raw);  // [h][h]
-  T* M = A + (size_t)blockIdx.z * stride;
-  for (int e = threadIdx.x; e < h * h; e += 256) {
-    int i = e / h, j = e % h;
-    Ls[e] = M[(size_t)(k + i) * n + k + j];
+  __shared__ T Ls[64][65];
+  __shared__ T Y[64][65];
+  const T* M = A + (size_t)blockIdx.z * stride;
+  const int j = threadIdx.x;
+  for (int r = 0; r < 64; ++r) {
+    T z;
+    z.x = 0;
+    z.y = 0;
+    Ls[r][j] = (r < h && j < h) ? M[(size_t)(k + r) * n + k + j] : z;
   }
   __syncthreads();
-  int c = cb + blockIdx.x * 256 + threadIdx.x;
-  if (c >= ce) return;
-  constexpr int kMaxH = 64;
-  T x[kMaxH];
-#pragma unroll
-  for (int i = 0; i < kMaxH; ++i)
-    if (i < h) x[i] = M[(size_t)(k + i) * n + c];
-#pragma unroll
-  for (int i = 0; i < kMaxH; ++i) {
-    if (i >= h) break;
-    T s = x[i];
-#pragma unroll
-    for (int j = 0; j < kMaxH; ++j) {
-      if (j >= i) break;
-      T l = Ls[i * h + j];
-      s.x -= l.x * x[j].x - l.y * x[j].y;
-      s.y -= l.x * x[j].y + l.y * x[j].x;
-    }
-    x[i] = s;
-    M[(size_t)(k + i) * n + c] = s;
+  for (int r = 0; r < 64; ++r) {
+    T y;
+    y.x = r == j ? (R)1 : (R)0;
+    y.y = 0;
+    if (r > j && r < h)
+      for (int q = j; q < r; ++q) {
+        const T l = Ls[r][q], x = Y[q][j];
+        y.x -= l.x * x.x - l.y * x.y;
+        y.y -= l.x * x.y + l.y * x.x;
+      }
+    Y[r][j] = y;
   }
+  T* out = linv + (size_t)blockIdx.z * 64 * 64;
+  for (int r = 0; r < 64; ++r) out[r * 64 + j] = Y[r][j];
+}
+
+// In-panel TRSM (at most 64 columns right of a block of h = 4..64 rows):
+// 64 columns x 4 threads; thread t of a column keeps rows j = t (mod 4) in
+// registers and row i's dot product is split over the four threads.
+template <typename R, int H>
+__global__ __launch_bounds__(256) void trsm_small(typename V2<R>::T* A, int n, long long stride, int k, int cb,
+                                                  int ce) {
+  using T = typename V2<R>::T;
+  constexpr int Q = H / 4;
+  __shared__ T Ls[H][H + 1];
+  T* M = A + (size_t)blockIdx.z * stride;
+  for (int e = threadIdx.x; e < H * H; e += 256) {
+    const int i = e / H, j = e % H;
+    Ls[i][j] = M[(size_t)(k + i) * n + k + j];
+  }
+  __syncthreads();
+  const int t = threadIdx.x & 3;
+  const int c = cb + blockIdx.x * 64 + (threadIdx.x >> 2);
+  const bool ok = c < ce;
+  T x[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    T z;
+    z.x = 0;
+    z.y = 0;
+    x[q] = ok ? M[(size_t)(k + 4 * q + t) * n + c] : z;
+  }
+#pragma unroll
+  for (int i = 1; i < H; ++i) {
+    R sr = 0, si = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (4 * q + t < i) {
+        const T l = Ls[i][4 * q + t];
+        sr += l.x * x[q].x - l.y * x[q].y;
+        si += l.x * x[q].y + l.y * x[q].x;
+      }
+    sr += __shfl_xor(sr, 1);
+    si += __shfl_xor(si, 1);
+    sr += __shfl_xor(sr, 2);
+    si += __shfl_xor(si, 2);
+    if ((i & 3) == t) {
+      x[i >> 2].x -= sr;
+      x[i >> 2].y -= si;
+    }
+  }
+  if (ok)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) M[(size_t)(k + 4 * q + t) * n + c] = x[q];
+}
+
+template <typename R> struct Mfma;
+
+template <typename R>
+__global__ __launch_bounds__(256) void trsm_inv(typename V2<R>::T* A, int n, long long stride, int k, int h,
+                                                int cb, int ce, const typename V2<R>::T* linv) {
+  using T = typename V2<R>::T;
+  using C4 = typename Mfma<R>::C4;
+  __shared__ T Xs[64][65];  // [row][col]
+  T* M = A + (size_t)blockIdx.z * stride;
+  const T* Li = linv + (size_t)blockIdx.z * 64 * 64;
+  const int c0 = cb + blockIdx.x * 64;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    T z;
+    z.x = 0;
+    z.y = 0;
+    Xs[r][c] = (r < h && c0 + c < ce) ? M[(size_t)(k + r) * n + c0 + c] : z;
+  }
+  __syncthreads();
+  if (16 * wave >= h) return;
+  C4 cr[4], ci[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    cr[j] = C4{0, 0, 0, 0};
+    ci[j] = C4{0, 0, 0, 0};
+  }
+  const T* Lrow = Li + (size_t)(16 * wave + (lane & 15)) * 64 + (lane >> 4);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int kk = 4 * s + (lane >> 4);
+    const T a = Lrow[4 * s];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T bb = Xs[kk][16 * j + (lane & 15)];
+      cr[j] = Mfma<R>::op(a.x, bb.x, cr[j]);
+      cr[j] = Mfma<R>::op(-a.y, bb.y, cr[j]);
+      ci[j] = Mfma<R>::op(a.x, bb.y, ci[j]);
+      ci[j] = Mfma<R>::op(a.y, bb.x, ci[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * wave + Mfma<R>::row(lane, i);
+      const int c = c0 + 16 * j + (lane & 15);
+      if (r < h && c < ce) {
+        T v;
+        v.x = cr[j][i];
+        v.y = ci[j][i];
+        M[(size_t)(k + r) * n + c] = v;
+      }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -242,7 +351,6 @@ __global__ __launch_bounds__(256) void trsm_lu(typename V2<R>::T* A, int n, long
 // ---------------------------------------------------------------------------
 constexpr int kGT = 64, kGK = 16;
 
-template <typename R> struct Mfma;
 // Operand layout (both): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
 // Accumulator layout (measured on gfx950): column l % 16 in both; row
 // 4 * i + l / 16 for f64, 4 * (l / 16) + i for f32, i = register 0..3.
@@ -266,8 +374,10 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
                                                    int Mr, int c0, int Nc, int k0, int K) {
   using T = typename V2<R>::T;
   using C4 = typename Mfma<R>::C4;
-  __shared__ R As_re[kGK][kGT + 1], As_im[kGK][kGT + 1];  // [k][row]
-  __shared__ R Bs_re[kGK][kGT + 1], Bs_im[kGK][kGT + 1];  // [k][col]
+  // [k][row] / [k][col]; the row stride kGT + 16 puts the four k rows a
+  // wave reads at once in disjoint bank ranges
+  __shared__ R As_re[kGK][kGT + 16], As_im[kGK][kGT + 16];
+  __shared__ R Bs_re[kGK][kGT + 16], Bs_im[kGK][kGT + 16];
   T* M = A + (size_t)blockIdx.z * stride;
   const int tr = r0 + blockIdx.y * kGT;
   const int tc = c0 + blockIdx.x * kGT;
@@ -370,11 +480,25 @@ hipError_t swaps(typename V2<R>::T* A, const int32_t* ipiv, const LuBatch& b, in
 }
 
 template <typename R>
-hipError_t trsm(typename V2<R>::T* A, const LuBatch& b, int k, int h, int cb, int ce, hipStream_t s) {
+hipError_t trsm(typename V2<R>::T* A, const LuBatch& b, int k, int h, int cb, int ce, typename V2<R>::T* linv,
+                hipStream_t s) {
   if (ce <= cb || h <= 0) return hipSuccess;
-  dim3 g((ce - cb + 255) / 256, 1, b.nb);
-  size_t lds = sizeof(typename V2<R>::T) * (size_t)h * h;
-  hipLaunchKernelGGL(trsm_lu<R>, g, dim3(256), lds, s, A, b.n, b.stride, k, h, cb, ce);
+  if (h > 64) return hipErrorInvalidValue;
+  if (ce - cb <= 64) {  // inside a panel: register substitution, no inverse
+    dim3 g(1, 1, b.nb);
+    switch (h) {
+      case 4: hipLaunchKernelGGL((trsm_small<R, 4>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
+      case 8: hipLaunchKernelGGL((trsm_small<R, 8>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
+      case 16: hipLaunchKernelGGL((trsm_small<R, 16>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
+      case 32: hipLaunchKernelGGL((trsm_small<R, 32>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
+      case 64: hipLaunchKernelGGL((trsm_small<R, 64>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
+      default: return hipErrorInvalidValue;  // panel halves are powers of two
+    }
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(64), 0, s, A, b.n, b.stride, k, h, linv);
+  hipLaunchKernelGGL(trsm_inv<R>, dim3((ce - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, A, b.n, b.stride, k, h, cb,
+                     ce, linv);
   return hipGetLastError();
 }
 
@@ -387,18 +511,26 @@ hipError_t trsm(typename V2<R>::T* A, const LuBatch& b, int k, int h, int cb, in
 // Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
 template <typename R>
 hipError_t panel_rec(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& b, int c0, int w,
-                     hipStream_t s) {
+                     typename V2<R>::T* linv, hipStream_t s) {
   if (w <= kBaseW) {
-    hipLaunchKernelGGL(base_panel<R>, dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
-                       b.stride, c0, w);
+    const int rows = b.n - c0;  // the strip's rows, spread over the workgroup
+    if (rows <= 2 * kPanelThreads)
+      hipLaunchKernelGGL((base_panel<R, 2>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
+                         b.stride, c0, w);
+    else if (rows <= 4 * kPanelThreads)
+      hipLaunchKernelGGL((base_panel<R, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
+                         b.stride, c0, w);
+    else
+      hipLaunchKernelGGL((base_panel<R, 8>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
+                         b.stride, c0, w);
     return hipGetLastError();
   }
   int h = w / 2;
-  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0, h, s));
+  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0, h, linv, s));
   MSV_TRY(swaps<R>(A, ipiv, b, c0, c0 + h, c0 + h, c0 + w, s));
-  MSV_TRY(trsm<R>(A, b, c0, h, c0 + h, c0 + w, s));
+  MSV_TRY(trsm<R>(A, b, c0, h, c0 + h, c0 + w, linv, s));
   MSV_TRY(gemm<R>(A, b, c0 + h, b.n - c0 - h, c0 + h, w - h, c0, h, s));
-  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0 + h, w - h, s));
+  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0 + h, w - h, linv, s));
   // swaps of the right half also apply to the left half of the panel
   MSV_TRY(swaps<R>(A, ipiv, b, c0 + h, c0 + w, c0, c0 + h, s));
   return hipSuccess;
@@ -409,21 +541,22 @@ __global__ void zero_info(int32_t* info, int nb) {
 }
 
 template <typename R>
-hipError_t factor(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
+hipError_t factor(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& b, typename V2<R>::T* linv,
+                  hipStream_t s) {
   const int n = b.n;
-  if (n > kPanelThreads * kRowsPerThread) return hipErrorInvalidValue;
+  if (n > kPanelThreads * kMaxRowsPerThread) return hipErrorInvalidValue;
   hipLaunchKernelGGL(zero_info, dim3(1), dim3(256), 0, s, info, b.nb);
   MSV_TRY(hipGetLastError());
   const int NB = 128;
   for (int k = 0; k < n; k += NB) {
     int w = n - k < NB ? n - k : NB;
-    MSV_TRY(panel_rec<R>(A, ipiv, info, b, k, w, s));
+    MSV_TRY(panel_rec<R>(A, ipiv, info, b, k, w, linv, s));
     MSV_TRY(swaps<R>(A, ipiv, b, k, k + w, 0, k, s));
     MSV_TRY(swaps<R>(A, ipiv, b, k, k + w, k + w, n, s));
     // U12 = L11^{-1} A12 in blocks of 64 rows (TRSM register limit), then A22
     for (int kk = k; kk < k + w; kk += 64) {
       int h = k + w - kk < 64 ? k + w - kk : 64;
-      MSV_TRY(trsm<R>(A, b, kk, h, k + w, n, s));
+      MSV_TRY(trsm<R>(A, b, kk, h, k + w, n, linv, s));
       if (kk + h < k + w) MSV_TRY(gemm<R>(A, b, kk + h, k + w - kk - h, k + w, n - k - w, kk, h, s));
     }
     MSV_TRY(gemm<R>(A, b, k + w, n - k - w, k + w, n - k - w, k, w, s));
@@ -433,10 +566,10 @@ hipError_t factor(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBa
 
 }  // namespace
 
-hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
-  return factor<double>(A, ipiv, info, b, s);
+hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
+  return factor<double>(A, ipiv, info, b, static_cast<double2*>(work), s);
 }
-hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s) {
-  return factor<float>(A, ipiv, info, b, s);
+hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
+  return factor<float>(A, ipiv, info, b, static_cast<float2*>(work), s);
 }
 }  // namespace msv

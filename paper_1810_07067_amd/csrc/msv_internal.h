@@ -71,8 +71,9 @@ struct LuBatch {
   long long ld;    // leading dimension (= n)
   long long stride;  // elements between matrices
 };
-hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s);
-hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, hipStream_t s);
+// work: nb * 64 * 64 complex elements of the factor's precision
+hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
+hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 
 // Right-hand-side batches for the solves (trsv.hip): up to kVB vectors that
 // use factor `fac`; vector v is stored at element off[v] * n of the work

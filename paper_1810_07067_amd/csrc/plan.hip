@@ -43,6 +43,13 @@ struct msv_plan {
   int32_t* d_perm = nullptr;   // row permutation of each factor
   void* d_inv = nullptr;       // inverses of the 64 x 64 diagonal blocks of L and U
   size_t inv_bytes = 0;
+  void* d_luw = nullptr;       // LU workspace: one 64 x 64 block per matrix
+  size_t luw_bytes = 0;
+  // side streams for the factorization: groups of modes run concurrently so
+  // the latency-bound panel steps of one group overlap the GEMMs of another
+  static constexpr int kFacStreams = 1;
+  hipStream_t fac_st[kFacStreams] = {};
+  hipEvent_t fac_ev[kFacStreams + 1] = {};
   size_t ipiv_elems = 0;
   bool info_checked = false;
   // solve workspace
@@ -162,9 +169,13 @@ void msv_plan_destroy(msv_plan* p) {
   if (!p) return;
   void* bufs[] = {p->d_r, p->d_z, p->d_tr, p->d_tz, p->d_w, p->d_sqw, p->d_sup, p->d_lag_self,
                   p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
-                  p->d_info, p->d_perm, p->d_inv, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm, p->d_vb};
+                  p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm, p->d_vb};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  for (hipStream_t st : p->fac_st)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : p->fac_ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete p;
 }
 
@@ -501,6 +512,45 @@ msv_status msv_assemble(msv_plan* p, const msv_c128* d_kern, int32_t m_lo, int32
   return MSV_OK;
 }
 
+// Factor nb matrices (complex128 at A64 or complex64 at A32) in up to
+// kFacStreams contiguous groups on side streams, joined back into s.
+static hipError_t factor_groups(msv_plan* p, msv_c128* A64, float2* A32, int n, int nb, hipStream_t s) {
+  const int G = std::min(msv_plan::kFacStreams, nb);
+  if (G == 1) {
+    msv::LuBatch b{n, nb, n, (long long)n * n};
+    return A64 ? msv::lu_factor_z(reinterpret_cast<double2*>(A64), p->d_ipiv, p->d_info, b, p->d_luw, s)
+               : msv::lu_factor_c(A32, p->d_ipiv, p->d_info, b, p->d_luw, s);
+  }
+  for (int g = 0; g < G; ++g)
+    if (!p->fac_st[g]) {
+      hipError_t e = hipStreamCreateWithFlags(&p->fac_st[g], hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+  for (int g = 0; g <= G; ++g)
+    if (!p->fac_ev[g]) {
+      hipError_t e = hipEventCreateWithFlags(&p->fac_ev[g], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+  hipError_t e = hipEventRecord(p->fac_ev[G], s);
+  if (e != hipSuccess) return e;
+  const size_t nn = (size_t)n * n;
+  for (int g = 0; g < G; ++g) {
+    const int lo = g * nb / G, hi = (g + 1) * nb / G;
+    if ((e = hipStreamWaitEvent(p->fac_st[g], p->fac_ev[G], 0)) != hipSuccess) return e;
+    msv::LuBatch bg{n, hi - lo, n, (long long)nn};
+    if (A64)
+      e = msv::lu_factor_z(reinterpret_cast<double2*>(A64) + lo * nn, p->d_ipiv + (size_t)lo * n, p->d_info + lo, bg,
+                           static_cast<double2*>(p->d_luw) + (size_t)lo * 64 * 64, p->fac_st[g]);
+    else
+      e = msv::lu_factor_c(A32 + lo * nn, p->d_ipiv + (size_t)lo * n, p->d_info + lo, bg,
+                           static_cast<float2*>(p->d_luw) + (size_t)lo * 64 * 64, p->fac_st[g]);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(p->fac_ev[g], p->fac_st[g])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, p->fac_ev[g], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, void* stream) {
   if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
   if (!d_A) return fail(p, MSV_EINVAL, "null matrix buffer");
@@ -522,9 +572,16 @@ msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, vo
       return fail(p, MSV_ENOMEM, "pivot allocation failed");
     p->ipiv_elems = (size_t)nb * n;
   }
-  msv::LuBatch b{n, nb, n, (long long)nn};
+  const size_t luw_bytes = (size_t)nb * 64 * 64 * 16;
+  if (luw_bytes > p->luw_bytes) {
+    if (p->d_luw) (void)hipFree(p->d_luw);
+    p->d_luw = nullptr;
+    p->luw_bytes = 0;
+    if (hipMalloc(&p->d_luw, luw_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "LU workspace allocation failed");
+    p->luw_bytes = luw_bytes;
+  }
   if (p->precision == 0) {
-    MSV_HIP(p, msv::lu_factor_z(reinterpret_cast<double2*>(d_A), p->d_ipiv, p->d_info, b, s));
+    MSV_HIP(p, factor_groups(p, d_A, nullptr, n, nb, s));
   } else {
     if ((size_t)nb * nn > p->fac32_elems) {
       if (p->d_fac32) (void)hipFree(p->d_fac32);
@@ -535,7 +592,7 @@ msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, vo
       p->fac32_elems = (size_t)nb * nn;
     }
     MSV_HIP(p, msv::conv_c64(reinterpret_cast<const double2*>(d_A), p->d_fac32, (size_t)nb * nn, s));
-    MSV_HIP(p, msv::lu_factor_c(p->d_fac32, p->d_ipiv, p->d_info, b, s));
+    MSV_HIP(p, factor_groups(p, nullptr, p->d_fac32, n, nb, s));
   }
   MSV_HIP(p, msv::lu_perm(p->d_ipiv, p->d_perm, n, nb, s));
   const size_t inv_bytes = (size_t)nb * ((n + 63) / 64) * 2 * 64 * 64 * (p->precision == 0 ? 16 : 8);
