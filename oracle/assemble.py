@@ -10,7 +10,10 @@ Equations per target node i (rows 4i..4i+3):
                                              - i w (eps0 N^{k0} - eps1 N^{k1}) M
 
 (eq. mullerrep; the magnetic equation is placed first so that the identity
-terms sit on the diagonal).  N and K act on a tangential density a = (a^1, a^2)
+terms sit on the diagonal).  The tabulated kernels are g^{k0} and g^{k0} - g^{k1}
+(with their derivatives), so mu0 N^{k0} - mu1 N^{k1} is formed as
+(mu0 - mu1) N^{k0} + mu1 (N^{k0} - N^{k1}).  N and K act on a tangential
+density a = (a^1, a^2)
 through the coefficients of Lemma 1 (eqs. equc1-equc3),
 
   c^1 = int a^1 r r' g^2 - i int a^2 r g^3,   c^2 = i int a^1 r r' g^3 + int a^2 r g^2,
@@ -30,8 +33,9 @@ directly), and the mode-m expansions of Section 3:
 (target quantities r = r_t, r' = r'_t, z' = z'_t).  The e_theta rows are the
 negatives of the printed ones: n x V = V_theta t - (r' V_r + z' V_z) e_theta for
 n = z' e_r - r' e_z, which the printed expansions do not follow.  In K^{k0}-K^{k1}
-the k^2 c terms use each wavenumber's own kernels; every other term uses the
-difference g^{k0} - g^{k1} and the tabulated difference of second derivatives.
+the k^2 c terms use each wavenumber's own kernels, written
+(k0^2 - k1^2) c(g^{k0}) + k1^2 c(g^{k0} - g^{k1}); every other term uses the
+difference g^{k0} - g^{k1} and the tabulated differences of derivatives.
 
 Quadrature (eq. disequ, eq_nyslike2): far panels use w_j K(x_i, x_j); the
 target's own panel and its neighbours use the support nodes.  Finally the L^2
@@ -78,9 +82,9 @@ def blocks(tab_m, m, rt, trt, tzt, rs, trs, tzs, k0, k1, omega, eps0, mu0, eps1,
         return out
 
     N0 = N_op(0)
-    N1 = N_op(3)
-    # difference family
-    D = G1[0:3] - G1[3:6], G2[0:3] - G2[3:6], G3[0:3] - G3[3:6]
+    dN = N_op(3)  # N^{k0} - N^{k1}: N is linear in the kernel family
+    # difference family (tabulated directly)
+    D = G1[3:6], G2[3:6], G3[3:6]
 
     def cd(i):
         g1, g2, g3 = D[0][i], D[1][i], D[2][i]
@@ -102,25 +106,27 @@ def blocks(tab_m, m, rt, trt, tzt, rs, trs, tzs, k0, k1, omega, eps0, mu0, eps1,
     rz1, rz3 = c2nd(7)
     zz1, zz3 = c2nd(8)
     k0c = cvals(0)
-    k1c = cvals(3)
+    dkc = cvals(3)  # c-values of g^{k0} - g^{k1}
     K = np.zeros_like(N0)
+    kd2 = k0 ** 2 - k1 ** 2
     for b in range(2):
-        Kt = (k0 ** 2 * k0c[1][b] - k1 ** 2 * k1c[1][b]) + (im / rt ** 2) * c1[b] \
+        # k0^2 c(g^{k0}) - k1^2 c(g^{k1}) = (k0^2 - k1^2) c(g^{k0}) + k1^2 c(g^{k0} - g^{k1})
+        Kt = (kd2 * k0c[1][b] + k1 ** 2 * dkc[1][b]) + (im / rt ** 2) * c1[b] \
             + (im / rt) * r1[b] - (m * m / rt ** 2) * c2[b] + (im / rt) * z3[b]
         dzD = (1 / rt) * z1[b] + rz1[b] + (im / rt) * z2[b] + zz3[b]
         drD = -c1[b] / rt ** 2 + (1 / rt) * r1[b] + rr1[b] - (im / rt ** 2) * c2[b] \
             + (im / rt) * r2[b] + rz3[b]
-        kk = k0 ** 2 * (tzt * k0c[2][b] + trt * k0c[0][b]) \
-            - k1 ** 2 * (tzt * k1c[2][b] + trt * k1c[0][b])
+        kk = kd2 * (tzt * k0c[2][b] + trt * k0c[0][b]) + k1 ** 2 * (tzt * dkc[2][b] + trt * dkc[0][b])
         Kth = -(kk + tzt * dzD + trt * drD)
         K[0, b] = Kt
         K[1, b] = Kth
     iw = 1j * omega
     B = np.zeros((4, 4) + K.shape[2:], dtype=complex)
-    B[0:2, 0:2] = -iw * (mu0 * N0 - mu1 * N1)
+    # mu0 N^{k0} - mu1 N^{k1} = (mu0 - mu1) N^{k0} + mu1 (N^{k0} - N^{k1})
+    B[0:2, 0:2] = -iw * ((mu0 - mu1) * N0 + mu1 * dN)
     B[0:2, 2:4] = -K
     B[2:4, 0:2] = K
-    B[2:4, 2:4] = -iw * (eps0 * N0 - eps1 * N1)
+    B[2:4, 2:4] = -iw * ((eps0 - eps1) * N0 + eps1 * dN)
     return B
 
 

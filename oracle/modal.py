@@ -4,14 +4,18 @@ For a target (r_t, z_t) and a source (r_s, z_s) on the generating curve the
 nine stored quantities per azimuthal mode m are (eq. green11 and derivatives
 with respect to the target coordinates):
 
-    0 g^{k0}_m   1 d_r g^{k0}_m   2 d_z g^{k0}_m
-    3 g^{k1}_m   4 d_r g^{k1}_m   5 d_z g^{k1}_m
+    0 g^{k0}_m           1 d_r g^{k0}_m           2 d_z g^{k0}_m
+    3 (g^{k0}-g^{k1})_m  4 d_r (g^{k0}-g^{k1})_m  5 d_z (g^{k0}-g^{k1})_m
     6 d_rr (g^{k0}-g^{k1})_m   7 d_rz (g^{k0}-g^{k1})_m   8 d_zz (g^{k0}-g^{k1})_m
 
 with g^k_m = int_0^{2pi} e^{ik rho}/(4 pi rho) e^{-i m phi} dphi and rho^2 =
 d^2 + 4 r_t r_s sin^2(phi/2).  Only the k0 - k1 difference of the second
 derivatives enters the Mueller system (Section 4.3), which removes their
-hypersingularity.
+hypersingularity.  The interior family is stored as the difference too:
+the K operators enter only as K^{k0} - K^{k1}, N^{k1} = N^{k0} - (N^{k0} -
+N^{k1}), and at the support nodes closest to a target d_r g and d_z g reach
+1e9, so forming the difference from two tabulated values would keep about
+7 digits of it; formed from the integrands below it keeps full precision.
 
 Kernel splitting (Sections 4.1-4.3).  Every integrand is written as
 sum(analytic factor x X) + analytic part, with X in {1/rho, 1/rho^3}:
@@ -21,9 +25,16 @@ sum(analytic factor x X) + analytic part, with X in {1/rho, 1/rho^3}:
     (3 - 3ik rho - k^2 rho^2) e^{ik rho} = U_k + i V_k,
         U = 3 cos x - x^2 cos x + 3 x sin x,  V = 3 sin x - x^2 sin x - 3 x cos x
 
-(x = k rho).  Y/rho^3, V/rho^5, (U_{k0}-U_{k1})/rho^2 and (W_{k0}-W_{k1})/rho^2
-are analytic in phi, evaluated with Taylor series for small |x| (the paper's
-small-rho Taylor remark in Section 4.1).  The factor r_d = r_t - r_s cos(phi)
+(x = k rho).  Y/rho^3, V/rho^5, (U_{k0}-U_{k1})/rho^2, (W_{k0}-W_{k1})/rho^2 and
+(cos(k0 rho) - cos(k1 rho))/rho^2 are analytic in phi, evaluated with Taylor
+series for small |x| (the paper's small-rho Taylor remark in Section 4.1).
+The differences of the first family are
+
+    (g^{k0} - g^{k1}) 4 pi  = rho^2 Cd X1 + i (k0 sinc(k0 rho) - k1 sinc(k1 rho))
+    d_r (g^{k0} - g^{k1}) 4 pi = r_d (-Wd X1 + i Y3d),   d_z: z_t - z_s for r_d
+
+with Cd = k0^2 Ct(k0 rho) - k1^2 Ct(k1 rho), Ct(x) = (cos x - 1)/x^2,
+Wd = k0^2 Wt(k0 rho) - k1^2 Wt(k1 rho), Y3d = k0^3 Y3(k0 rho) - k1^3 Y3(k1 rho).  The factor r_d = r_t - r_s cos(phi)
 of the r-derivatives is written r_d = (rho^2 + a) / (2 r_t) with
 a = r_t^2 - r_s^2 - (z_t - z_s)^2 so that no smooth factor carries a cancelling
 r_d next to a singular X:
@@ -100,6 +111,7 @@ _C_Y3 = [(-1) ** (i + 1) * 2 * (i + 1) / _fact[2 * i + 3] for i in range(_NSER)]
 _C_WT = [(-1) ** i * (2 * i + 1) / _fact[2 * i + 2] for i in range(_NSER)]
 _C_UT = [(-1) ** (i + 1) * (2 * i + 1) * (2 * i - 1) / _fact[2 * i + 2] for i in range(_NSER)]
 _C_V5 = [(-1) ** i * 4 * (i + 2) * (i + 1) / _fact[2 * i + 5] for i in range(_NSER)]
+_C_CT = [(-1) ** (i + 1) / _fact[2 * i + 2] for i in range(_NSER)]
 
 
 def _horner(coef, y):
@@ -112,7 +124,7 @@ def _horner(coef, y):
 def analytic_factors(x):
     """For x = k rho (real or complex array):
     cos x, sinc x, W = cos x + x sin x, Y3 = Y/x^3, Wt = (W-1)/x^2,
-    Ut = (U-3)/x^2, V5 = V/x^5."""
+    Ut = (U-3)/x^2, V5 = V/x^5, Ct = (cos x - 1)/x^2."""
     x = np.asarray(x)
     c = np.cos(x)
     s = np.sin(x)
@@ -124,8 +136,9 @@ def analytic_factors(x):
         Wt = np.where(small, _horner(_C_WT, y), (c + x * s - 1.0) / y)
         Ut = np.where(small, _horner(_C_UT, y), (3.0 * c - y * c + 3.0 * x * s - 3.0) / y)
         V5 = np.where(small, _horner(_C_V5, y), (3.0 * s - y * s - 3.0 * x * c) / (y * y * x))
+        Ct = np.where(small, _horner(_C_CT, y), (c - 1.0) / y)
     W = 1.0 + y * Wt
-    return c, sinc, W, Y3, Wt, Ut, V5
+    return c, sinc, W, Y3, Wt, Ut, V5, Ct
 
 
 def sample_types(rt, dr, dz, cosphi, rho2, X1, X3, k0, k1, exact=False):
@@ -149,21 +162,21 @@ def sample_types(rt, dr, dz, cosphi, rho2, X1, X3, k0, k1, exact=False):
     else:
         Xa = (X1 + a * X3) / (2.0 * rt)
         Xaa = (rho2 * X1 + 2.0 * a * X1 + a * a * X3) / (4.0 * rt * rt)
-    out = []
-    fac = {}
-    for key, k in (("0", k0), ("1", k1)):
-        c, sinc, W, Y3, Wt, Ut, V5 = analytic_factors(k * rho)
-        fac[key] = (c, sinc, W, Y3, Wt, Ut, V5, k)
-        g = c * X1 + 1j * k * sinc
-        dz = zd * (-W * X3 + 1j * k ** 3 * Y3)
-        dr = -W * Xa + 1j * k ** 3 * Y3 * rd
-        out += [g, dr, dz]
-    c0, _, _, Y30, Wt0, Ut0, V50, k0_ = fac["0"]
-    c1, _, _, Y31, Wt1, Ut1, V51, k1_ = fac["1"]
+    c0, sinc0, W0, Y30, Wt0, Ut0, V50, Ct0 = analytic_factors(k0 * rho)
+    c1, sinc1, W1, Y31, Wt1, Ut1, V51, Ct1 = analytic_factors(k1 * rho)
+    k0_, k1_ = k0, k1
+    g0 = c0 * X1 + 1j * k0 * sinc0
+    dr0 = -W0 * Xa + 1j * k0 ** 3 * Y30 * rd
+    dz0 = zd * (-W0 * X3 + 1j * k0 ** 3 * Y30)
     Pd = k0_ ** 2 * Ut0 - k1_ ** 2 * Ut1
     Wd = k0_ ** 2 * Wt0 - k1_ ** 2 * Wt1
     V5d = k0_ ** 5 * V50 - k1_ ** 5 * V51
     Y3d = k0_ ** 3 * Y30 - k1_ ** 3 * Y31
+    Cd = k0_ ** 2 * Ct0 - k1_ ** 2 * Ct1
+    Sd = k0_ * sinc0 - k1_ * sinc1
+    dg = rho2 * Cd * X1 + 1j * Sd
+    F1d = -Wd * X1 + 1j * Y3d
+    out = [g0, dr0, dz0, dg, rd * F1d, zd * F1d]
     rr = Pd * Xaa - Wd * X1 + 1j * (V5d * rd * rd + Y3d)
     rz = Pd * zd * Xa + 1j * V5d * rd * zd
     zz = Pd * zd * zd * X3 - Wd * X1 + 1j * (V5d * zd * zd + Y3d)
@@ -246,18 +259,17 @@ def direct_trapezoid(rt, zt, rs, zs, k0, k1, M, Lt):
     rho = np.sqrt(rho2)
     rd = rt - rs * cp
     zd = zt - zs
-    out = []
-    hess = {}
+    f = {}
     for k in (k0, k1):
         E = np.exp(1j * k * rho)
-        g = E / rho
         F1 = (1j * k * rho - 1) * E / (rho * rho2)
-        out += [g, rd * F1, zd * F1]
         G = E * (3 - 3j * k * rho - k * k * rho2) / (rho2 * rho2 * rho)
-        hess[k] = (G, F1)
-    G = hess[k0][0] - hess[k1][0]
-    H = hess[k0][1] - hess[k1][1]
-    out += [rd * rd * G + H, rd * zd * G, zd * zd * G + H]
+        f[k] = (E / rho, F1, G)
+    g0, F10, _ = f[k0]
+    dg = f[k0][0] - f[k1][0]
+    H = f[k0][1] - f[k1][1]
+    G = f[k0][2] - f[k1][2]
+    out = [g0, rd * F10, zd * F10, dg, rd * H, zd * H, rd * rd * G + H, rd * zd * G, zd * zd * G + H]
     K = np.stack([np.broadcast_to(o, rho.shape) for o in out])
     F = np.fft.fft(K, axis=-1) * (2 * np.pi / Lt) / (4 * np.pi)
     return F[..., : M + 2].transpose(1, 0, 2)

@@ -7,6 +7,10 @@
 //   rows 0,1:  -i w (mu0 N^{k0} - mu1 N^{k1}) on J,   -(K^{k0} - K^{k1}) on M
 //   rows 2,3:   (K^{k0} - K^{k1}) on J,   -i w (eps0 N^{k0} - eps1 N^{k1}) on M
 //
+// The table holds g^{k0} and g^{k0} - g^{k1} (with derivatives), so
+// mu N^{k0} - mu' N^{k1} = (mu - mu') N^{k0} + mu' (N^{k0} - N^{k1}) and the
+// k^2 terms of K are (k0^2 - k1^2) c(g^{k0}) + k1^2 c(g^{k0} - g^{k1}).
+//
 // with N and K in mode m from the coefficients c^1, c^2, c^3 of Lemma 1 and the
 // expansions of Section 3 (e_theta components taken with the sign that
 // n x V = V_theta t - (r' V_r + z' V_z) e_theta gives for n = z' e_r - r' e_z).
@@ -45,21 +49,21 @@ __device__ __forceinline__ cd ld(const double2* p) {
 __device__ __forceinline__ cd mul_i(cd a) { return mk(-a.im, a.re); }  // i a
 
 struct Consts {
-  cd k02, k12;    // k0^2, k1^2
-  cd cmu0, cmu1;  // -i w mu0, -i w mu1
-  cd ceps0, ceps1;
+  cd k12, kd2;      // k1^2, k0^2 - k1^2
+  cd cmu01, cmu1;   // -i w (mu0 - mu1), -i w mu1
+  cd ceps01, ceps1;
   cd jmu, jeps;   // (i w/2)(mu0+mu1), (i w/2)(eps0+eps1)
 };
 
 __device__ Consts make_consts(const AsmParams& P) {
   Consts c;
-  c.k02 = mk(P.k0 * P.k0, 0);
   cd k1 = mk(P.k1r, P.k1i);
   c.k12 = k1 * k1;
+  c.kd2 = mk(P.k0 * P.k0, 0) - c.k12;
   cd miw = mk(0, -P.omega);
-  c.cmu0 = miw * mk(P.mu0r, P.mu0i);
+  c.cmu01 = miw * mk(P.mu0r - P.mu1r, P.mu0i - P.mu1i);
   c.cmu1 = miw * mk(P.mu1r, P.mu1i);
-  c.ceps0 = miw * mk(P.eps0r, P.eps0i);
+  c.ceps01 = miw * mk(P.eps0r - P.eps1r, P.eps0i - P.eps1i);
   c.ceps1 = miw * mk(P.eps1r, P.eps1i);
   cd hiw = mk(0, 0.5 * P.omega);
   c.jmu = hiw * mk(P.mu0r + P.mu1r, P.mu0i + P.mu1i);
@@ -114,31 +118,23 @@ __device__ void block4(const cd T[3][kTypes], int m, double rt, double trt, doub
       N[kk][1][be] = -inner;
     }
   }
-  // K^{k0} - K^{k1}
-  cd D1[3], D2[3], D3[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    D1[i] = G1[i] - G1[i + 3];
-    D2[i] = G2[i] - G2[i + 3];
-    D3[i] = G3[i] - G3[i + 3];
-  }
-  Cv d = cvals(D1[0], D2[0], D3[0], rs, trs, tzs);
-  Cv dr = cvals(D1[1], D2[1], D3[1], rs, trs, tzs);
-  Cv dz = cvals(D1[2], D2[2], D3[2], rs, trs, tzs);
+  // K^{k0} - K^{k1} from the difference family (types 3..5)
+  Cv d = cvals(G1[3], G2[3], G3[3], rs, trs, tzs);
+  Cv dr = cvals(G1[4], G2[4], G3[4], rs, trs, tzs);
+  Cv dz = cvals(G1[5], G2[5], G3[5], rs, trs, tzs);
   Cv rr = cvals(G1[6], G2[6], G3[6], rs, trs, tzs);
   Cv rz = cvals(G1[7], G2[7], G3[7], rs, trs, tzs);
   Cv zz = cvals(G1[8], G2[8], G3[8], rs, trs, tzs);
   Cv g0 = cvals(G1[0], G2[0], G3[0], rs, trs, tzs);
-  Cv g1 = cvals(G1[3], G2[3], G3[3], rs, trs, tzs);
   cd K[2][2];
 #pragma unroll
   for (int be = 0; be < 2; ++be) {
-    cd Kt = C.k02 * g0.c2[be] - C.k12 * g1.c2[be] + im_r2 * d.c1[be] + im_r * dr.c1[be] -
+    cd Kt = C.kd2 * g0.c2[be] + C.k12 * d.c2[be] + im_r2 * d.c1[be] + im_r * dr.c1[be] -
             m2_r2 * d.c2[be] + im_r * dz.c3[be];
     cd dzD = irt * dz.c1[be] + rz.c1[be] + im_r * dz.c2[be] + zz.c3[be];
     cd drD = -(irt * irt) * d.c1[be] + irt * dr.c1[be] + rr.c1[be] - im_r2 * d.c2[be] +
              im_r * dr.c2[be] + rz.c3[be];
-    cd kk = C.k02 * (tzt * g0.c3[be] + trt * g0.c1[be]) - C.k12 * (tzt * g1.c3[be] + trt * g1.c1[be]);
+    cd kk = C.kd2 * (tzt * g0.c3[be] + trt * g0.c1[be]) + C.k12 * (tzt * d.c3[be] + trt * d.c1[be]);
     K[0][be] = Kt;
     K[1][be] = -(kk + tzt * dzD + trt * drD);
   }
@@ -146,10 +142,11 @@ __device__ void block4(const cd T[3][kTypes], int m, double rt, double trt, doub
   for (int al = 0; al < 2; ++al)
 #pragma unroll
     for (int be = 0; be < 2; ++be) {
-      B[al][be] = C.cmu0 * N[0][al][be] - C.cmu1 * N[1][al][be];
+      // N[0] = N^{k0}, N[1] = N^{k0} - N^{k1}
+      B[al][be] = C.cmu01 * N[0][al][be] + C.cmu1 * N[1][al][be];
       B[al][2 + be] = -K[al][be];
       B[2 + al][be] = K[al][be];
-      B[2 + al][2 + be] = C.ceps0 * N[0][al][be] - C.ceps1 * N[1][al][be];
+      B[2 + al][2 + be] = C.ceps01 * N[0][al][be] + C.ceps1 * N[1][al][be];
     }
 }
 

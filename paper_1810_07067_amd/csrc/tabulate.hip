@@ -29,7 +29,7 @@ constexpr int kSeq = 2 * kTypes;  // 18 real sequences
 constexpr int kNSer = 20;
 
 struct SeriesCoef {
-  double sinc[kNSer], y3[kNSer], wt[kNSer], ut[kNSer], v5[kNSer];
+  double sinc[kNSer], y3[kNSer], wt[kNSer], ut[kNSer], v5[kNSer], ct[kNSer];
 };
 
 constexpr double cfact(int n) {
@@ -42,7 +42,7 @@ constexpr SeriesCoef make_coef() {
   // Taylor coefficients in y = x^2 of
   //   sinc x, Y3 = (x cos x - sin x)/x^3, Wt = (cos x + x sin x - 1)/x^2,
   //   Ut = (3 cos x - x^2 cos x + 3 x sin x - 3)/x^2,
-  //   V5 = (3 sin x - x^2 sin x - 3 x cos x)/x^5.
+  //   V5 = (3 sin x - x^2 sin x - 3 x cos x)/x^5, Ct = (cos x - 1)/x^2.
   SeriesCoef c{};
   for (int i = 0; i < kNSer; ++i) {
     double sg = (i % 2 == 0) ? 1.0 : -1.0;
@@ -51,6 +51,7 @@ constexpr SeriesCoef make_coef() {
     c.wt[i] = sg * (2.0 * i + 1) / cfact(2 * i + 2);
     c.ut[i] = -sg * (2.0 * i + 1) * (2.0 * i - 1) / cfact(2 * i + 2);
     c.v5[i] = sg * 4.0 * (i + 2) * (i + 1) / cfact(2 * i + 5);
+    c.ct[i] = -sg / cfact(2 * i + 2);
   }
   return c;
 }
@@ -74,10 +75,10 @@ __device__ __forceinline__ cd cinv(cd a) {
 
 // Analytic factors of x = k rho (Section 4; small-rho Taylor branch).
 struct FacR {
-  double c, sinc, W, Y3, Wt, Ut, V5;
+  double c, sinc, W, Y3, Wt, Ut, V5, Ct;
 };
 struct FacC {
-  cd c, sinc, W, Y3, Wt, Ut, V5;
+  cd c, sinc, W, Y3, Wt, Ut, V5, Ct;
 };
 
 __device__ __forceinline__ FacR factors(double x) {
@@ -88,7 +89,7 @@ __device__ __forceinline__ FacR factors(double x) {
   f.c = c;
   if (fabs(x) <= 2.0) {
     double a0 = kCoef.sinc[kNSer - 1], a1 = kCoef.y3[kNSer - 1], a2 = kCoef.wt[kNSer - 1];
-    double a3 = kCoef.ut[kNSer - 1], a4 = kCoef.v5[kNSer - 1];
+    double a3 = kCoef.ut[kNSer - 1], a4 = kCoef.v5[kNSer - 1], a5 = kCoef.ct[kNSer - 1];
 #pragma unroll
     for (int i = kNSer - 2; i >= 0; --i) {
       a0 = fma(a0, y, kCoef.sinc[i]);
@@ -96,12 +97,14 @@ __device__ __forceinline__ FacR factors(double x) {
       a2 = fma(a2, y, kCoef.wt[i]);
       a3 = fma(a3, y, kCoef.ut[i]);
       a4 = fma(a4, y, kCoef.v5[i]);
+      a5 = fma(a5, y, kCoef.ct[i]);
     }
     f.sinc = a0;
     f.Y3 = a1;
     f.Wt = a2;
     f.Ut = a3;
     f.V5 = a4;
+    f.Ct = a5;
   } else {
     double ix = 1.0 / x;
     double iy = ix * ix;
@@ -110,6 +113,7 @@ __device__ __forceinline__ FacR factors(double x) {
     f.Wt = (c + x * s - 1.0) * iy;
     f.Ut = (3.0 * c - y * c + 3.0 * x * s - 3.0) * iy;
     f.V5 = (3.0 * s - y * s - 3.0 * x * c) * iy * iy * ix;
+    f.Ct = (c - 1.0) * iy;
   }
   f.W = 1.0 + y * f.Wt;
   return f;
@@ -127,7 +131,7 @@ __device__ __forceinline__ FacC factors(cd x) {
   if (x.re * x.re + x.im * x.im <= 4.0) {
     cd a0 = mk(kCoef.sinc[kNSer - 1], 0), a1 = mk(kCoef.y3[kNSer - 1], 0);
     cd a2 = mk(kCoef.wt[kNSer - 1], 0), a3 = mk(kCoef.ut[kNSer - 1], 0);
-    cd a4 = mk(kCoef.v5[kNSer - 1], 0);
+    cd a4 = mk(kCoef.v5[kNSer - 1], 0), a5 = mk(kCoef.ct[kNSer - 1], 0);
 #pragma unroll
     for (int i = kNSer - 2; i >= 0; --i) {
       a0 = a0 * y + mk(kCoef.sinc[i], 0);
@@ -135,12 +139,14 @@ __device__ __forceinline__ FacC factors(cd x) {
       a2 = a2 * y + mk(kCoef.wt[i], 0);
       a3 = a3 * y + mk(kCoef.ut[i], 0);
       a4 = a4 * y + mk(kCoef.v5[i], 0);
+      a5 = a5 * y + mk(kCoef.ct[i], 0);
     }
     f.sinc = a0;
     f.Y3 = a1;
     f.Wt = a2;
     f.Ut = a3;
     f.V5 = a4;
+    f.Ct = a5;
   } else {
     cd ix = cinv(x);
     cd iy = ix * ix;
@@ -150,6 +156,7 @@ __device__ __forceinline__ FacC factors(cd x) {
     f.Wt = (c + xs - mk(1.0, 0)) * iy;
     f.Ut = (3.0 * c - yc + 3.0 * xs - mk(3.0, 0)) * iy;
     f.V5 = (3.0 * s - ys - 3.0 * xc) * iy * iy * ix;
+    f.Ct = (c - mk(1.0, 0)) * iy;
   }
   f.W = mk(1.0, 0) + y * f.Wt;
   return f;
@@ -199,38 +206,38 @@ __device__ __forceinline__ void sample(const Pair& g, double s2, double cphi, do
   o[3] = k03 * f0.Y3 * rd;
   o[4] = -zd * f0.W * X3;
   o[5] = zd * k03 * f0.Y3;
-  cd P, Wd, V5d, Y3d;
+  // interior family as k0 - k1 differences:
+  //   dg = rho^2 Cd X1 + i Sd,  d_r dg = r_d F,  d_z dg = z_d F,  F = -Wd X1 + i Y3d
+  cd P, Wd, V5d, Y3d, Cd, Sd;
   if (!K1C) {
     double k1r = k1.re;
     FacR f1 = factors(k1r * rho);
     double k12 = k1r * k1r, k13 = k12 * k1r, k15 = k13 * k12;
-    o[6] = f1.c * X1;
-    o[7] = k1r * f1.sinc;
-    o[8] = -f1.W * Xa;
-    o[9] = k13 * f1.Y3 * rd;
-    o[10] = -zd * f1.W * X3;
-    o[11] = zd * k13 * f1.Y3;
     P = mk(k02 * f0.Ut - k12 * f1.Ut, 0);
     Wd = mk(k02 * f0.Wt - k12 * f1.Wt, 0);
     V5d = mk(k05 * f0.V5 - k15 * f1.V5, 0);
     Y3d = mk(k03 * f0.Y3 - k13 * f1.Y3, 0);
+    Cd = mk(k02 * f0.Ct - k12 * f1.Ct, 0);
+    Sd = mk(k0 * f0.sinc - k1r * f1.sinc, 0);
   } else {
     FacC f1 = factors(rho * k1);
     cd k12 = k1 * k1, k13 = k12 * k1, k15 = k13 * k12;
-    cd g1 = X1 * f1.c + mk(0, 1) * (k1 * f1.sinc);
-    cd ky = k13 * f1.Y3;
-    cd dr1 = mk(0, 1) * (rd * ky) - Xa * f1.W;
-    cd dz1 = zd * (mk(0, 1) * ky - X3 * f1.W);
-    o[6] = g1.re;
-    o[7] = g1.im;
-    o[8] = dr1.re;
-    o[9] = dr1.im;
-    o[10] = dz1.re;
-    o[11] = dz1.im;
     P = mk(k02 * f0.Ut, 0) - k12 * f1.Ut;
     Wd = mk(k02 * f0.Wt, 0) - k12 * f1.Wt;
     V5d = mk(k05 * f0.V5, 0) - k15 * f1.V5;
-    Y3d = mk(k03 * f0.Y3, 0) - ky;
+    Y3d = mk(k03 * f0.Y3, 0) - k13 * f1.Y3;
+    Cd = mk(k02 * f0.Ct, 0) - k12 * f1.Ct;
+    Sd = mk(k0 * f0.sinc, 0) - k1 * f1.sinc;
+  }
+  {
+    const cd dg = (rho2 * X1) * Cd + mk(-Sd.im, Sd.re);
+    const cd F = mk(-Y3d.im - X1 * Wd.re, Y3d.re - X1 * Wd.im);
+    o[6] = dg.re;
+    o[7] = dg.im;
+    o[8] = rd * F.re;
+    o[9] = rd * F.im;
+    o[10] = zd * F.re;
+    o[11] = zd * F.im;
   }
   // i * (V5d rd^2 + Y3d) etc.
   cd t_rr = V5d * mk(rd * rd, 0) + Y3d;

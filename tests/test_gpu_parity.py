@@ -20,9 +20,14 @@ end:
                   dense solve: 1e-10 relative (max norm).
   end to end      far fields and surface currents (the latter in the L2 norm
                   of the discretization, weights sqrt(w_j), Section 6), each
-                  to max(1e-10, 16 * sens) relative, sens being the oracle's
-                  own change of that output under the same ulp perturbation
-                  of the table.
+                  to max(1e-10, 4 * sens) relative.  sens is the oracle's own
+                  change of that output when every table entry is scaled by
+                  an independent 1 + 1e-14 u: both implementations evaluate
+                  the kernels to 0.5e-14 .. 1.5e-14 of a 30-digit quadrature
+                  (the derivative kernels at near-singular support nodes reach
+                  1e9), and for bodies with mu1 != mu0 the terms
+                  (mu0 - mu1) N^{k0}, (eps0 - eps1) N^{k0} carry those
+                  differences to the far field at a few 1e-10.
 """
 import numpy as np
 import pytest
@@ -63,9 +68,9 @@ def l2w(curve):
     return np.sqrt(np.repeat(geometry.gl_weights(curve), 4))
 
 
-def ulp_perturbed(tab, seed):
+def perturbed(tab, seed, rel):
     rng = np.random.default_rng(seed)
-    return tab * (1.0 + 2.0 ** -53 * rng.uniform(-1.0, 1.0, tab.shape))
+    return tab * (1.0 + rel * rng.uniform(-1.0, 1.0, tab.shape))
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -75,13 +80,14 @@ def case(request):
     sup, kp = oracle_setup(curve, k0, eps1, M, L, mu1=mu1)
     tab = oracle_table(curve, sup, kp)
     mats = np.array([oracle_matrix(curve, sup, tab, m, k0, kp.k1, eps1, mu1) for m in range(M + 1)])
-    tabp = ulp_perturbed(tab, 11)
-    matsp = np.array([oracle_matrix(curve, sup, tabp, m, k0, kp.k1, eps1, mu1) for m in range(M + 1)])
+    matsp = np.array([oracle_matrix(curve, sup, perturbed(tab, 11, 2.0 ** -53), m, k0, kp.k1, eps1, mu1)
+                      for m in range(M + 1)])
+    matsk = [oracle_matrix(curve, sup, perturbed(tab, 12, 1e-14), m, k0, kp.k1, eps1, mu1) for m in range(M + 1)]
     w = geometry.gl_weights(curve)
     waves = [incident.tilted_direction(30.0), incident.tilted_direction(75.0)]
     rhs = incident.rhs_modes(curve, waves, k0, -M, M, mu0=1.0)
     x = osolve.solve_modes(list(mats), w, rhs, -M, M)
-    xp = osolve.solve_modes(list(matsp), w, rhs, -M, M)
+    xp = osolve.solve_modes(matsk, w, rhs, -M, M)
     E = farfield.far_field(curve, w, x[:, 0], -M, k0, k0, 1.0, DIRS)
     Ep = farfield.far_field(curve, w, xp[:, 0], -M, k0, k0, 1.0, DIRS)
     sw = l2w(curve)
@@ -145,10 +151,10 @@ def test_end_to_end(case, precision):
     xerr = np.linalg.norm(sw * (x - c["x"])) / np.linalg.norm(sw * c["x"])
     E = farfield.far_field(curve, c["w"], x[:, 0], -M, k0, k0, 1.0, DIRS)
     ferr = np.max(np.abs(E - c["E"])) / np.max(np.abs(c["E"]))
-    xtol = max(1e-10, 16.0 * c["sens_x"])
-    ftol = max(1e-10, 16.0 * c["sens_E"])
-    print(f"[e2e] {c['name']} prec {precision} far field {ferr:.3e} (oracle ulp sensitivity "
-          f"{c['sens_E']:.3e}); currents L2 {xerr:.3e} (oracle ulp sensitivity {c['sens_x']:.3e})", flush=True)
+    xtol = max(1e-10, 4.0 * c["sens_x"])
+    ftol = max(1e-10, 4.0 * c["sens_E"])
+    print(f"[e2e] {c['name']} prec {precision} far field {ferr:.3e} (oracle sensitivity "
+          f"{c['sens_E']:.3e}); currents L2 {xerr:.3e} (oracle sensitivity {c['sens_x']:.3e})", flush=True)
     assert ferr < ftol, (ferr, ftol)
     assert xerr < xtol, (xerr, xtol)
 

@@ -88,10 +88,10 @@ def test_modal_helmholtz_identity(k1):
     zs = np.array([0.005, 0.1, 0.9])
     K = modal.modal_kernels(rt, zt, rs, zs, kp)
     m = np.arange(kp.M + 2)[None, :]
-    dg = K[:, 0] - K[:, 3]
-    dgr = K[:, 1] - K[:, 4]
+    dg = K[:, 3]
+    dgr = K[:, 4]
     res = K[:, 6] + dgr / rt[:, None] - m * m / rt[:, None] ** 2 * dg + K[:, 8] \
-        + kp.k0 ** 2 * K[:, 0] - kp.k1 ** 2 * K[:, 3]
+        + (kp.k0 ** 2 - kp.k1 ** 2) * K[:, 0] + kp.k1 ** 2 * K[:, 3]
     scale = np.max(np.abs(K[:, 6]), axis=1)[:, None] + np.max(np.abs(m * m * dg), axis=1)[:, None]
     assert np.max(np.abs(res) / scale) < 1e-12
 
