@@ -81,9 +81,9 @@ def test_mie_far_field(sphere_case):
     e = np.cross(np.cross(c["d"], c["p"]), c["d"])
     Em = mie.far_field(c["k0"], 1.0, np.sqrt(c["eps1"]), c["d"], e, dirs)
     err = np.max(np.linalg.norm(E - Em, axis=1)) / np.max(np.linalg.norm(Em, axis=1))
-    # 8 equal panels on the semicircle: ~1.4e-9, limited by the rows next to the
-    # axis, where the 1/r_t and 1/r_t^2 factors of the mode-1 operators amplify
-    # rounding
+    # 8 equal panels on the semicircle: ~1.7e-9, limited by the rows next to the
+    # axis, where the 1/r_t and 1/r_t^2 factors of the mode operators amplify
+    # rounding of the kernels
     assert err < 5e-9, err
 
 
