@@ -374,9 +374,10 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
                                                    int Mr, int c0, int Nc, int k0, int K) {
   using T = typename V2<R>::T;
   using C4 = typename Mfma<R>::C4;
-  // [k][row] / [k][col]; the row stride kGT + 16 puts the four k rows a
-  // wave reads at once in disjoint bank ranges
-  __shared__ R As_re[kGK][kGT + 16], As_im[kGK][kGT + 16];
+  // A as [row][k] with stride kGK + 1, B as [k][col] with stride kGT + 16:
+  // both the transposing stores and the MFMA operand reads of a wave then
+  // fall in distinct LDS banks
+  __shared__ R As_re[kGT][kGK + 1], As_im[kGT][kGK + 1];
   __shared__ R Bs_re[kGK][kGT + 16], Bs_im[kGK][kGT + 16];
   T* M = A + (size_t)blockIdx.z * stride;
   const int tr = r0 + blockIdx.y * kGT;
@@ -402,8 +403,8 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
       a.x = 0;
       a.y = 0;
       if (gr < rend && gk < kend) a = M[(size_t)gr * n + gk];
-      As_re[kk][rr] = -a.x;
-      As_im[kk][rr] = a.y;
+      As_re[rr][kk] = -a.x;
+      As_im[rr][kk] = a.y;
       int kb = e / kGT, cc = e % kGT;
       int gkb = kc + kb, gc = tc + cc;
       T b;
@@ -421,8 +422,8 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
       R are[2], aim[2], bre[2], bim[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        are[a] = As_re[kk][wr + 16 * a + li];  // = -Re A
-        aim[a] = As_im[kk][wr + 16 * a + li];  // = +Im A
+        are[a] = As_re[wr + 16 * a + li][kk];  // = -Re A
+        aim[a] = As_im[wr + 16 * a + li][kk];  // = +Im A
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
