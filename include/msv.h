@@ -144,6 +144,39 @@ msv_status msv_solve(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_rhs,
 /* Iterations used by the last precision-1 msv_solve (max over modes). */
 int32_t msv_last_ir_iterations(const msv_plan *plan);
 
+/* ---------------------------------------------------------------------------
+ * Batching form.  The paper factors the modes of one body at a time, with the
+ * modes spread over threads (Section 6).  Here the per-mode systems of several
+ * bodies, of different orders, are factored by one shared sequence of launches.
+ * That sequence is captured once in a HIP graph and replayed.
+ *
+ * msv_batch_create: plans[i] (precision 1, distinct) with its matrices
+ * d_A[i] = [m_hi-m_lo+1][4N_i][4N_i] from msv_assemble(plans[i], .., m_lo,
+ * m_hi, ..).  The matrices must stay alive and unchanged while the batch is
+ * used.  Creation allocates each plan's factor storage.  It then times both
+ * outer panel widths (64 and 128 columns) on the batch itself, keeps the
+ * faster graph, and leaves every plan factored as by msv_factor.  128 is only
+ * a candidate when every order below the largest is a multiple of 128.
+ * It synchronizes `stream` and returns MSV_EINVAL for bad arguments, MSV_ENOMEM
+ * and MSV_EHIP otherwise (message: msv_batch_last_error(NULL)).
+ *
+ * msv_batch_factor: refactors the batch from the current contents of d_A,
+ * ordered on `stream` (the graph runs on the batch's own stream, joined by
+ * events).  Afterwards msv_solve works on each plan.  Factorizations of the
+ * same plan outside the batch overwrite its factors.
+ * ------------------------------------------------------------------------- */
+typedef struct msv_batch msv_batch;
+msv_status msv_batch_create(msv_batch **out, msv_plan *const *plans, msv_c128 *const *d_A, int32_t n_plans,
+                            int32_t m_lo, int32_t m_hi, void *stream);
+msv_status msv_batch_factor(msv_batch *batch, void *stream);
+void msv_batch_destroy(msv_batch *batch);
+const char *msv_batch_last_error(const msv_batch *batch);
+/* outer panel width the autotuner chose (64 or 128) */
+int32_t msv_batch_panel(const msv_batch *batch);
+/* the timed duration in ms of one batched factorization with panel width 64 or
+ * 128 (-1 if that candidate was not run) */
+float msv_batch_tuned_ms(const msv_batch *batch, int32_t panel);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,9 @@ _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESINGULAR", 5: "ENOCONV"}
 
 EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nodes",
            "msv_num_support", "msv_table_entries", "msv_matrix_order", "msv_tabulate",
-           "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations"]
+           "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations",
+           "msv_batch_create", "msv_batch_factor", "msv_batch_destroy", "msv_batch_last_error",
+           "msv_batch_panel", "msv_batch_tuned_ms"]
 
 
 class MsvError(RuntimeError):
@@ -82,6 +84,19 @@ def load_library(path: str = LIB_PATH):
     lib.msv_factor.restype = ctypes.c_int
     lib.msv_solve.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.msv_solve.restype = ctypes.c_int
+    lib.msv_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, P]
+    lib.msv_batch_create.restype = ctypes.c_int
+    lib.msv_batch_factor.argtypes = [P, P]
+    lib.msv_batch_factor.restype = ctypes.c_int
+    lib.msv_batch_destroy.argtypes = [P]
+    lib.msv_batch_destroy.restype = None
+    lib.msv_batch_last_error.argtypes = [P]
+    lib.msv_batch_last_error.restype = ctypes.c_char_p
+    lib.msv_batch_panel.argtypes = [P]
+    lib.msv_batch_panel.restype = ctypes.c_int32
+    lib.msv_batch_tuned_ms.argtypes = [P, ctypes.c_int32]
+    lib.msv_batch_tuned_ms.restype = ctypes.c_float
     _lib = lib
     return lib
 
@@ -189,6 +204,49 @@ class Plan:
                                        ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                        _stream_handle(stream)))
         return out
+
+
+class Batch:
+    """Per-mode systems of several plans factored by one captured launch
+    sequence (msv_batch_create / msv_batch_factor)."""
+
+    def __init__(self, plans, mats, m_lo, m_hi, stream=None):
+        self.lib = plans[0].lib
+        for p, A in zip(plans, mats):
+            assert A.is_contiguous() and tuple(A.shape) == (m_hi - m_lo + 1, p.n, p.n)
+        self._plans = list(plans)
+        self._mats = list(mats)  # the library keeps using these buffers
+        P = ctypes.c_void_p
+        ph = (P * len(plans))(*[p._h.value for p in plans])
+        ah = (P * len(mats))(*[A.data_ptr() for A in mats])
+        self._h = P()
+        st = self.lib.msv_batch_create(ctypes.byref(self._h), ph, ah, len(plans), int(m_lo), int(m_hi),
+                                       _stream_handle(stream))
+        if st != MSV_OK:
+            raise MsvError(st, self.lib.msv_batch_last_error(None).decode())
+
+    @property
+    def panel(self) -> int:
+        return int(self.lib.msv_batch_panel(self._h))
+
+    def tuned_ms(self, panel: int) -> float:
+        return float(self.lib.msv_batch_tuned_ms(self._h, int(panel)))
+
+    def factor(self, stream=None):
+        st = self.lib.msv_batch_factor(self._h, _stream_handle(stream))
+        if st != MSV_OK:
+            raise MsvError(st, self.lib.msv_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.msv_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def plan_from_curve(curve, rules, k0, eps1, mu1=1.0, m_max=16, fft_len=64, precision=0, **kw):

@@ -2,8 +2,12 @@
 // gfx950, for the per-mode Mueller systems (one matrix per azimuthal mode; the
 // paper factors each mode with LAPACK, Section 6).
 //
-// Storage: row-major, matrices of order n, `nb` matrices `stride` elements
-// apart; all kernels index the matrix by blockIdx.z.
+// Storage: row-major.  A batch is either uniform (`nb` matrices of order n,
+// `stride` elements apart) or a list of matrices of different orders (the
+// batching form: modes of several bodies factored by the same launches).
+// Kernels take the matrix from blockIdx.z; extents given as -1 run to the
+// matrix's own order, and a matrix whose order a step lies beyond does
+// nothing in that step.
 //
 // Factorization (right-looking, recursive panels):
 //   for each outer panel of NB = 128 columns:
@@ -25,6 +29,32 @@ template <typename R> struct V2;
 template <> struct V2<double> { using T = double2; };
 template <> struct V2<float> { using T = float2; };
 
+// A batch of matrices, uniform or listed (see msv_internal.h, LuMat).
+template <typename T>
+struct Mats {
+  T* A;             // uniform: matrix z at A + z * stride
+  int32_t* ipiv;    // uniform: [nb][n]
+  int32_t* info;    // uniform: [nb]
+  long long stride;
+  int n;
+  const LuMat* list;  // non-null: matrix z is list[z]
+};
+template <typename T>
+struct Mz {
+  T* a;
+  int32_t* piv;
+  int32_t* info;
+  int n;
+};
+template <typename T>
+__device__ __forceinline__ Mz<T> mat_at(const Mats<T>& B, int z) {
+  if (B.list) {
+    const LuMat& m = B.list[z];
+    return Mz<T>{static_cast<T*>(m.a), m.ipiv, m.info, m.n};
+  }
+  return Mz<T>{B.A + (size_t)z * B.stride, B.ipiv + (size_t)z * B.n, B.info + z, B.n};
+}
+
 constexpr int kBaseW = 8;      // strip width of the base panel
 constexpr int kPanelThreads = 1024;
 constexpr int kMaxRowsPerThread = 8;  // n <= kPanelThreads * kMaxRowsPerThread
@@ -35,12 +65,13 @@ constexpr int kMaxRowsPerThread = 8;  // n <= kPanelThreads * kMaxRowsPerThread
 // column loop is unrolled so the strip is indexed with constants.
 // ---------------------------------------------------------------------------
 template <typename R, int kRowsPerThread>
-__global__ __launch_bounds__(kPanelThreads) void base_panel(typename V2<R>::T* A, int32_t* ipiv,
-                                                            int32_t* info, int n, long long stride,
-                                                            int c0, int w) {
+__global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>::T> B, int c0, int w) {
   using T = typename V2<R>::T;
-  T* M = A + (size_t)blockIdx.z * stride;
-  int32_t* piv = ipiv + (size_t)blockIdx.z * n;
+  const Mz<T> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (c0 >= n) return;
+  T* M = mz.a;
+  int32_t* piv = mz.piv;
   __shared__ R red_v[kPanelThreads / 64];
   __shared__ int red_i[kPanelThreads / 64];
   __shared__ T prow[kBaseW];
@@ -100,7 +131,7 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(typename V2<R>::T* A
           ii = red_i[q];
         }
       if (b == (R)0 || ii >= rows) {
-        if (info[blockIdx.z] == 0) info[blockIdx.z] = c0 + j + 1;
+        if (*mz.info == 0) *mz.info = c0 + j + 1;
         ii = j;
       }
       s_p = ii;
@@ -186,10 +217,13 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(typename V2<R>::T* A
 // row interchanges for pivots [k1, k2) applied to columns [cb, ce)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void laswp(T* A, const int32_t* ipiv, int n, long long stride, int k1,
-                                             int k2, int cb, int ce) {
-  T* M = A + (size_t)blockIdx.z * stride;
-  const int32_t* piv = ipiv + (size_t)blockIdx.z * n;
+__global__ __launch_bounds__(256) void laswp(Mats<T> B, int k1, int k2, int cb, int ce) {
+  const Mz<T> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (k1 >= n) return;
+  if (ce < 0) ce = n;
+  T* M = mz.a;
+  const int32_t* piv = mz.piv;
   int c = cb + blockIdx.x * 256 + threadIdx.x;
   if (c >= ce) return;
   for (int k = k1; k < k2; ++k) {
@@ -209,12 +243,15 @@ __global__ __launch_bounds__(256) void laswp(T* A, const int32_t* ipiv, int n, l
 // workgroup reads its whole tile into LDS before writing it back).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(64) void linv_block(const typename V2<R>::T* A, int n, long long stride, int k,
-                                                 int h, typename V2<R>::T* linv) {
+__global__ __launch_bounds__(64) void linv_block(Mats<typename V2<R>::T> B, int k, int h,
+                                                 typename V2<R>::T* linv) {
   using T = typename V2<R>::T;
   __shared__ T Ls[64][65];
   __shared__ T Y[64][65];
-  const T* M = A + (size_t)blockIdx.z * stride;
+  const Mz<T> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (k >= n) return;
+  const T* M = mz.a;
   const int j = threadIdx.x;
   for (int r = 0; r < 64; ++r) {
     T z;
@@ -243,12 +280,15 @@ __global__ __launch_bounds__(64) void linv_block(const typename V2<R>::T* A, int
 // 64 columns x 4 threads; thread t of a column keeps rows j = t (mod 4) in
 // registers and row i's dot product is split over the four threads.
 template <typename R, int H>
-__global__ __launch_bounds__(256) void trsm_small(typename V2<R>::T* A, int n, long long stride, int k, int cb,
-                                                  int ce) {
+__global__ __launch_bounds__(256) void trsm_small(Mats<typename V2<R>::T> B, int k, int cb, int ce) {
   using T = typename V2<R>::T;
   constexpr int Q = H / 4;
   __shared__ T Ls[H][H + 1];
-  T* M = A + (size_t)blockIdx.z * stride;
+  const Mz<T> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (k >= n) return;
+  if (ce < 0) ce = n;
+  T* M = mz.a;
   for (int e = threadIdx.x; e < H * H; e += 256) {
     const int i = e / H, j = e % H;
     Ls[i][j] = M[(size_t)(k + i) * n + k + j];
@@ -292,12 +332,16 @@ __global__ __launch_bounds__(256) void trsm_small(typename V2<R>::T* A, int n, l
 template <typename R> struct Mfma;
 
 template <typename R>
-__global__ __launch_bounds__(256) void trsm_inv(typename V2<R>::T* A, int n, long long stride, int k, int h,
-                                                int cb, int ce, const typename V2<R>::T* linv) {
+__global__ __launch_bounds__(256) void trsm_inv(Mats<typename V2<R>::T> B, int k, int h, int cb, int ce,
+                                                const typename V2<R>::T* linv) {
   using T = typename V2<R>::T;
   using C4 = typename Mfma<R>::C4;
   __shared__ T Xs[64][65];  // [row][col]
-  T* M = A + (size_t)blockIdx.z * stride;
+  const Mz<T> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (k >= n) return;
+  if (ce < 0) ce = n;
+  T* M = mz.a;
   const T* Li = linv + (size_t)blockIdx.z * 64 * 64;
   const int c0 = cb + blockIdx.x * 64;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -370,8 +414,8 @@ template <> struct Mfma<float> {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, long long stride, int r0,
-                                                   int Mr, int c0, int Nc, int k0, int K) {
+__global__ __launch_bounds__(256) void gemm_update(Mats<typename V2<R>::T> B, int r0, int rend, int c0, int cend,
+                                                   int k0, int K) {
   using T = typename V2<R>::T;
   using C4 = typename Mfma<R>::C4;
   // A as [row][k] with stride kGK + 1, B as [k][col] with stride kGT + 16:
@@ -379,9 +423,14 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
   // fall in distinct LDS banks
   __shared__ R As_re[kGT][kGK + 1], As_im[kGT][kGK + 1];
   __shared__ R Bs_re[kGK][kGT + 16], Bs_im[kGK][kGT + 16];
-  T* M = A + (size_t)blockIdx.z * stride;
+  const Mz<T> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (rend < 0) rend = n;
+  if (cend < 0) cend = n;
   const int tr = r0 + blockIdx.y * kGT;
   const int tc = c0 + blockIdx.x * kGT;
+  if (k0 >= n || tr >= rend || tc >= cend) return;
+  T* M = mz.a;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -393,7 +442,7 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
       cre[a][b] = C4{0, 0, 0, 0};
       cim[a][b] = C4{0, 0, 0, 0};
     }
-  const int rend = r0 + Mr, cend = c0 + Nc, kend = k0 + K;
+  const int kend = k0 + K;
   for (int kc = k0; kc < kend; kc += kGK) {
     // load A tile [64 rows][16 k] and B tile [16 k][64 cols]
     for (int e = tid; e < kGT * kGK; e += 256) {
@@ -462,44 +511,61 @@ __global__ __launch_bounds__(256) void gemm_update(typename V2<R>::T* A, int n, 
       }
 }
 
+// Host view of a batch: the device descriptor plus its count and the
+// largest order (which sizes the grids).
+template <typename T>
+struct Batch {
+  Mats<T> d;
+  int nb;
+  int nmax;
+  T* linv;  // [nb][64][64] workspace
+};
+
+// C[r0:rend, c0:cend] -= A[r0:rend, k0:k0+K] * A[k0:k0+K, c0:cend]; rend or
+// cend -1 = the matrix order.  The grid covers the largest order.
 template <typename R>
-hipError_t gemm(typename V2<R>::T* A, const LuBatch& b, int r0, int Mr, int c0, int Nc, int k0, int K,
+hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int cend, int k0, int K,
                 hipStream_t s) {
+  const int Mr = (rend < 0 ? b.nmax : rend) - r0, Nc = (cend < 0 ? b.nmax : cend) - c0;
   if (Mr <= 0 || Nc <= 0 || K <= 0) return hipSuccess;
   dim3 g((Nc + kGT - 1) / kGT, (Mr + kGT - 1) / kGT, b.nb);
-  hipLaunchKernelGGL(gemm_update<R>, g, dim3(256), 0, s, A, b.n, b.stride, r0, Mr, c0, Nc, k0, K);
+  hipLaunchKernelGGL(gemm_update<R>, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t swaps(typename V2<R>::T* A, const int32_t* ipiv, const LuBatch& b, int k1, int k2, int cb,
-                 int ce, hipStream_t s) {
-  if (ce <= cb || k2 <= k1) return hipSuccess;
-  dim3 g((ce - cb + 255) / 256, 1, b.nb);
-  hipLaunchKernelGGL(laswp<typename V2<R>::T>, g, dim3(256), 0, s, A, ipiv, b.n, b.stride, k1, k2, cb, ce);
+hipError_t swaps(const Batch<typename V2<R>::T>& b, int k1, int k2, int cb, int ce, hipStream_t s) {
+  const int cmax = ce < 0 ? b.nmax : ce;
+  if (cmax <= cb || k2 <= k1) return hipSuccess;
+  dim3 g((cmax - cb + 255) / 256, 1, b.nb);
+  hipLaunchKernelGGL(laswp<typename V2<R>::T>, g, dim3(256), 0, s, b.d, k1, k2, cb, ce);
   return hipGetLastError();
 }
 
+// X = A[k:k+h, cb:ce] <- L^{-1} X with L the unit-lower A[k:k+h, k:k+h];
+// ce -1 = the matrix order (row block of an outer step), otherwise the
+// columns lie inside a panel (at most 64).
 template <typename R>
-hipError_t trsm(typename V2<R>::T* A, const LuBatch& b, int k, int h, int cb, int ce, typename V2<R>::T* linv,
-                hipStream_t s) {
-  if (ce <= cb || h <= 0) return hipSuccess;
+hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce, hipStream_t s) {
+  const int cmax = ce < 0 ? b.nmax : ce;
+  if (cmax <= cb || h <= 0) return hipSuccess;
   if (h > 64) return hipErrorInvalidValue;
-  if (ce - cb <= 64) {  // inside a panel: register substitution, no inverse
+  if (ce >= 0) {  // inside a panel: register substitution, no inverse
+    if (ce - cb > 64) return hipErrorInvalidValue;
     dim3 g(1, 1, b.nb);
     switch (h) {
-      case 4: hipLaunchKernelGGL((trsm_small<R, 4>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
-      case 8: hipLaunchKernelGGL((trsm_small<R, 8>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
-      case 16: hipLaunchKernelGGL((trsm_small<R, 16>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
-      case 32: hipLaunchKernelGGL((trsm_small<R, 32>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
-      case 64: hipLaunchKernelGGL((trsm_small<R, 64>), g, dim3(256), 0, s, A, b.n, b.stride, k, cb, ce); break;
+      case 4: hipLaunchKernelGGL((trsm_small<R, 4>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+      case 8: hipLaunchKernelGGL((trsm_small<R, 8>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+      case 16: hipLaunchKernelGGL((trsm_small<R, 16>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+      case 32: hipLaunchKernelGGL((trsm_small<R, 32>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+      case 64: hipLaunchKernelGGL((trsm_small<R, 64>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
       default: return hipErrorInvalidValue;  // panel halves are powers of two
     }
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(64), 0, s, A, b.n, b.stride, k, h, linv);
-  hipLaunchKernelGGL(trsm_inv<R>, dim3((ce - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, A, b.n, b.stride, k, h, cb,
-                     ce, linv);
+  hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(64), 0, s, b.d, k, h, b.linv);
+  hipLaunchKernelGGL(trsm_inv<R>, dim3((cmax - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, b.d, k, h, cb, ce,
+                     b.linv);
   return hipGetLastError();
 }
 
@@ -511,56 +577,55 @@ hipError_t trsm(typename V2<R>::T* A, const LuBatch& b, int k, int h, int cb, in
 
 // Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
 template <typename R>
-hipError_t panel_rec(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& b, int c0, int w,
-                     typename V2<R>::T* linv, hipStream_t s) {
+hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, hipStream_t s) {
   if (w <= kBaseW) {
-    const int rows = b.n - c0;  // the strip's rows, spread over the workgroup
+    const int rows = b.nmax - c0;  // the strip's rows, spread over the workgroup
     if (rows <= 2 * kPanelThreads)
-      hipLaunchKernelGGL((base_panel<R, 2>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
-                         b.stride, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 2>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
     else if (rows <= 4 * kPanelThreads)
-      hipLaunchKernelGGL((base_panel<R, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
-                         b.stride, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
     else
-      hipLaunchKernelGGL((base_panel<R, 8>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, A, ipiv, info, b.n,
-                         b.stride, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 8>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
     return hipGetLastError();
   }
   int h = w / 2;
-  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0, h, linv, s));
-  MSV_TRY(swaps<R>(A, ipiv, b, c0, c0 + h, c0 + h, c0 + w, s));
-  MSV_TRY(trsm<R>(A, b, c0, h, c0 + h, c0 + w, linv, s));
-  MSV_TRY(gemm<R>(A, b, c0 + h, b.n - c0 - h, c0 + h, w - h, c0, h, s));
-  MSV_TRY(panel_rec<R>(A, ipiv, info, b, c0 + h, w - h, linv, s));
+  MSV_TRY(panel_rec<R>(b, c0, h, s));
+  MSV_TRY(swaps<R>(b, c0, c0 + h, c0 + h, c0 + w, s));
+  MSV_TRY(trsm<R>(b, c0, h, c0 + h, c0 + w, s));
+  MSV_TRY(gemm<R>(b, c0 + h, -1, c0 + h, c0 + w, c0, h, s));
+  MSV_TRY(panel_rec<R>(b, c0 + h, w - h, s));
   // swaps of the right half also apply to the left half of the panel
-  MSV_TRY(swaps<R>(A, ipiv, b, c0 + h, c0 + w, c0, c0 + h, s));
+  MSV_TRY(swaps<R>(b, c0 + h, c0 + w, c0, c0 + h, s));
   return hipSuccess;
 }
 
-__global__ void zero_info(int32_t* info, int nb) {
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) info[i] = 0;
+template <typename T>
+__global__ void zero_info(Mats<T> B, int nb) {
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) *mat_at(B, i).info = 0;
 }
 
+// Outer panels of NB = 64 or 128 columns.  In a listed batch every order
+// below the largest must be a multiple of NB, so that a panel is never cut
+// short for one matrix and not for another.
 template <typename R>
-hipError_t factor(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& b, typename V2<R>::T* linv,
-                  hipStream_t s) {
-  const int n = b.n;
+hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
+  const int n = b.nmax;
   if (n > kPanelThreads * kMaxRowsPerThread) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(zero_info, dim3(1), dim3(256), 0, s, info, b.nb);
+  if (NB != 64 && NB != 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_info<typename V2<R>::T>, dim3(1), dim3(256), 0, s, b.d, b.nb);
   MSV_TRY(hipGetLastError());
-  const int NB = 128;
   for (int k = 0; k < n; k += NB) {
     int w = n - k < NB ? n - k : NB;
-    MSV_TRY(panel_rec<R>(A, ipiv, info, b, k, w, linv, s));
-    MSV_TRY(swaps<R>(A, ipiv, b, k, k + w, 0, k, s));
-    MSV_TRY(swaps<R>(A, ipiv, b, k, k + w, k + w, n, s));
-    // U12 = L11^{-1} A12 in blocks of 64 rows (TRSM register limit), then A22
+    MSV_TRY(panel_rec<R>(b, k, w, s));
+    MSV_TRY(swaps<R>(b, k, k + w, 0, k, s));
+    MSV_TRY(swaps<R>(b, k, k + w, k + w, -1, s));
+    // U12 = L11^{-1} A12 in blocks of 64 rows, then A22
     for (int kk = k; kk < k + w; kk += 64) {
       int h = k + w - kk < 64 ? k + w - kk : 64;
-      MSV_TRY(trsm<R>(A, b, kk, h, k + w, n, linv, s));
-      if (kk + h < k + w) MSV_TRY(gemm<R>(A, b, kk + h, k + w - kk - h, k + w, n - k - w, kk, h, s));
+      MSV_TRY(trsm<R>(b, kk, h, k + w, -1, s));
+      if (kk + h < k + w) MSV_TRY(gemm<R>(b, kk + h, k + w, k + w, -1, kk, h, s));
     }
-    MSV_TRY(gemm<R>(A, b, k + w, n - k - w, k + w, n - k - w, k, w, s));
+    MSV_TRY(gemm<R>(b, k + w, -1, k + w, -1, k, w, s));
   }
   return hipSuccess;
 }
@@ -568,9 +633,15 @@ hipError_t factor(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBa
 }  // namespace
 
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
-  return factor<double>(A, ipiv, info, b, static_cast<double2*>(work), s);
+  Batch<double2> bt{Mats<double2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, static_cast<double2*>(work)};
+  return factor<double>(bt, 128, s);
 }
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
-  return factor<float>(A, ipiv, info, b, static_cast<float2*>(work), s);
+  Batch<float2> bt{Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, static_cast<float2*>(work)};
+  return factor<float>(bt, 128, s);
+}
+hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s) {
+  Batch<float2> bt{Mats<float2>{nullptr, nullptr, nullptr, 0, nmax, d_list}, nb, nmax, static_cast<float2*>(work)};
+  return factor<float>(bt, panel, s);
 }
 }  // namespace msv

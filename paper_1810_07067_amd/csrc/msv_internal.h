@@ -71,9 +71,22 @@ struct LuBatch {
   long long ld;    // leading dimension (= n)
   long long stride;  // elements between matrices
 };
+// One matrix of a listed batch (matrices of different orders factored by the
+// same launches): row-major storage of order n, its pivots [n] and info flag.
+struct LuMat {
+  void* a;
+  int32_t* ipiv;
+  int32_t* info;
+  int32_t n;
+  int32_t pad;
+};
 // work: nb * 64 * 64 complex elements of the factor's precision
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
+// complex64 factorization of a listed batch (d_list on the device) with outer
+// panels of `panel` = 64 or 128 columns; nmax is the largest order, every
+// other order a multiple of `panel`
+hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s);
 
 // Right-hand-side batches for the solves (trsv.hip): up to kVB vectors that
 // use factor `fac`; vector v is stored at element off[v] * n of the work

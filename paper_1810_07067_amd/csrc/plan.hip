@@ -551,12 +551,9 @@ static hipError_t factor_groups(msv_plan* p, msv_c128* A64, float2* A32, int n, 
   return hipSuccess;
 }
 
-msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, void* stream) {
-  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
-  if (!d_A) return fail(p, MSV_EINVAL, "null matrix buffer");
-  if (m_lo < 0 || m_hi < m_lo || m_hi > p->M) return fail(p, MSV_EINVAL, "need 0 <= m_lo <= m_hi <= M");
-  hipStream_t s = (hipStream_t)stream;
-  const int n = 4 * p->N, nb = m_hi - m_lo + 1;
+// Factor storage of modes m_lo .. m_lo + nb - 1: pivots, permutations, info
+// flags, LU workspace, complex64 factors (precision 1), block inverses.
+static msv_status factor_buffers(msv_plan* p, int n, int nb) {
   const size_t nn = (size_t)n * n;
   if ((size_t)nb * n > p->ipiv_elems) {
     if (p->d_ipiv) (void)hipFree(p->d_ipiv);
@@ -580,21 +577,14 @@ msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, vo
     if (hipMalloc(&p->d_luw, luw_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "LU workspace allocation failed");
     p->luw_bytes = luw_bytes;
   }
-  if (p->precision == 0) {
-    MSV_HIP(p, factor_groups(p, d_A, nullptr, n, nb, s));
-  } else {
-    if ((size_t)nb * nn > p->fac32_elems) {
-      if (p->d_fac32) (void)hipFree(p->d_fac32);
-      p->d_fac32 = nullptr;
-      p->fac32_elems = 0;
-      if (hipMalloc(&p->d_fac32, sizeof(float2) * (size_t)nb * nn) != hipSuccess)
-        return fail(p, MSV_ENOMEM, "complex64 factor allocation failed");
-      p->fac32_elems = (size_t)nb * nn;
-    }
-    MSV_HIP(p, msv::conv_c64(reinterpret_cast<const double2*>(d_A), p->d_fac32, (size_t)nb * nn, s));
-    MSV_HIP(p, factor_groups(p, nullptr, p->d_fac32, n, nb, s));
+  if (p->precision == 1 && (size_t)nb * nn > p->fac32_elems) {
+    if (p->d_fac32) (void)hipFree(p->d_fac32);
+    p->d_fac32 = nullptr;
+    p->fac32_elems = 0;
+    if (hipMalloc(&p->d_fac32, sizeof(float2) * (size_t)nb * nn) != hipSuccess)
+      return fail(p, MSV_ENOMEM, "complex64 factor allocation failed");
+    p->fac32_elems = (size_t)nb * nn;
   }
-  MSV_HIP(p, msv::lu_perm(p->d_ipiv, p->d_perm, n, nb, s));
   const size_t inv_bytes = (size_t)nb * ((n + 63) / 64) * 2 * 64 * 64 * (p->precision == 0 ? 16 : 8);
   if (inv_bytes > p->inv_bytes) {
     if (p->d_inv) (void)hipFree(p->d_inv);
@@ -603,15 +593,229 @@ msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, vo
     if (hipMalloc(&p->d_inv, inv_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "block inverse allocation failed");
     p->inv_bytes = inv_bytes;
   }
+  return MSV_OK;
+}
+
+// After the LU: row permutations, diagonal-block inverses, bookkeeping.
+static msv_status factor_finish(msv_plan* p, msv_c128* d_A, int m_lo, int m_hi, hipStream_t s) {
+  const int n = 4 * p->N, nb = m_hi - m_lo + 1;
+  const long long nn = (long long)n * n;
+  MSV_HIP(p, msv::lu_perm(p->d_ipiv, p->d_perm, n, nb, s));
   if (p->precision == 0)
-    MSV_HIP(p, msv::lu_inv_diag_z(reinterpret_cast<const double2*>(d_A), (long long)nn, n, nb,
-                                  static_cast<double2*>(p->d_inv), s));
+    MSV_HIP(p, msv::lu_inv_diag_z(reinterpret_cast<const double2*>(d_A), nn, n, nb, static_cast<double2*>(p->d_inv), s));
   else
-    MSV_HIP(p, msv::lu_inv_diag_c(p->d_fac32, (long long)nn, n, nb, static_cast<float2*>(p->d_inv), s));
+    MSV_HIP(p, msv::lu_inv_diag_c(p->d_fac32, nn, n, nb, static_cast<float2*>(p->d_inv), s));
   p->fac_lo = m_lo;
   p->fac_hi = m_hi;
   p->fac_A = d_A;
   p->info_checked = false;
+  return MSV_OK;
+}
+
+msv_status msv_factor(msv_plan* p, msv_c128* d_A, int32_t m_lo, int32_t m_hi, void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  if (!d_A) return fail(p, MSV_EINVAL, "null matrix buffer");
+  if (m_lo < 0 || m_hi < m_lo || m_hi > p->M) return fail(p, MSV_EINVAL, "need 0 <= m_lo <= m_hi <= M");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = 4 * p->N, nb = m_hi - m_lo + 1;
+  const size_t nn = (size_t)n * n;
+  msv_status st = factor_buffers(p, n, nb);
+  if (st != MSV_OK) return st;
+  if (p->precision == 0) {
+    MSV_HIP(p, factor_groups(p, d_A, nullptr, n, nb, s));
+  } else {
+    MSV_HIP(p, msv::conv_c64(reinterpret_cast<const double2*>(d_A), p->d_fac32, (size_t)nb * nn, s));
+    MSV_HIP(p, factor_groups(p, nullptr, p->d_fac32, n, nb, s));
+  }
+  return factor_finish(p, d_A, m_lo, m_hi, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batching form: the modes of several bodies factored by the same launches
+// (a listed batch of matrices of different orders), the launch sequence
+// captured once in a HIP graph and replayed; the outer panel width is picked
+// at creation by timing both candidates on the batch itself.
+// ---------------------------------------------------------------------------
+struct msv_batch {
+  std::vector<msv_plan*> plans;
+  std::vector<msv_c128*> A;
+  int m_lo = 0, m_hi = 0;
+  int nb = 0, nmax = 0;
+  msv::LuMat* d_list = nullptr;
+  void* d_work = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int panel = 128;
+  float tuned_ms[2] = {-1.f, -1.f};  // panel 64, panel 128
+  std::string err;
+};
+
+static thread_local std::string g_batch_err;
+
+static msv_status batch_fail(msv_batch* b, msv_status st, const std::string& msg) {
+  if (b) b->err = msg;
+  else g_batch_err = msg;
+  return st;
+}
+
+// The launch sequence of one batched factorization, on stream s.
+static hipError_t batch_sequence(msv_batch* b, int panel, hipStream_t s) {
+  hipError_t e;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    msv_plan* p = b->plans[i];
+    const size_t n = 4 * (size_t)p->N, cnt = (size_t)(b->m_hi - b->m_lo + 1) * n * n;
+    if ((e = msv::conv_c64(reinterpret_cast<const double2*>(b->A[i]), p->d_fac32, cnt, s)) != hipSuccess) return e;
+  }
+  if ((e = msv::lu_factor_list_c(b->d_list, b->nb, b->nmax, panel, b->d_work, s)) != hipSuccess) return e;
+  const int nbp = b->m_hi - b->m_lo + 1;
+  for (msv_plan* p : b->plans) {
+    const int n = 4 * p->N;
+    if ((e = msv::lu_perm(p->d_ipiv, p->d_perm, n, nbp, s)) != hipSuccess) return e;
+    if ((e = msv::lu_inv_diag_c(p->d_fac32, (long long)n * n, n, nbp, static_cast<float2*>(p->d_inv), s)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t batch_capture(msv_batch* b, int panel, hipGraph_t* g, hipGraphExec_t* x) {
+  hipError_t e = hipStreamBeginCapture(b->st, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  hipError_t e2 = batch_sequence(b, panel, b->st);
+  e = hipStreamEndCapture(b->st, g);
+  if (e2 != hipSuccess) return e2;
+  if (e != hipSuccess) return e;
+  return hipGraphInstantiate(x, *g, nullptr, nullptr, 0);
+}
+
+void msv_batch_destroy(msv_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_list) (void)hipFree(b->d_list);
+  if (b->d_work) (void)hipFree(b->d_work);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->st) (void)hipStreamDestroy(b->st);
+  delete b;
+}
+
+const char* msv_batch_last_error(const msv_batch* b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
+
+int32_t msv_batch_panel(const msv_batch* b) { return b ? b->panel : 0; }
+
+msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* const* d_A, int32_t n_plans,
+                            int32_t m_lo, int32_t m_hi, void* stream) {
+  g_batch_err.clear();
+  if (!out || !plans || !d_A || n_plans < 1) return batch_fail(nullptr, MSV_EINVAL, "need plans and matrices");
+  *out = nullptr;
+  int nmax = 0;
+  for (int i = 0; i < n_plans; ++i) {
+    const msv_plan* p = plans[i];
+    if (!p || !d_A[i]) return batch_fail(nullptr, MSV_EINVAL, "null plan or matrix buffer");
+    if (p->precision != 1) return batch_fail(nullptr, MSV_EINVAL, "batched factorization needs precision 1 plans");
+    if (m_lo < 0 || m_hi < m_lo || m_hi > p->M) return batch_fail(nullptr, MSV_EINVAL, "need 0 <= m_lo <= m_hi <= M");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == p) return batch_fail(nullptr, MSV_EINVAL, "a plan appears twice");
+    nmax = std::max(nmax, 4 * p->N);
+  }
+  bool ok128 = true;
+  for (int i = 0; i < n_plans; ++i) {
+    const int n = 4 * plans[i]->N;
+    if (n != nmax && n % 128 != 0) ok128 = false;
+  }
+  msv_batch* b = new msv_batch();
+  b->plans.assign(plans, plans + n_plans);
+  b->A.assign(d_A, d_A + n_plans);
+  b->m_lo = m_lo;
+  b->m_hi = m_hi;
+  b->nmax = nmax;
+  const int nbp = m_hi - m_lo + 1;
+  b->nb = n_plans * nbp;
+  std::vector<msv::LuMat> list;
+  for (int i = 0; i < n_plans; ++i) {
+    msv_plan* p = plans[i];
+    const int n = 4 * p->N;
+    msv_status st = factor_buffers(p, n, nbp);
+    if (st != MSV_OK) {
+      std::string m = p->err;
+      msv_batch_destroy(b);
+      return batch_fail(nullptr, st, m);
+    }
+    for (int k = 0; k < nbp; ++k)
+      list.push_back(msv::LuMat{p->d_fac32 + (size_t)k * n * n, p->d_ipiv + (size_t)k * n, p->d_info + k, n, 0});
+  }
+  if (hipMalloc(&b->d_list, sizeof(msv::LuMat) * list.size()) != hipSuccess ||
+      hipMalloc(&b->d_work, (size_t)b->nb * 64 * 64 * sizeof(float2)) != hipSuccess ||
+      hipMemcpy(b->d_list, list.data(), sizeof(msv::LuMat) * list.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&b->ev_in) != hipSuccess || hipEventCreate(&b->ev_out) != hipSuccess) {
+    msv_batch_destroy(b);
+    return batch_fail(nullptr, MSV_ENOMEM, "batch allocation failed");
+  }
+  // autotune the outer panel width: capture, run once to warm up, time once
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  const int cands[2] = {64, 128};
+  for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+    if (cands[c] == 128 && !ok128) continue;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    e = batch_capture(b, cands[c], &g, &x);
+    if (e == hipSuccess) e = hipGraphLaunch(x, b->st);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_in, b->st);
+    if (e == hipSuccess) e = hipGraphLaunch(x, b->st);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->st);
+    if (e == hipSuccess) e = hipEventSynchronize(b->ev_out);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b->tuned_ms[c], b->ev_in, b->ev_out);
+    const bool best = e == hipSuccess && (!b->exec || b->tuned_ms[c] < b->tuned_ms[c == 1 ? 0 : 1]);
+    if (best) {
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      b->exec = x;
+      b->graph = g;
+      b->panel = cands[c];
+    } else {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  }
+  // leave the plans factored by the chosen configuration
+  if (e == hipSuccess && b->exec) e = hipGraphLaunch(b->exec, b->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+  if (e != hipSuccess || !b->exec) {
+    std::string m = std::string("HIP: ") + hipGetErrorString(e);
+    msv_batch_destroy(b);
+    return batch_fail(nullptr, MSV_EHIP, m);
+  }
+  for (int i = 0; i < n_plans; ++i) {
+    plans[i]->fac_lo = m_lo;
+    plans[i]->fac_hi = m_hi;
+    plans[i]->fac_A = d_A[i];
+    plans[i]->info_checked = false;
+  }
+  *out = b;
+  return MSV_OK;
+}
+
+float msv_batch_tuned_ms(const msv_batch* b, int32_t panel) {
+  if (!b) return -1.f;
+  return panel == 64 ? b->tuned_ms[0] : panel == 128 ? b->tuned_ms[1] : -1.f;
+}
+
+msv_status msv_batch_factor(msv_batch* b, void* stream) {
+  if (!b) return batch_fail(nullptr, MSV_EINVAL, "null batch");
+  hipStream_t s = (hipStream_t)stream;
+  if (hipEventRecord(b->ev_in, s) != hipSuccess || hipStreamWaitEvent(b->st, b->ev_in, 0) != hipSuccess ||
+      hipGraphLaunch(b->exec, b->st) != hipSuccess || hipEventRecord(b->ev_out, b->st) != hipSuccess ||
+      hipStreamWaitEvent(s, b->ev_out, 0) != hipSuccess)
+    return batch_fail(b, MSV_EHIP, "graph launch failed");
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    b->plans[i]->fac_lo = b->m_lo;
+    b->plans[i]->fac_hi = b->m_hi;
+    b->plans[i]->fac_A = b->A[i];
+    b->plans[i]->info_checked = false;
+  }
   return MSV_OK;
 }
 

@@ -520,13 +520,20 @@ hipError_t launch_one(const TabParams& P, hipStream_t s) {
   const int neven = (NM + 1) / 2;
   const int G = (neven + MB - 1) / MB;
   const int Q = 2 * G;
-  const int TP = kThreads / Q;
-  const int JC = kThreads / TP;
   const int Mq = P.Mq;
-  size_t lds = sizeof(double) * ((size_t)P.L + (P.L / 2 + 2) + 4 * TP + (size_t)JC * TP * 2 * kSeq +
-                                 (NEAR ? (size_t)TP * 2 * (Mq + 1) : 0)) +
-               sizeof(int) * 2 * TP;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto lds_of = [&](int tp) {
+    const int jc = kThreads / tp;
+    return sizeof(double) * ((size_t)P.L + (P.L / 2 + 2) + 4 * tp + (size_t)jc * tp * 2 * kSeq +
+                             (NEAR ? (size_t)tp * 2 * (Mq + 1) : 0)) +
+           sizeof(int) * 2 * tp;
+  };
+  // pairs per workgroup: all Q accumulator groups busy, LDS within 112 KB
+  // (threads beyond TP * Q only sample)
+  int TP = kThreads / Q;
+  while (TP > 8 && lds_of(TP) > 112 * 1024) TP /= 2;
+  const int JC = kThreads / TP;
+  const size_t lds = lds_of(TP);
+  if (lds > 112 * 1024) return hipErrorInvalidValue;
   dim3 grid;
   if (NEAR) {
     if (P.n_near == 0) return hipSuccess;

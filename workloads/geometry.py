@@ -192,7 +192,16 @@ def random_body(rng: np.random.Generator, n_panels: int, tip_levels: int = 0) ->
     edges = np.linspace(0.0, t_cut, n_panels)
     panels = [(x0, x1, f) for x0, x1 in zip(edges[:-1], edges[1:])]
     seg = _segment((float(r_c[0]), float(z_c[0])), tip)
-    for lo, hi in zip(*(lambda c_: (c_[:-1], c_[1:]))(_dyadic(0.0, 1.0, tip_levels, True))):
+    # segment panels about as long as the last body panel, the last one
+    # refined dyadically toward the tip (neighbour length ratios <= 2)
+    _, _, dr_c, dz_c = f(np.array([t_cut]))
+    body_len = float(np.hypot(dr_c[0], dz_c[0])) * (t_cut / (n_panels - 1))
+    seg_len = float(np.hypot(tip[0] - r_c[0], tip[1] - z_c[0]))
+    k = max(1, int(round(seg_len / body_len)))
+    cuts = np.linspace(0.0, 1.0, k + 1)
+    for lo, hi in zip(cuts[:-2], cuts[1:-1]):
+        panels.append((lo, hi, seg))
+    for lo, hi in zip(*(lambda c_: (c_[:-1], c_[1:]))(_dyadic(cuts[-2], 1.0, tip_levels, True))):
         panels.append((lo, hi, seg))
     return _from_panels("random_tip", panels, False, {"kind": "random_tip", "a": a, "c": c})
 
