@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kSeq = 2 * kTypes;  // 18 real sequences
-constexpr int kNSer = 20;
+constexpr int kNSer = 13;  // |x| <= 2: the 13th term is below 1e-17 of the first
 
 struct SeriesCoef {
   double sinc[kNSer], y3[kNSer], wt[kNSer], ut[kNSer], v5[kNSer], ct[kNSer];
