@@ -511,6 +511,110 @@ __global__ __launch_bounds__(256) void gemm_update(Mats<typename V2<R>::T> B, in
       }
 }
 
+// complex64 trailing update, 16-byte loads (two complex per load) with the
+// next K chunk's loads issued before the current chunk's MFMAs.
+__global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
+                                                     int K) {
+  using C4 = Mfma<float>::C4;
+  __shared__ float As_re[kGT][kGK + 1], As_im[kGT][kGK + 1];
+  __shared__ float Bs_re[kGK][kGT + 16], Bs_im[kGK][kGT + 16];
+  const Mz<float2> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (rend < 0) rend = n;
+  if (cend < 0) cend = n;
+  const int tr = r0 + blockIdx.y * kGT;
+  const int tc = c0 + blockIdx.x * kGT;
+  if (k0 >= n || tr >= rend || tc >= cend) return;
+  float2* M = mz.a;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  C4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = C4{0, 0, 0, 0};
+      cim[a][b] = C4{0, 0, 0, 0};
+    }
+  const int kend = k0 + K;
+  // thread -> pair of complex: A tile 64 rows x 8 pairs, B tile 16 rows x 32 pairs
+  // (columns start at even offsets; n and all extents are multiples of 4)
+  float4 ra[2], rb[2];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 3, kp = (e & 7) * 2;
+      const int gr = tr + rr, gk = kc + kp;
+      ra[q] = (gr < rend && gk < kend) ? *reinterpret_cast<const float4*>(M + (size_t)gr * n + gk)
+                                       : float4{0.f, 0.f, 0.f, 0.f};
+      const int kb = e >> 5, cp = (e & 31) * 2;
+      const int gkb = kc + kb, gc = tc + cp;
+      rb[q] = (gkb < kend && gc < cend) ? *reinterpret_cast<const float4*>(M + (size_t)gkb * n + gc)
+                                        : float4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  fetch(k0);
+  for (int kc = k0; kc < kend; kc += kGK) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 3, kp = (e & 7) * 2;
+      As_re[rr][kp] = -ra[q].x;
+      As_im[rr][kp] = ra[q].y;
+      As_re[rr][kp + 1] = -ra[q].z;
+      As_im[rr][kp + 1] = ra[q].w;
+      const int kb = e >> 5, cp = (e & 31) * 2;
+      Bs_re[kb][cp] = rb[q].x;
+      Bs_im[kb][cp] = rb[q].y;
+      Bs_re[kb][cp + 1] = rb[q].z;
+      Bs_im[kb][cp + 1] = rb[q].w;
+    }
+    __syncthreads();
+    if (kc + kGK < kend) fetch(kc + kGK);
+#pragma unroll
+    for (int k4 = 0; k4 < kGK; k4 += 4) {
+      const int kk = k4 + (lane >> 4);
+      const int li = lane & 15;
+      float are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        are[a] = As_re[wr + 16 * a + li][kk];
+        aim[a] = As_im[wr + 16 * a + li][kk];
+        bre[a] = Bs_re[kk][wc + 16 * a + li];
+        bim[a] = Bs_im[kk][wc + 16 * a + li];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cre[a][b] = Mfma<float>::op(are[a], bre[b], cre[a][b]);
+          cre[a][b] = Mfma<float>::op(aim[a], bim[b], cre[a][b]);
+          cim[a][b] = Mfma<float>::op(are[a], bim[b], cim[a][b]);
+          cim[a][b] = Mfma<float>::op(-aim[a], bre[b], cim[a][b]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + Mfma<float>::row(lane, i);
+        const int gc = tc + wc + 16 * b + (lane & 15);
+        if (gr < rend && gc < cend) {
+          float2* p = M + (size_t)gr * n + gc;
+          float2 v = *p;
+          v.x += cre[a][b][i];
+          v.y += cim[a][b][i];
+          *p = v;
+        }
+      }
+}
+
 // Host view of a batch: the device descriptor plus its count and the
 // largest order (which sizes the grids).
 template <typename T>
@@ -529,7 +633,10 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
   const int Mr = (rend < 0 ? b.nmax : rend) - r0, Nc = (cend < 0 ? b.nmax : cend) - c0;
   if (Mr <= 0 || Nc <= 0 || K <= 0) return hipSuccess;
   dim3 g((Nc + kGT - 1) / kGT, (Mr + kGT - 1) / kGT, b.nb);
-  hipLaunchKernelGGL(gemm_update<R>, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
+  if constexpr (sizeof(R) == 4)
+    hipLaunchKernelGGL(gemm_update_c, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
+  else
+    hipLaunchKernelGGL(gemm_update<R>, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
   return hipGetLastError();
 }
 
