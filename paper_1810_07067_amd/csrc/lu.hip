@@ -55,16 +55,15 @@ __device__ __forceinline__ Mz<T> mat_at(const Mats<T>& B, int z) {
   return Mz<T>{B.A + (size_t)z * B.stride, B.ipiv + (size_t)z * B.n, B.info + z, B.n};
 }
 
-constexpr int kBaseW = 8;      // strip width of the base panel
 constexpr int kPanelThreads = 1024;
 constexpr int kMaxRowsPerThread = 8;  // n <= kPanelThreads * kMaxRowsPerThread
 
 // ---------------------------------------------------------------------------
-// base panel: rows [c0, n) x columns [c0, c0 + w), w <= 8, pivoting in column.
+// base panel: rows [c0, n) x columns [c0, c0 + w), w <= kBaseW, pivoting in column.
 // Thread tid owns rows c0 + tid + i * kPanelThreads, i < kRowsPerThread; the
 // column loop is unrolled so the strip is indexed with constants.
 // ---------------------------------------------------------------------------
-template <typename R, int kRowsPerThread>
+template <typename R, int kRowsPerThread, int kBaseW>
 __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>::T> B, int c0, int w) {
   using T = typename V2<R>::T;
   const Mz<T> mz = mat_at(B, blockIdx.z);
@@ -685,14 +684,17 @@ hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce,
 // Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
 template <typename R>
 hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, hipStream_t s) {
-  if (w <= kBaseW) {
-    const int rows = b.nmax - c0;  // the strip's rows, spread over the workgroup
-    if (rows <= 2 * kPanelThreads)
-      hipLaunchKernelGGL((base_panel<R, 2>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
-    else if (rows <= 4 * kPanelThreads)
-      hipLaunchKernelGGL((base_panel<R, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
+  // strips: 8 columns while they fit the registers of 2 rows per thread, else 4
+  const int rows = b.nmax - c0;  // the strip's rows, spread over the workgroup
+  if (rows <= 2 * kPanelThreads && w <= 8) {
+    hipLaunchKernelGGL((base_panel<R, 2, 8>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
+    return hipGetLastError();
+  }
+  if (rows > 2 * kPanelThreads && w <= 4) {
+    if (rows <= 4 * kPanelThreads)
+      hipLaunchKernelGGL((base_panel<R, 4, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
     else
-      hipLaunchKernelGGL((base_panel<R, 8>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 8, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
     return hipGetLastError();
   }
   int h = w / 2;
