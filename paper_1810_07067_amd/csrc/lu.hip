@@ -50,9 +50,10 @@ template <typename T>
 __device__ __forceinline__ Mz<T> mat_at(const Mats<T>& B, int z) {
   if (B.list) {
     const LuMat& m = B.list[z];
-    return Mz<T>{static_cast<T*>(m.a), m.ipiv, m.info, m.n};
+    return Mz<T>{global_ptr(static_cast<T*>(m.a)), global_ptr(m.ipiv), global_ptr(m.info), m.n};
   }
-  return Mz<T>{B.A + (size_t)z * B.stride, B.ipiv + (size_t)z * B.n, B.info + z, B.n};
+  return Mz<T>{global_ptr(B.A + (size_t)z * B.stride), global_ptr(B.ipiv + (size_t)z * B.n),
+               global_ptr(B.info + z), B.n};
 }
 
 constexpr int kPanelThreads = 1024;
@@ -85,10 +86,7 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
     int r = tid + i * kPanelThreads;
 #pragma unroll
     for (int c = 0; c < kBaseW; ++c) {
-      T z;
-      z.x = 0;
-      z.y = 0;
-      v[i][c] = (r < rows && c < w) ? M[(size_t)(c0 + r) * n + c0 + c] : z;
+      v[i][c] = load_or_zero(M + (size_t)(c0 + r) * n + c0 + c, r < rows && c < w);
     }
   }
 #pragma unroll
@@ -253,10 +251,7 @@ __global__ __launch_bounds__(64) void linv_block(Mats<typename V2<R>::T> B, int 
   const T* M = mz.a;
   const int j = threadIdx.x;
   for (int r = 0; r < 64; ++r) {
-    T z;
-    z.x = 0;
-    z.y = 0;
-    Ls[r][j] = (r < h && j < h) ? M[(size_t)(k + r) * n + k + j] : z;
+    Ls[r][j] = load_or_zero(M + (size_t)(k + r) * n + k + j, r < h && j < h);
   }
   __syncthreads();
   for (int r = 0; r < 64; ++r) {
@@ -299,10 +294,7 @@ __global__ __launch_bounds__(256) void trsm_small(Mats<typename V2<R>::T> B, int
   T x[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    T z;
-    z.x = 0;
-    z.y = 0;
-    x[q] = ok ? M[(size_t)(k + 4 * q + t) * n + c] : z;
+    x[q] = load_or_zero(M + (size_t)(k + 4 * q + t) * n + c, ok);
   }
 #pragma unroll
   for (int i = 1; i < H; ++i) {
@@ -346,10 +338,7 @@ __global__ __launch_bounds__(256) void trsm_inv(Mats<typename V2<R>::T> B, int k
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int e = tid; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
-    T z;
-    z.x = 0;
-    z.y = 0;
-    Xs[r][c] = (r < h && c0 + c < ce) ? M[(size_t)(k + r) * n + c0 + c] : z;
+    Xs[r][c] = load_or_zero(M + (size_t)(k + r) * n + c0 + c, r < h && c0 + c < ce);
   }
   __syncthreads();
   if (16 * wave >= h) return;
@@ -442,27 +431,40 @@ __global__ __launch_bounds__(256) void gemm_update(Mats<typename V2<R>::T> B, in
       cim[a][b] = C4{0, 0, 0, 0};
     }
   const int kend = k0 + K;
+  // A tile [64 rows][16 k] and B tile [16 k][64 cols], four elements of each
+  // per thread, loaded one chunk ahead without a condition (an out-of-range
+  // element reads M[0]) and masked where they are stored to LDS
+  constexpr int kQ = kGT * kGK / 256;
+  T ra[kQ], rb[kQ];
+  bool oka[kQ], okb[kQ];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e / kGK, kk = e % kGK;
+      const int gr = tr + rr, gk = kc + kk;
+      oka[q] = gr < rend && gk < kend;
+      ra[q] = M[oka[q] ? (size_t)gr * n + gk : 0];
+      const int kb = e / kGT, cc = e % kGT;
+      const int gkb = kc + kb, gc = tc + cc;
+      okb[q] = gkb < kend && gc < cend;
+      rb[q] = M[okb[q] ? (size_t)gkb * n + gc : 0];
+    }
+  };
+  fetch(k0);
   for (int kc = k0; kc < kend; kc += kGK) {
-    // load A tile [64 rows][16 k] and B tile [16 k][64 cols]
-    for (int e = tid; e < kGT * kGK; e += 256) {
-      int rr = e / kGK, kk = e % kGK;
-      int gr = tr + rr, gk = kc + kk;
-      T a;
-      a.x = 0;
-      a.y = 0;
-      if (gr < rend && gk < kend) a = M[(size_t)gr * n + gk];
-      As_re[rr][kk] = -a.x;
-      As_im[rr][kk] = a.y;
-      int kb = e / kGT, cc = e % kGT;
-      int gkb = kc + kb, gc = tc + cc;
-      T b;
-      b.x = 0;
-      b.y = 0;
-      if (gkb < kend && gc < cend) b = M[(size_t)gkb * n + gc];
-      Bs_re[kb][cc] = b.x;
-      Bs_im[kb][cc] = b.y;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e / kGK, kk = e % kGK;
+      As_re[rr][kk] = oka[q] ? -ra[q].x : (R)0;
+      As_im[rr][kk] = oka[q] ? ra[q].y : (R)0;
+      const int kb = e / kGT, cc = e % kGT;
+      Bs_re[kb][cc] = okb[q] ? rb[q].x : (R)0;
+      Bs_im[kb][cc] = okb[q] ? rb[q].y : (R)0;
     }
     __syncthreads();
+    if (kc + kGK < kend) fetch(kc + kGK);
 #pragma unroll
     for (int k4 = 0; k4 < kGK; k4 += 4) {
       const int kk = k4 + (lane >> 4);
@@ -491,21 +493,32 @@ __global__ __launch_bounds__(256) void gemm_update(Mats<typename V2<R>::T> B, in
     }
     __syncthreads();
   }
-  // accumulate into C (accumulator layout per Mfma<R>::row)
+  // accumulate into C (accumulator layout per Mfma<R>::row); all loads are
+  // issued before the first add
+  T cv[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int gr = tr + wr + 16 * a + Mfma<R>::row(lane, i);
-        int gc = tc + wc + 16 * b + (lane & 15);
+        const int gr = tr + wr + 16 * a + Mfma<R>::row(lane, i);
+        const int gc = tc + wc + 16 * b + (lane & 15);
+        cv[a][b][i] = M[(gr < rend && gc < cend) ? (size_t)gr * n + gc : 0];
+      }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + Mfma<R>::row(lane, i);
+        const int gc = tc + wc + 16 * b + (lane & 15);
         if (gr < rend && gc < cend) {
-          T* p = M + (size_t)gr * n + gc;
-          T v = *p;
+          T v = cv[a][b][i];
           v.x += cre[a][b][i];
           v.y += cim[a][b][i];
-          *p = v;
+          M[(size_t)gr * n + gc] = v;
         }
       }
 }
@@ -538,20 +551,24 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
     }
   const int kend = k0 + K;
   // thread -> pair of complex: A tile 64 rows x 8 pairs, B tile 16 rows x 32 pairs
-  // (columns start at even offsets; n and all extents are multiples of 4)
+  // (columns start at even offsets; n and all extents are multiples of 4).
+  // The loads are unconditional (an out-of-range element reads M[0]) and
+  // masked where they are stored to LDS, so nothing waits on them before
+  // the next chunk's MFMAs are issued.
   float4 ra[2], rb[2];
+  bool oka[2], okb[2];
   auto fetch = [&](int kc) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = tid + 256 * q;
       const int rr = e >> 3, kp = (e & 7) * 2;
       const int gr = tr + rr, gk = kc + kp;
-      ra[q] = (gr < rend && gk < kend) ? *reinterpret_cast<const float4*>(M + (size_t)gr * n + gk)
-                                       : float4{0.f, 0.f, 0.f, 0.f};
+      oka[q] = gr < rend && gk < kend;
+      ra[q] = *reinterpret_cast<const float4*>(M + (oka[q] ? (size_t)gr * n + gk : 0));
       const int kb = e >> 5, cp = (e & 31) * 2;
       const int gkb = kc + kb, gc = tc + cp;
-      rb[q] = (gkb < kend && gc < cend) ? *reinterpret_cast<const float4*>(M + (size_t)gkb * n + gc)
-                                        : float4{0.f, 0.f, 0.f, 0.f};
+      okb[q] = gkb < kend && gc < cend;
+      rb[q] = *reinterpret_cast<const float4*>(M + (okb[q] ? (size_t)gkb * n + gc : 0));
     }
   };
   fetch(k0);
@@ -560,15 +577,15 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
     for (int q = 0; q < 2; ++q) {
       const int e = tid + 256 * q;
       const int rr = e >> 3, kp = (e & 7) * 2;
-      As_re[rr][kp] = -ra[q].x;
-      As_im[rr][kp] = ra[q].y;
-      As_re[rr][kp + 1] = -ra[q].z;
-      As_im[rr][kp + 1] = ra[q].w;
+      As_re[rr][kp] = oka[q] ? -ra[q].x : 0.f;
+      As_im[rr][kp] = oka[q] ? ra[q].y : 0.f;
+      As_re[rr][kp + 1] = oka[q] ? -ra[q].z : 0.f;
+      As_im[rr][kp + 1] = oka[q] ? ra[q].w : 0.f;
       const int kb = e >> 5, cp = (e & 31) * 2;
-      Bs_re[kb][cp] = rb[q].x;
-      Bs_im[kb][cp] = rb[q].y;
-      Bs_re[kb][cp + 1] = rb[q].z;
-      Bs_im[kb][cp + 1] = rb[q].w;
+      Bs_re[kb][cp] = okb[q] ? rb[q].x : 0.f;
+      Bs_im[kb][cp] = okb[q] ? rb[q].y : 0.f;
+      Bs_re[kb][cp + 1] = okb[q] ? rb[q].z : 0.f;
+      Bs_im[kb][cp + 1] = okb[q] ? rb[q].w : 0.f;
     }
     __syncthreads();
     if (kc + kGK < kend) fetch(kc + kGK);
@@ -596,6 +613,19 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
     }
     __syncthreads();
   }
+  // C += acc: all 16 loads issued before the first add
+  float2 cv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + Mfma<float>::row(lane, i);
+        const int gc = tc + wc + 16 * b + (lane & 15);
+        const bool ok = gr < rend && gc < cend;
+        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
+      }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -605,11 +635,10 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
         const int gr = tr + wr + 16 * a + Mfma<float>::row(lane, i);
         const int gc = tc + wc + 16 * b + (lane & 15);
         if (gr < rend && gc < cend) {
-          float2* p = M + (size_t)gr * n + gc;
-          float2 v = *p;
+          float2 v = cv[a][b][i];
           v.x += cre[a][b][i];
           v.y += cim[a][b][i];
-          *p = v;
+          M[(size_t)gr * n + gc] = v;
         }
       }
 }

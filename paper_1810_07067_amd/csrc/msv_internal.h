@@ -73,6 +73,28 @@ struct LuBatch {
 };
 // One matrix of a listed batch (matrices of different orders factored by the
 // same launches): row-major storage of order n, its pivots [n] and info flag.
+// A device pointer that the compiler is told lies in global memory.  Pointers
+// read from memory (a list of matrices) or from a struct argument are generic
+// to it; loads through them become flat loads, which also count against the
+// LDS wait counter and so stall every LDS wait until they return.  On gfx9 a
+// generic address of global memory is the global address itself.
+template <typename T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+  return (T*)(T __attribute__((address_space(1)))*)(size_t)p;
+}
+
+// *p where ok, else zero (a two-component vector type).  Written as a branch
+// around the load so that the compiler does not pick between the address of
+// p and the address of a local zero and load through a flat pointer.
+template <typename T>
+__device__ __forceinline__ T load_or_zero(const T* p, bool ok) {
+  T v;
+  v.x = 0;
+  v.y = 0;
+  if (ok) v = *p;
+  return v;
+}
+
 struct LuMat {
   void* a;
   int32_t* ipiv;

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64) void inv_diag(const typename C2<R>::T* LU, long
   const int h = min(64, n - rb);
   const T* M = LU + (size_t)f * stride;
   const T zero = {0, 0};
-  for (int r = 0; r < 64; ++r) D[r][j] = (r < h && j < h) ? M[(size_t)(rb + r) * n + rb + j] : zero;
+  for (int r = 0; r < 64; ++r) D[r][j] = load_or_zero(M + (size_t)(rb + r) * n + rb + j, r < h && j < h);
   __syncthreads();
   T* out = inv + ((size_t)f * nblk + blk) * 2 * 64 * 64;
   // L^-1 column j: y_r = [r == j] - sum_{j <= k < r} L[r][k] y_k
@@ -178,10 +178,9 @@ __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, con
   const int nblk = (n + 63) / 64;
   const int rb = blk * 64;
   const int h = min(64, n - rb);
-  const T zero = {0, 0};
   for (int e = tid; e < kVB * 64; e += 256) {
     const int v = e >> 6, k = e & 63;
-    xb[k][v] = (v < nv && k < h) ? X[(size_t)s_off[v] * n + rb + k] : zero;
+    xb[k][v] = load_or_zero(X + (size_t)s_off[v] * n + rb + k, v < nv && k < h);
   }
   __syncthreads();
   // x_i = inv(T_ii) b_i, wave w: rows 16w .. 16w+15
