@@ -523,13 +523,22 @@ __global__ __launch_bounds__(256) void gemm_update(Mats<typename V2<R>::T> B, in
       }
 }
 
-// complex64 trailing update, 16-byte loads (two complex per load) with the
-// next K chunk's loads issued before the current chunk's MFMAs.
+// complex64 trailing update.  The tiles are staged in LDS as they lie in
+// memory (complex interleaved, row-major), written with 16-byte stores.  The
+// MFMA k-slot of lane group q at step s holds k = 4q + s of the 16-k chunk, so
+// that a lane's A values for the four steps are four consecutive complex
+// numbers (two 16-byte LDS reads) and its B value per step one complex (one
+// 8-byte read).  Row strides of 18 (A) and 68 (B) complex keep the reads and
+// the writes of a wave free of bank conflicts.  The next chunk's global
+// loads are issued before the current chunk's MFMAs.
+constexpr int kAS = kGK + 2, kBS = kGT + 4;
 __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
                                                      int K) {
   using C4 = Mfma<float>::C4;
-  __shared__ float As_re[kGT][kGK + 1], As_im[kGT][kGK + 1];
-  __shared__ float Bs_re[kGK][kGT + 16], Bs_im[kGK][kGT + 16];
+  __shared__ float4 As4[kGT * kAS / 2];  // [row][k] complex, 16-byte aligned
+  __shared__ float4 Bs4[kGK * kBS / 2];  // [k][col] complex
+  float2* As = reinterpret_cast<float2*>(As4);
+  float2* Bs = reinterpret_cast<float2*>(Bs4);
   const Mz<float2> mz = mat_at(B, blockIdx.z);
   const int n = mz.n;
   if (rend < 0) rend = n;
@@ -541,7 +550,8 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  C4 cre[2][2], cim[2][2];
+  const int li = lane & 15, lq = lane >> 4;
+  C4 cre[2][2], cim[2][2];  // + A B
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -550,11 +560,10 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
       cim[a][b] = C4{0, 0, 0, 0};
     }
   const int kend = k0 + K;
-  // thread -> pair of complex: A tile 64 rows x 8 pairs, B tile 16 rows x 32 pairs
-  // (columns start at even offsets; n and all extents are multiples of 4).
-  // The loads are unconditional (an out-of-range element reads M[0]) and
-  // masked where they are stored to LDS, so nothing waits on them before
-  // the next chunk's MFMAs are issued.
+  // thread -> pair of complex: A tile 64 rows x 8 pairs, B tile 16 rows x 32
+  // pairs (columns start at even offsets; n and all extents are multiples of
+  // 4).  The loads are unconditional (an out-of-range element reads M[0])
+  // and masked where they are stored to LDS.
   float4 ra[2], rb[2];
   bool oka[2], okb[2];
   auto fetch = [&](int kc) {
@@ -571,49 +580,59 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
       rb[q] = *reinterpret_cast<const float4*>(M + (okb[q] ? (size_t)gkb * n + gc : 0));
     }
   };
+  // component-wise, so that no address is selected (which would put the
+  // prefetch registers in scratch memory)
+  auto masked = [](const float4& r, bool ok) {
+    return make_float4(ok ? r.x : 0.f, ok ? r.y : 0.f, ok ? r.z : 0.f, ok ? r.w : 0.f);
+  };
   fetch(k0);
   for (int kc = k0; kc < kend; kc += kGK) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = tid + 256 * q;
       const int rr = e >> 3, kp = (e & 7) * 2;
-      As_re[rr][kp] = oka[q] ? -ra[q].x : 0.f;
-      As_im[rr][kp] = oka[q] ? ra[q].y : 0.f;
-      As_re[rr][kp + 1] = oka[q] ? -ra[q].z : 0.f;
-      As_im[rr][kp + 1] = oka[q] ? ra[q].w : 0.f;
+      *reinterpret_cast<float4*>(As + rr * kAS + kp) = masked(ra[q], oka[q]);
       const int kb = e >> 5, cp = (e & 31) * 2;
-      Bs_re[kb][cp] = okb[q] ? rb[q].x : 0.f;
-      Bs_im[kb][cp] = okb[q] ? rb[q].y : 0.f;
-      Bs_re[kb][cp + 1] = okb[q] ? rb[q].z : 0.f;
-      Bs_im[kb][cp + 1] = okb[q] ? rb[q].w : 0.f;
+      *reinterpret_cast<float4*>(Bs + kb * kBS + cp) = masked(rb[q], okb[q]);
     }
     __syncthreads();
     if (kc + kGK < kend) fetch(kc + kGK);
+    float4 av[2][2];  // [a][half]: complex k = 4 lq + 0..3 of row wr + 16 a + li
 #pragma unroll
-    for (int k4 = 0; k4 < kGK; k4 += 4) {
-      const int kk = k4 + (lane >> 4);
-      const int li = lane & 15;
+    for (int a = 0; a < 2; ++a) {
+      const float4* pa = reinterpret_cast<const float4*>(As + (wr + 16 * a + li) * kAS + 4 * lq);
+      av[a][0] = pa[0];
+      av[a][1] = pa[1];
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
       float are[2], aim[2], bre[2], bim[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        are[a] = As_re[wr + 16 * a + li][kk];
-        aim[a] = As_im[wr + 16 * a + li][kk];
-        bre[a] = Bs_re[kk][wc + 16 * a + li];
-        bim[a] = Bs_im[kk][wc + 16 * a + li];
+        const float4 h = av[a][st >> 1];
+        are[a] = (st & 1) ? h.z : h.x;
+        aim[a] = (st & 1) ? h.w : h.y;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const float2 v = Bs[(4 * lq + st) * kBS + wc + 16 * b + li];
+        bre[b] = v.x;
+        bim[b] = v.y;
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
+          // Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br
           cre[a][b] = Mfma<float>::op(are[a], bre[b], cre[a][b]);
-          cre[a][b] = Mfma<float>::op(aim[a], bim[b], cre[a][b]);
+          cre[a][b] = Mfma<float>::op(-aim[a], bim[b], cre[a][b]);
           cim[a][b] = Mfma<float>::op(are[a], bim[b], cim[a][b]);
-          cim[a][b] = Mfma<float>::op(-aim[a], bre[b], cim[a][b]);
+          cim[a][b] = Mfma<float>::op(aim[a], bre[b], cim[a][b]);
         }
     }
     __syncthreads();
   }
-  // C += acc: all 16 loads issued before the first add
+  // C -= A B: all 16 loads issued before the first subtraction
   float2 cv[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -622,7 +641,7 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gr = tr + wr + 16 * a + Mfma<float>::row(lane, i);
-        const int gc = tc + wc + 16 * b + (lane & 15);
+        const int gc = tc + wc + 16 * b + li;
         const bool ok = gr < rend && gc < cend;
         cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
       }
@@ -633,11 +652,11 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gr = tr + wr + 16 * a + Mfma<float>::row(lane, i);
-        const int gc = tc + wc + 16 * b + (lane & 15);
+        const int gc = tc + wc + 16 * b + li;
         if (gr < rend && gc < cend) {
           float2 v = cv[a][b][i];
-          v.x += cre[a][b][i];
-          v.y += cim[a][b][i];
+          v.x -= cre[a][b][i];
+          v.y -= cim[a][b][i];
           M[(size_t)gr * n + gc] = v;
         }
       }
