@@ -76,7 +76,6 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
   __shared__ int red_i[kPanelThreads / 64];
   __shared__ T prow[kBaseW];
   __shared__ T oldj[kBaseW];
-  __shared__ int s_p;
   const int tid = threadIdx.x;
   const int rows = n - c0;
   // rows owned: r = c0 + tid + i * kPanelThreads
@@ -119,23 +118,23 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
       red_i[tid >> 6] = bi;
     }
     __syncthreads();
-    if (tid == 0) {
-      R b = red_v[0];
-      int ii = red_i[0];
-      for (int q = 1; q < kPanelThreads / 64; ++q)
-        if (red_v[q] > b || (red_v[q] == b && red_i[q] < ii)) {
-          b = red_v[q];
-          ii = red_i[q];
-        }
-      if (b == (R)0 || ii >= rows) {
-        if (*mz.info == 0) *mz.info = c0 + j + 1;
-        ii = j;
+    // every thread picks the pivot from the per-wave candidates
+    R bv = red_v[0];
+    int p = red_i[0];
+#pragma unroll
+    for (int q = 1; q < kPanelThreads / 64; ++q) {
+      const R cv = red_v[q];
+      const int ci = red_i[q];
+      if (cv > bv || (cv == bv && ci < p)) {
+        bv = cv;
+        p = ci;
       }
-      s_p = ii;
-      piv[c0 + j] = c0 + ii;
     }
-    __syncthreads();
-    const int p = s_p;
+    if (bv == (R)0 || p >= rows) {
+      if (tid == 0 && *mz.info == 0) *mz.info = c0 + j + 1;
+      p = j;
+    }
+    if (tid == 0) piv[c0 + j] = c0 + p;
     // swap local rows j and p through LDS: prow <- row p, oldj <- row j
     const int oj = j % kPanelThreads, ij = j / kPanelThreads;
     const int op = p % kPanelThreads, ip = p / kPanelThreads;
@@ -198,7 +197,8 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
           }
       }
     }
-    __syncthreads();
+    // no barrier here: the next column's LDS writes come after its first
+    // barrier, which every thread reaches only once done with prow and red_*
   }
 #pragma unroll
   for (int i = 0; i < kRowsPerThread; ++i) {

@@ -45,11 +45,6 @@ struct msv_plan {
   size_t inv_bytes = 0;
   void* d_luw = nullptr;       // LU workspace: one 64 x 64 block per matrix
   size_t luw_bytes = 0;
-  // side streams for the factorization: groups of modes run concurrently so
-  // the latency-bound panel steps of one group overlap the GEMMs of another
-  static constexpr int kFacStreams = 1;
-  hipStream_t fac_st[kFacStreams] = {};
-  hipEvent_t fac_ev[kFacStreams + 1] = {};
   size_t ipiv_elems = 0;
   bool info_checked = false;
   // solve workspace
@@ -172,10 +167,6 @@ void msv_plan_destroy(msv_plan* p) {
                   p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm, p->d_vb};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
-  for (hipStream_t st : p->fac_st)
-    if (st) (void)hipStreamDestroy(st);
-  for (hipEvent_t ev : p->fac_ev)
-    if (ev) (void)hipEventDestroy(ev);
   delete p;
 }
 
@@ -512,43 +503,11 @@ msv_status msv_assemble(msv_plan* p, const msv_c128* d_kern, int32_t m_lo, int32
   return MSV_OK;
 }
 
-// Factor nb matrices (complex128 at A64 or complex64 at A32) in up to
-// kFacStreams contiguous groups on side streams, joined back into s.
+// Factor nb matrices (complex128 at A64 or complex64 at A32) on s.
 static hipError_t factor_groups(msv_plan* p, msv_c128* A64, float2* A32, int n, int nb, hipStream_t s) {
-  const int G = std::min(msv_plan::kFacStreams, nb);
-  if (G == 1) {
-    msv::LuBatch b{n, nb, n, (long long)n * n};
-    return A64 ? msv::lu_factor_z(reinterpret_cast<double2*>(A64), p->d_ipiv, p->d_info, b, p->d_luw, s)
-               : msv::lu_factor_c(A32, p->d_ipiv, p->d_info, b, p->d_luw, s);
-  }
-  for (int g = 0; g < G; ++g)
-    if (!p->fac_st[g]) {
-      hipError_t e = hipStreamCreateWithFlags(&p->fac_st[g], hipStreamNonBlocking);
-      if (e != hipSuccess) return e;
-    }
-  for (int g = 0; g <= G; ++g)
-    if (!p->fac_ev[g]) {
-      hipError_t e = hipEventCreateWithFlags(&p->fac_ev[g], hipEventDisableTiming);
-      if (e != hipSuccess) return e;
-    }
-  hipError_t e = hipEventRecord(p->fac_ev[G], s);
-  if (e != hipSuccess) return e;
-  const size_t nn = (size_t)n * n;
-  for (int g = 0; g < G; ++g) {
-    const int lo = g * nb / G, hi = (g + 1) * nb / G;
-    if ((e = hipStreamWaitEvent(p->fac_st[g], p->fac_ev[G], 0)) != hipSuccess) return e;
-    msv::LuBatch bg{n, hi - lo, n, (long long)nn};
-    if (A64)
-      e = msv::lu_factor_z(reinterpret_cast<double2*>(A64) + lo * nn, p->d_ipiv + (size_t)lo * n, p->d_info + lo, bg,
-                           static_cast<double2*>(p->d_luw) + (size_t)lo * 64 * 64, p->fac_st[g]);
-    else
-      e = msv::lu_factor_c(A32 + lo * nn, p->d_ipiv + (size_t)lo * n, p->d_info + lo, bg,
-                           static_cast<float2*>(p->d_luw) + (size_t)lo * 64 * 64, p->fac_st[g]);
-    if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(p->fac_ev[g], p->fac_st[g])) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, p->fac_ev[g], 0)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  msv::LuBatch b{n, nb, n, (long long)n * n};
+  return A64 ? msv::lu_factor_z(reinterpret_cast<double2*>(A64), p->d_ipiv, p->d_info, b, p->d_luw, s)
+             : msv::lu_factor_c(A32, p->d_ipiv, p->d_info, b, p->d_luw, s);
 }
 
 // Factor storage of modes m_lo .. m_lo + nb - 1: pivots, permutations, info

@@ -10,13 +10,19 @@
 //
 // Solve = gather by the pivot permutation, then one launch per 64-row block
 // for the forward (unit L) and backward (U) sweeps.  The inverses of the
-// 64 x 64 diagonal blocks of L and U are formed once per factorization, so a
-// launch for block i is two dense products: every workgroup forms
-// x_i = inv(T_ii) b_i from the current b_i (redundantly; the block sits in
-// L2), workgroup 0 stores x_i in the output array, and each workgroup
-// subtracts T[c, i] x_i from one 64-row chunk c of the rows not yet solved.
-// Input and output arrays differ, so no workgroup reads a row another one
-// writes in the same launch.
+// 64 x 64 diagonal blocks of L and U are formed once per factorization.  The
+// launch for block i subtracts T[c, i] x_i from every 64-row chunk c not yet
+// solved (one workgroup per chunk); the workgroup of the next chunk then
+// forms that block's solution x = inv(T_cc) b_c from its updated b_c and
+// stores it, so the next launch reads it instead of recomputing it (only the
+// first launch of a sweep forms its x_i itself, in every workgroup).  Input
+// and output arrays differ, so no workgroup reads a row another one writes
+// in the same launch.
+//
+// Operand layout of the 16x16x4 MFMA products here: lane group q = lane / 16
+// takes k = 16 q + s at step s, so each lane reads 16 consecutive elements of
+// its matrix row; LDS vector tiles keep k at row 4 (k % 16) + k / 16, so the
+// four lane groups of a step read distinct banks.
 #include <hip/hip_runtime.h>
 
 #include "msv_internal.h"
@@ -53,30 +59,59 @@ template <> struct Mf<float> {
   static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
+// LDS row of element k of a 64 x kVB vector tile.
+__device__ __forceinline__ int pk(int k) { return 4 * (k & 15) + (k >> 4); }
+
+// a[s] = p[s], s < 16, with 16-byte loads (p 16-byte aligned).
+__device__ __forceinline__ void load_row16(const float2* p, float2 (&a)[16]) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float4 t = q[j];
+    a[2 * j] = float2{t.x, t.y};
+    a[2 * j + 1] = float2{t.z, t.w};
+  }
+}
+__device__ __forceinline__ void load_row16(const double2* p, double2 (&a)[16]) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) a[j] = p[j];
+}
+
 // (cr, ci) += A[16 rows x 64 cols] * B[64 x 16], complex: the wave's 16 rows
-// start at Arow (leading dimension ld), only columns < kmax and rows with
-// row_ok are read; B is a [64][kVB] tile in LDS.
+// start at Arow (leading dimension ld, 16-byte aligned rows), only columns
+// < kmax and rows with row_ok are read; B is a [64][kVB] tile in LDS with k at
+// row pk(k).  Two accumulator pairs halve the MFMA dependency chains.
 template <typename R>
 __device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t ld, bool row_ok, int kmax,
                                          const typename C2<R>::T (*B)[kVB], typename Mf<R>::C4& cr,
                                          typename Mf<R>::C4& ci) {
   using T = typename C2<R>::T;
-  const int lane = threadIdx.x & 63;
-  const T* ap = Arow + (size_t)(lane & 15) * ld + (lane >> 4);
+  using C4 = typename Mf<R>::C4;
+  const int lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
+  const T* ap = Arow + (size_t)li * ld + 16 * q;
   T a[16];
+  if (row_ok && 16 * q + 16 <= kmax) {
+    load_row16(ap, a);
+  } else {
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const int k = 4 * s + (lane >> 4);
-    a[s] = (row_ok && k < kmax) ? ap[4 * s] : T{0, 0};
+    for (int s = 0; s < 16; ++s) a[s] = load_or_zero(ap + s, row_ok && 16 * q + s < kmax);
   }
+  C4 r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const T b = B[4 * s + (lane >> 4)][lane & 15];
-    cr = Mf<R>::op(a[s].x, b.x, cr);
-    cr = Mf<R>::op(-a[s].y, b.y, cr);
-    ci = Mf<R>::op(a[s].x, b.y, ci);
-    ci = Mf<R>::op(a[s].y, b.x, ci);
+  for (int s = 0; s < 16; s += 2) {
+    const T b0 = B[4 * s + q][li];
+    const T b1 = B[4 * (s + 1) + q][li];
+    cr = Mf<R>::op(a[s].x, b0.x, cr);
+    r1 = Mf<R>::op(a[s + 1].x, b1.x, r1);
+    ci = Mf<R>::op(a[s].x, b0.y, ci);
+    i1 = Mf<R>::op(a[s + 1].x, b1.y, i1);
+    cr = Mf<R>::op(-a[s].y, b0.y, cr);
+    r1 = Mf<R>::op(-a[s + 1].y, b1.y, r1);
+    ci = Mf<R>::op(a[s].y, b0.x, ci);
+    i1 = Mf<R>::op(a[s + 1].y, b1.x, i1);
   }
+  cr += r1;
+  ci += i1;
 }
 
 // Inverses of the 64 x 64 diagonal blocks of the unit-lower L and upper U
@@ -164,13 +199,14 @@ __global__ __launch_bounds__(256) void gather_perm(const double2* in, TO* out, c
 template <typename R, bool FWD>
 __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, const typename C2<R>::T* inv,
                                                 long long stride, int n, const VecBatch* vb,
-                                                typename C2<R>::T* X, typename C2<R>::T* Y, int blk) {
+                                                typename C2<R>::T* X, typename C2<R>::T* Y, int blk, int first) {
   using T = typename C2<R>::T;
   using C4 = typename Mf<R>::C4;
-  __shared__ T xb[64][kVB];  // b_i
-  __shared__ T xi[64][kVB];  // x_i
+  __shared__ T xt[64][kVB];  // x_blk
+  __shared__ T xn[64][kVB];  // a right-hand-side block
   __shared__ int s_off[kVB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int v = lane & 15;
   const VecBatch& b = vb[blockIdx.y];
   const int nv = b.nv;
   if (tid < kVB) s_off[tid] = tid < nv ? b.off[tid] : 0;
@@ -178,79 +214,114 @@ __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, con
   const int nblk = (n + 63) / 64;
   const int rb = blk * 64;
   const int h = min(64, n - rb);
-  for (int e = tid; e < kVB * 64; e += 256) {
-    const int v = e >> 6, k = e & 63;
-    xb[k][v] = load_or_zero(X + (size_t)s_off[v] * n + rb + k, v < nv && k < h);
+  const size_t inv_blk = 2 * 64 * 64;
+  const T* inv_f = inv + (size_t)b.fac * nblk * inv_blk + (FWD ? 0 : 64 * 64);
+  if (first) {
+    // x_blk = inv(T_blk,blk) b_blk, in every workgroup; workgroup 0 stores it
+    for (int e = tid; e < kVB * 64; e += 256) {
+      const int vv = e >> 6, k = e & 63;
+      xn[pk(k)][vv] = load_or_zero(X + (size_t)s_off[vv] * n + rb + k, vv < nv && k < h);
+    }
+    __syncthreads();
+    C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    tile_mma<R>(inv_f + blk * inv_blk + (size_t)(16 * w) * 64, 64, true, 64, xn, cr, ci);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * w + Mf<R>::row(lane, i);
+      xt[pk(r)][v] = T{cr[i], ci[i]};
+      if (blockIdx.x == 0 && v < nv && r < h) Y[(size_t)s_off[v] * n + rb + r] = T{cr[i], ci[i]};
+    }
+  } else {
+    for (int e = tid; e < kVB * 64; e += 256) {
+      const int vv = e >> 6, k = e & 63;
+      xt[pk(k)][vv] = load_or_zero(Y + (size_t)s_off[vv] * n + rb + k, vv < nv && k < h);
+    }
   }
   __syncthreads();
-  // x_i = inv(T_ii) b_i, wave w: rows 16w .. 16w+15
-  const T* Inv = inv + (((size_t)b.fac * nblk + blk) * 2 + (FWD ? 0 : 1)) * 64 * 64;
-  C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  tile_mma<R>(Inv + (size_t)(16 * w) * 64, 64, true, 64, xb, cr, ci);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) xi[16 * w + Mf<R>::row(lane, i)][lane & 15] = T{cr[i], ci[i]};
-  __syncthreads();
-  if (blockIdx.x == 0)
-    for (int e = tid; e < kVB * 64; e += 256) {
-      const int v = e >> 6, k = e & 63;
-      if (v < nv && k < h) Y[(size_t)s_off[v] * n + rb + k] = xi[k][v];
-    }
-  const int c = FWD ? blk + 1 + (int)blockIdx.x : (int)blockIdx.x;
-  if (FWD ? (c >= nblk) : (c >= blk)) return;
+  const int chunks = FWD ? nblk - 1 - blk : blk;
+  if ((int)blockIdx.x >= chunks) return;
+  const int c = FWD ? blk + 1 + (int)blockIdx.x : blk - 1 - (int)blockIdx.x;
   const int cb = c * 64;
   const int hc = min(64, n - cb);
   const T* M = LU + (size_t)b.fac * stride;
+  C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  const int r0 = 16 * w;
+  tile_mma<R>(M + (size_t)(cb + r0) * n + rb, n, r0 + v < hc, h, xt, cr, ci);
+  const bool next = blockIdx.x == 0;  // chunk c is the next block to solve
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + Mf<R>::row(lane, i);
+    T o = {0, 0};
+    if (v < nv && r < hc) {
+      T* xp = X + (size_t)s_off[v] * n + cb + r;
+      o = *xp;
+      o.x -= cr[i];
+      o.y -= ci[i];
+      *xp = o;
+    }
+    if (next) xn[pk(r)][v] = o;
+  }
+  if (!next) return;
+  __syncthreads();
+  // x_c = inv(T_cc) b_c
   cr = C4{0, 0, 0, 0};
   ci = C4{0, 0, 0, 0};
-  const int r0 = 16 * w;
-  tile_mma<R>(M + (size_t)(cb + r0) * n + rb, n, r0 + (lane & 15) < hc, h, xi, cr, ci);
-  const int v = lane & 15;
-  if (v < nv)
+  tile_mma<R>(inv_f + c * inv_blk + (size_t)(16 * w) * 64, 64, true, 64, xn, cr, ci);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = r0 + Mf<R>::row(lane, i);
-      if (r < hc) {
-        T* xp = X + (size_t)s_off[v] * n + cb + r;
-        T o = *xp;
-        o.x -= cr[i];
-        o.y -= ci[i];
-        *xp = o;
-      }
-    }
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * w + Mf<R>::row(lane, i);
+    if (v < nv && r < hc) Y[(size_t)s_off[v] * n + cb + r] = T{cr[i], ci[i]};
+  }
 }
 
 // r_v = b_v - A[fac] x_v (complex128).  Workgroup: 64 rows (16 per wave);
-// x is staged in 64-column tiles.
+// no LDS: lane (row r, group q) streams A[r][k0 + 16q .. +16) and x_v at the
+// same k (x is read from L2 by every wave), so the waves run without
+// barriers and their loads overlap other waves' MFMAs.
 __global__ __launch_bounds__(256) void residual_b(const double2* A, long long stride, int n,
                                                   const VecBatch* vb, const double2* bv,
                                                   const double2* x, double2* r) {
   using C4 = Mf<double>::C4;
-  __shared__ double2 xt[64][kVB];
-  __shared__ int s_off[kVB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, q = lane >> 4;
   const VecBatch& b = vb[blockIdx.y];
   const int nv = b.nv;
-  if (tid < kVB) s_off[tid] = tid < nv ? b.off[tid] : 0;
   const double2* M = A + (size_t)b.fac * stride;
   const int r0 = blockIdx.x * 64 + 16 * w;
-  const bool row_ok = r0 + (lane & 15) < n;
-  C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  const bool row_ok = r0 + li < n;
+  // lane li also stands for vector li of the x operand
+  const bool vec_ok = li < nv;
+  const double2* xv = x + (size_t)(vec_ok ? b.off[li] : b.off[0]) * n + 16 * q;
+  const double2* ap = M + (size_t)(row_ok ? r0 + li : 0) * n + 16 * q;
+  C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
   for (int k0 = 0; k0 < n; k0 += 64) {
-    __syncthreads();
-    for (int e = tid; e < kVB * 64; e += 256) {
-      const int v = e >> 6, k = e & 63;
-      xt[k][v] = (v < nv && k0 + k < n) ? x[(size_t)s_off[v] * n + k0 + k] : double2{0, 0};
+    // n is a multiple of 64: every lane's 16 columns lie inside the matrix
+    double2 a[16], xb[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      a[s] = ap[k0 + s];
+      xb[s] = xv[k0 + s];
     }
-    __syncthreads();
-    tile_mma<double>(M + (size_t)r0 * n + k0, n, row_ok, n - k0, xt, cr, ci);
+#pragma unroll
+    for (int s = 0; s < 16; s += 2) {
+      cr = Mf<double>::op(a[s].x, xb[s].x, cr);
+      r1 = Mf<double>::op(a[s + 1].x, xb[s + 1].x, r1);
+      ci = Mf<double>::op(a[s].x, xb[s].y, ci);
+      i1 = Mf<double>::op(a[s + 1].x, xb[s + 1].y, i1);
+      cr = Mf<double>::op(-a[s].y, xb[s].y, cr);
+      r1 = Mf<double>::op(-a[s + 1].y, xb[s + 1].y, r1);
+      ci = Mf<double>::op(a[s].y, xb[s].x, ci);
+      i1 = Mf<double>::op(a[s + 1].y, xb[s + 1].x, i1);
+    }
   }
-  const int v = lane & 15;
-  if (v < nv)
+  cr += r1;
+  ci += i1;
+  if (vec_ok)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = r0 + Mf<double>::row(lane, i);
       if (row < n) {
-        const size_t o = (size_t)s_off[v] * n + row;
+        const size_t o = (size_t)b.off[li] * n + row;
         const double2 bb = bv[o];
         r[o] = double2{bb.x - cr[i], bb.y - ci[i]};
       }
@@ -262,15 +333,19 @@ hipError_t solve_batches(const typename C2<R>::T* LU, const typename C2<R>::T* i
                          const VecBatch* d_vb, int nvb, typename C2<R>::T* X, typename C2<R>::T* Y,
                          hipStream_t s) {
   const int nblk = (n + 63) / 64;
-  for (int i = 0; i < nblk; ++i) {
-    const int chunks = nblk - i - 1;
+  // launch i updates the blocks after i and solves block i + 1 (forward);
+  // the last block is solved by the launch before it
+  const int nfwd = nblk > 1 ? nblk - 1 : 1;
+  for (int i = 0; i < nfwd; ++i) {
+    const int chunks = nblk - 1 - i;
     hipLaunchKernelGGL((tri_step<R, true>), dim3(chunks > 0 ? chunks : 1, nvb), dim3(256), 0, s, LU, inv, stride,
-                       n, d_vb, X, Y, i);
+                       n, d_vb, X, Y, i, i == 0 ? 1 : 0);
   }
-  for (int i = nblk - 1; i >= 0; --i) {
+  const int last = nblk > 1 ? 1 : 0;
+  for (int i = nblk - 1; i >= last; --i) {
     const int chunks = i;
     hipLaunchKernelGGL((tri_step<R, false>), dim3(chunks > 0 ? chunks : 1, nvb), dim3(256), 0, s, LU, inv,
-                       stride, n, d_vb, Y, X, i);
+                       stride, n, d_vb, Y, X, i, i == nblk - 1 ? 1 : 0);
   }
   return hipGetLastError();
 }
