@@ -275,53 +275,37 @@ __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, con
 }
 
 // r_v = b_v - A[fac] x_v (complex128).  Workgroup: 64 rows (16 per wave);
-// no LDS: lane (row r, group q) streams A[r][k0 + 16q .. +16) and x_v at the
-// same k (x is read from L2 by every wave), so the waves run without
-// barriers and their loads overlap other waves' MFMAs.
+// x is staged in LDS in 64-column tiles.  n is a multiple of 64.
 __global__ __launch_bounds__(256) void residual_b(const double2* A, long long stride, int n,
                                                   const VecBatch* vb, const double2* bv,
                                                   const double2* x, double2* r) {
   using C4 = Mf<double>::C4;
+  __shared__ double2 xt[64][kVB];
+  __shared__ int s_off[kVB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, q = lane >> 4;
   const VecBatch& b = vb[blockIdx.y];
   const int nv = b.nv;
+  if (tid < kVB) s_off[tid] = tid < nv ? b.off[tid] : 0;
   const double2* M = A + (size_t)b.fac * stride;
   const int r0 = blockIdx.x * 64 + 16 * w;
-  const bool row_ok = r0 + li < n;
-  // lane li also stands for vector li of the x operand
-  const bool vec_ok = li < nv;
-  const double2* xv = x + (size_t)(vec_ok ? b.off[li] : b.off[0]) * n + 16 * q;
-  const double2* ap = M + (size_t)(row_ok ? r0 + li : 0) * n + 16 * q;
-  C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
+  const bool row_ok = r0 + (lane & 15) < n;
+  C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
   for (int k0 = 0; k0 < n; k0 += 64) {
-    // n is a multiple of 64: every lane's 16 columns lie inside the matrix
-    double2 a[16], xb[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      a[s] = ap[k0 + s];
-      xb[s] = xv[k0 + s];
+    __syncthreads();
+    for (int e = tid; e < kVB * 64; e += 256) {
+      const int v = e >> 6, k = e & 63;
+      xt[pk(k)][v] = load_or_zero(x + (size_t)s_off[v] * n + k0 + k, v < nv);
     }
-#pragma unroll
-    for (int s = 0; s < 16; s += 2) {
-      cr = Mf<double>::op(a[s].x, xb[s].x, cr);
-      r1 = Mf<double>::op(a[s + 1].x, xb[s + 1].x, r1);
-      ci = Mf<double>::op(a[s].x, xb[s].y, ci);
-      i1 = Mf<double>::op(a[s + 1].x, xb[s + 1].y, i1);
-      cr = Mf<double>::op(-a[s].y, xb[s].y, cr);
-      r1 = Mf<double>::op(-a[s + 1].y, xb[s + 1].y, r1);
-      ci = Mf<double>::op(a[s].y, xb[s].x, ci);
-      i1 = Mf<double>::op(a[s + 1].y, xb[s + 1].x, i1);
-    }
+    __syncthreads();
+    tile_mma<double>(M + (size_t)r0 * n + k0, n, row_ok, 64, xt, cr, ci);
   }
-  cr += r1;
-  ci += i1;
-  if (vec_ok)
+  const int v = lane & 15;
+  if (v < nv)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = r0 + Mf<double>::row(lane, i);
       if (row < n) {
-        const size_t o = (size_t)b.off[li] * n + row;
+        const size_t o = (size_t)s_off[v] * n + row;
         const double2 bb = bv[o];
         r[o] = double2{bb.x - cr[i], bb.y - ci[i]};
       }
