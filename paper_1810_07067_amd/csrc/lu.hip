@@ -240,8 +240,8 @@ __global__ __launch_bounds__(256) void laswp(Mats<T> B, int k1, int k2, int cb, 
 // workgroup reads its whole tile into LDS before writing it back).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(64) void linv_block(Mats<typename V2<R>::T> B, int k, int h,
-                                                 typename V2<R>::T* linv) {
+__global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int k, int h,
+                                                  typename V2<R>::T* linv) {
   using T = typename V2<R>::T;
   __shared__ T Ls[64][65];
   __shared__ T Y[64][65];
@@ -249,25 +249,41 @@ __global__ __launch_bounds__(64) void linv_block(Mats<typename V2<R>::T> B, int 
   const int n = mz.n;
   if (k >= n) return;
   const T* M = mz.a;
-  const int j = threadIdx.x;
-  for (int r = 0; r < 64; ++r) {
-    Ls[r][j] = load_or_zero(M + (size_t)(k + r) * n + k + j, r < h && j < h);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    Ls[r][c] = load_or_zero(M + (size_t)(k + r) * n + k + c, r < h && c < h);
   }
   __syncthreads();
+  // column j by lanes 4j .. 4j + 3 of one wave: lane t sums the terms q = t
+  // (mod 4) of y_rj = [r == j] - sum_{j <= q < r} L[r][q] y_qj, two shuffles
+  // combine them, and lane t = 0 stores y_rj, which the four lanes read in
+  // later rows (LDS accesses of a wave complete in order)
+  const int j = tid >> 2, t = tid & 3;
   for (int r = 0; r < 64; ++r) {
-    T y;
-    y.x = r == j ? (R)1 : (R)0;
-    y.y = 0;
+    R sx = 0, sy = 0;
     if (r > j && r < h)
-      for (int q = j; q < r; ++q) {
+      for (int q = j + t; q < r; q += 4) {
         const T l = Ls[r][q], x = Y[q][j];
-        y.x -= l.x * x.x - l.y * x.y;
-        y.y -= l.x * x.y + l.y * x.x;
+        sx -= l.x * x.x - l.y * x.y;
+        sy -= l.x * x.y + l.y * x.x;
       }
-    Y[r][j] = y;
+    sx += __shfl_xor(sx, 1);
+    sy += __shfl_xor(sy, 1);
+    sx += __shfl_xor(sx, 2);
+    sy += __shfl_xor(sy, 2);
+    if (t == 0) {
+      T y;
+      y.x = r == j ? (R)1 : (r > j && r < h ? sx : (R)0);
+      y.y = r > j && r < h ? sy : (R)0;
+      Y[r][j] = y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
+  __syncthreads();
   T* out = linv + (size_t)blockIdx.z * 64 * 64;
-  for (int r = 0; r < 64; ++r) out[r * 64 + j] = Y[r][j];
+  for (int e = tid; e < 64 * 64; e += 256) out[e] = Y[e >> 6][e & 63];
 }
 
 // In-panel TRSM (at most 64 columns right of a block of h = 4..64 rows):
@@ -717,7 +733,7 @@ hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce,
     }
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(64), 0, s, b.d, k, h, b.linv);
+  hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, k, h, b.linv);
   hipLaunchKernelGGL(trsm_inv<R>, dim3((cmax - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, b.d, k, h, cb, ce,
                      b.linv);
   return hipGetLastError();
