@@ -59,6 +59,49 @@ __device__ __forceinline__ Mz<T> mat_at(const Mats<T>& B, int z) {
 constexpr int kPanelThreads = 1024;
 constexpr int kMaxRowsPerThread = 8;  // n <= kPanelThreads * kMaxRowsPerThread
 
+// One row of a strip, columns [0, W) of rowp with w valid: loaded without a
+// condition (row and column indices clamped by the caller and here) and
+// masked afterwards, so the loads of all rows are in flight together;
+// complex64 pairs as 16-byte loads (w even).
+template <int W>
+__device__ __forceinline__ void strip_load(const float2* rowp, int w, bool rok, float2 (&o)[W]) {
+#pragma unroll
+  for (int q = 0; q < W / 2; ++q) {
+    const bool ok = rok && 2 * q + 1 < w;
+    const float4 t = reinterpret_cast<const float4*>(rowp)[2 * q + 1 < w ? q : 0];
+    o[2 * q] = make_float2(ok ? t.x : 0.f, ok ? t.y : 0.f);
+    o[2 * q + 1] = make_float2(ok ? t.z : 0.f, ok ? t.w : 0.f);
+  }
+}
+template <int W>
+__device__ __forceinline__ void strip_load(const double2* rowp, int w, bool rok, double2 (&o)[W]) {
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const double2 t = rowp[c < w ? c : 0];
+    const bool ok = rok && c < w;
+    o[c] = make_double2(ok ? t.x : 0.0, ok ? t.y : 0.0);
+  }
+}
+template <int W>
+__device__ __forceinline__ void strip_store(float2* rowp, int w, const float2 (&o)[W]) {
+  if ((w & 1) == 0) {
+#pragma unroll
+    for (int q = 0; q < W / 2; ++q)
+      if (2 * q + 1 < w)
+        reinterpret_cast<float4*>(rowp)[q] = make_float4(o[2 * q].x, o[2 * q].y, o[2 * q + 1].x, o[2 * q + 1].y);
+  } else {
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      if (c < w) rowp[c] = o[c];
+  }
+}
+template <int W>
+__device__ __forceinline__ void strip_store(double2* rowp, int w, const double2 (&o)[W]) {
+#pragma unroll
+  for (int c = 0; c < W; ++c)
+    if (c < w) rowp[c] = o[c];
+}
+
 // ---------------------------------------------------------------------------
 // base panel: rows [c0, n) x columns [c0, c0 + w), w <= kBaseW, pivoting in column.
 // Thread tid owns rows c0 + tid + i * kPanelThreads, i < kRowsPerThread; the
@@ -80,12 +123,20 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
   const int rows = n - c0;
   // rows owned: r = c0 + tid + i * kPanelThreads
   T v[kRowsPerThread][kBaseW];
+  if (sizeof(T) == 8 && (w & 1)) {
+    // odd width (not produced by the blocking used here): element loads
 #pragma unroll
-  for (int i = 0; i < kRowsPerThread; ++i) {
-    int r = tid + i * kPanelThreads;
+    for (int i = 0; i < kRowsPerThread; ++i) {
+      const int r = tid + i * kPanelThreads;
 #pragma unroll
-    for (int c = 0; c < kBaseW; ++c) {
-      v[i][c] = load_or_zero(M + (size_t)(c0 + r) * n + c0 + c, r < rows && c < w);
+      for (int c = 0; c < kBaseW; ++c) v[i][c] = load_or_zero(M + (size_t)(c0 + r) * n + c0 + c, r < rows && c < w);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+      const int r = tid + i * kPanelThreads;
+      const bool rok = r < rows;
+      strip_load(M + (size_t)(c0 + (rok ? r : 0)) * n + c0, w, rok, v[i]);
     }
   }
 #pragma unroll
@@ -202,11 +253,8 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
   }
 #pragma unroll
   for (int i = 0; i < kRowsPerThread; ++i) {
-    int r = tid + i * kPanelThreads;
-    if (r < rows)
-#pragma unroll
-      for (int c = 0; c < kBaseW; ++c)
-        if (c < w) M[(size_t)(c0 + r) * n + c0 + c] = v[i][c];
+    const int r = tid + i * kPanelThreads;
+    if (r < rows) strip_store(M + (size_t)(c0 + r) * n + c0, w, v[i]);
   }
 }
 
@@ -748,18 +796,36 @@ hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce,
 // Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
 template <typename R>
 hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, hipStream_t s) {
-  // strips: 8 columns while they fit the registers of 2 rows per thread, else 4
+  // strips as wide as the registers allow without spilling: complex64 16
+  // columns up to 2 rows per thread, 8 up to 4, else 4; complex128 8 up to 2
+  // rows per thread, else 4 (every width <= 4 is a base case)
   const int rows = b.nmax - c0;  // the strip's rows, spread over the workgroup
-  if (rows <= 2 * kPanelThreads && w <= 8) {
-    hipLaunchKernelGGL((base_panel<R, 2, 8>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
-    return hipGetLastError();
-  }
-  if (rows > 2 * kPanelThreads && w <= 4) {
-    if (rows <= 4 * kPanelThreads)
-      hipLaunchKernelGGL((base_panel<R, 4, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
-    else
-      hipLaunchKernelGGL((base_panel<R, 8, 4>), dim3(1, 1, b.nb), dim3(kPanelThreads), 0, s, b.d, c0, w);
-    return hipGetLastError();
+  const dim3 g(1, 1, b.nb), t(kPanelThreads);
+  if constexpr (sizeof(R) == 4) {
+    if (rows <= 2 * kPanelThreads && w <= 16) {
+      hipLaunchKernelGGL((base_panel<R, 2, 16>), g, t, 0, s, b.d, c0, w);
+      return hipGetLastError();
+    }
+    if (rows > 2 * kPanelThreads && rows <= 4 * kPanelThreads && w <= 8) {
+      hipLaunchKernelGGL((base_panel<R, 4, 8>), g, t, 0, s, b.d, c0, w);
+      return hipGetLastError();
+    }
+    if (rows > 4 * kPanelThreads && w <= 4) {
+      hipLaunchKernelGGL((base_panel<R, 8, 4>), g, t, 0, s, b.d, c0, w);
+      return hipGetLastError();
+    }
+  } else {
+    if (rows <= 2 * kPanelThreads && w <= 8) {
+      hipLaunchKernelGGL((base_panel<R, 2, 8>), g, t, 0, s, b.d, c0, w);
+      return hipGetLastError();
+    }
+    if (rows > 2 * kPanelThreads && w <= 4) {
+      if (rows <= 4 * kPanelThreads)
+        hipLaunchKernelGGL((base_panel<R, 4, 4>), g, t, 0, s, b.d, c0, w);
+      else
+        hipLaunchKernelGGL((base_panel<R, 8, 4>), g, t, 0, s, b.d, c0, w);
+      return hipGetLastError();
+    }
   }
   int h = w / 2;
   MSV_TRY(panel_rec<R>(b, c0, h, s));
