@@ -115,8 +115,7 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
   if (c0 >= n) return;
   T* M = mz.a;
   int32_t* piv = mz.piv;
-  __shared__ R red_v[kPanelThreads / 64];
-  __shared__ int red_i[kPanelThreads / 64];
+  __shared__ unsigned long long red_k[kPanelThreads / 64];
   __shared__ T prow[kBaseW];
   __shared__ T oldj[kBaseW];
   const int tid = threadIdx.x;
@@ -142,46 +141,34 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
 #pragma unroll
   for (int j = 0; j < kBaseW; ++j) {
     if (j >= w) break;
-    // pivot search over local rows >= j
-    R best = -1;
-    int bi = 0x7fffffff;
+    // pivot search over local rows >= j on keys that order candidates by
+    // |re| + |im| (as float), then by the smaller row: no key is 0, the key
+    // of "no candidate"; all comparisons are branch-free maxima
+    unsigned long long best = 0;
 #pragma unroll
     for (int i = 0; i < kRowsPerThread; ++i) {
-      int r = tid + i * kPanelThreads;
-      if (r >= j && r < rows) {
-        R a = fabs(v[i][j].x) + fabs(v[i][j].y);
-        if (a > best || (a == best && r < bi)) {
-          best = a;
-          bi = r;
-        }
-      }
+      const int r = tid + i * kPanelThreads;
+      const float a = (float)(fabs(v[i][j].x) + fabs(v[i][j].y));
+      const unsigned long long key =
+          ((unsigned long long)__float_as_uint(a) << 32) | (unsigned)(0x7fffffff - r);
+      best = (r >= j && r < rows && key > best) ? key : best;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      R ob = __shfl_xor(best, off);
-      int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if ((tid & 63) == 0) {
-      red_v[tid >> 6] = best;
-      red_i[tid >> 6] = bi;
-    }
-    __syncthreads();
-    // every thread picks the pivot from the per-wave candidates
-    R bv = red_v[0];
-    int p = red_i[0];
 #pragma unroll
-    for (int q = 1; q < kPanelThreads / 64; ++q) {
-      const R cv = red_v[q];
-      const int ci = red_i[q];
-      if (cv > bv || (cv == bv && ci < p)) {
-        bv = cv;
-        p = ci;
-      }
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(best, off);
+      best = o > best ? o : best;
     }
-    if (bv == (R)0 || p >= rows) {
+    if ((tid & 63) == 0) red_k[tid >> 6] = best;
+    __syncthreads();
+    // every thread picks the pivot from the per-wave keys
+    unsigned long long kq[kPanelThreads / 64];
+#pragma unroll
+    for (int q = 0; q < kPanelThreads / 64; ++q) kq[q] = red_k[q];
+#pragma unroll
+    for (int q = 1; q < kPanelThreads / 64; ++q) best = kq[q] > best ? kq[q] : best;
+    best = kq[0] > best ? kq[0] : best;
+    int p = 0x7fffffff - (int)(unsigned)(best & 0xffffffffu);
+    if ((best >> 32) == 0 || p >= rows) {  // no candidate, or a zero column
       if (tid == 0 && *mz.info == 0) *mz.info = c0 + j + 1;
       p = j;
     }
