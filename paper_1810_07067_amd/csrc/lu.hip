@@ -783,14 +783,15 @@ hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce,
 // Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
 template <typename R>
 hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, hipStream_t s) {
-  // strips as wide as the registers allow without spilling: complex64 16
-  // columns up to 2 rows per thread, 8 up to 4, else 4; complex128 8 up to 2
-  // rows per thread, else 4 (every width <= 4 is a base case)
+  // strips of 8 columns while they fit the registers (complex64 up to 4 rows
+  // per thread, complex128 up to 2), else 4; every width <= 4 is a base case.
+  // (16 columns fit at 2 rows per thread but ran slower: the unrolled column
+  // loop grows past what the instruction cache holds)
   const int rows = b.nmax - c0;  // the strip's rows, spread over the workgroup
   const dim3 g(1, 1, b.nb), t(kPanelThreads);
   if constexpr (sizeof(R) == 4) {
-    if (rows <= 2 * kPanelThreads && w <= 16) {
-      hipLaunchKernelGGL((base_panel<R, 2, 16>), g, t, 0, s, b.d, c0, w);
+    if (rows <= 2 * kPanelThreads && w <= 8) {
+      hipLaunchKernelGGL((base_panel<R, 2, 8>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
     if (rows > 2 * kPanelThreads && rows <= 4 * kPanelThreads && w <= 8) {
