@@ -602,13 +602,16 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lq = lane >> 4;
-  C4 cre[2][2], cim[2][2];  // + A B
+  // A B by three real products: t1 = Ar Br, t2 = Ai Bi, t3 = (Ar + Ai)(Br + Bi);
+  // Re = t1 - t2, Im = t3 - t1 - t2
+  C4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cre[a][b] = C4{0, 0, 0, 0};
-      cim[a][b] = C4{0, 0, 0, 0};
+      t1[a][b] = C4{0, 0, 0, 0};
+      t2[a][b] = C4{0, 0, 0, 0};
+      t3[a][b] = C4{0, 0, 0, 0};
     }
   const int kend = k0 + K;
   // thread -> pair of complex: A tile 64 rows x 8 pairs, B tile 16 rows x 32
@@ -670,15 +673,18 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
         bre[b] = v.x;
         bim[b] = v.y;
       }
+      float sa[2], sb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) sa[a] = are[a] + aim[a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) sb[b] = bre[b] + bim[b];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          // Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br
-          cre[a][b] = Mfma<float>::op(are[a], bre[b], cre[a][b]);
-          cre[a][b] = Mfma<float>::op(-aim[a], bim[b], cre[a][b]);
-          cim[a][b] = Mfma<float>::op(are[a], bim[b], cim[a][b]);
-          cim[a][b] = Mfma<float>::op(aim[a], bre[b], cim[a][b]);
+          t1[a][b] = Mfma<float>::op(are[a], bre[b], t1[a][b]);
+          t2[a][b] = Mfma<float>::op(aim[a], bim[b], t2[a][b]);
+          t3[a][b] = Mfma<float>::op(sa[a], sb[b], t3[a][b]);
         }
     }
     __syncthreads();
@@ -706,8 +712,8 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
         const int gc = tc + wc + 16 * b + li;
         if (gr < rend && gc < cend) {
           float2 v = cv[a][b][i];
-          v.x -= cre[a][b][i];
-          v.y -= cim[a][b][i];
+          v.x -= t1[a][b][i] - t2[a][b][i];
+          v.y -= t3[a][b][i] - t1[a][b][i] - t2[a][b][i];
           M[(size_t)gr * n + gc] = v;
         }
       }
