@@ -165,10 +165,21 @@ __device__ __forceinline__ bool near_panel(const AsmParams& P, int pt, int ps) {
 
 constexpr int kFarThreads = 64;
 
-__global__ __launch_bounds__(kFarThreads) void assemble_far(AsmParams P) {
-  const int j = blockIdx.x * kFarThreads + threadIdx.x;
-  const int t = blockIdx.y;
-  const int mi = blockIdx.z;
+// Work items (mode, source block, target), mode fastest.  Workgroups are
+// dealt to the 8 XCDs round-robin, so the linear workgroup id is remapped to
+// give each XCD one contiguous range of items: the three modes that read a
+// table slice (m - 1, m, m + 1) then run back to back on one XCD and find the
+// slice in its L2, instead of reading it from HBM three times.
+__global__ __launch_bounds__(kFarThreads) void assemble_far(AsmParams P, int n_items) {
+  const int per = (n_items + 7) / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= n_items) return;
+  const int nm = P.m_hi - P.m_lo + 1;
+  const int njb = (P.N + kFarThreads - 1) / kFarThreads;
+  const int mi = item % nm;
+  const int jb = (item / nm) % njb;
+  const int t = item / nm / njb;
+  const int j = jb * kFarThreads + threadIdx.x;
   const int m = P.m_lo + mi;
   if (j >= P.N) return;
   if (near_panel(P, t / kOrder, j / kOrder)) return;
@@ -258,8 +269,10 @@ __global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P) {
 
 hipError_t launch_assemble(const AsmParams& P, hipStream_t s) {
   const int nm = P.m_hi - P.m_lo + 1;
-  dim3 gf((P.N + kFarThreads - 1) / kFarThreads, P.N, nm);
-  hipLaunchKernelGGL(assemble_far, gf, dim3(kFarThreads), 0, s, P);
+  const long long items = (long long)nm * ((P.N + kFarThreads - 1) / kFarThreads) * P.N;
+  if (items > (1LL << 30)) return hipErrorInvalidValue;
+  const int n_items = (int)items;
+  hipLaunchKernelGGL(assemble_far, dim3(8 * ((n_items + 7) / 8)), dim3(kFarThreads), 0, s, P, n_items);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   size_t lds = sizeof(double2) * 16 * (size_t)P.S;
