@@ -117,7 +117,7 @@ def bench_batching(rules, seed=4, n_bodies=16, M=16):
     flops = sum((8.0 / 3.0) * n ** 3 * (M + 1) for n in orders)
     return {"bodies": len(plans), "orders": orders, "modes_per_body": M + 1,
             "one_by_one_factor_ms": seq_ms, "batched_factor_ms": bat_ms, "speedup": seq_ms / bat_ms,
-            "panel": batch.panel, "tuned_ms": {"64": batch.tuned_ms(64), "128": batch.tuned_ms(128)},
+            "panel": batch.panel, "tuned_ms": {str(w): batch.tuned_ms(w) for w in (64, 128, 256)},
             "per_mode_factorizations_per_s": len(plans) * (M + 1) / (bat_ms * 1e-3),
             "tflops": flops / (bat_ms * 1e-3) / 1e12}
 

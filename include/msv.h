@@ -153,10 +153,11 @@ int32_t msv_last_ir_iterations(const msv_plan *plan);
  * msv_batch_create: plans[i] (precision 1, distinct) with its matrices
  * d_A[i] = [m_hi-m_lo+1][4N_i][4N_i] from msv_assemble(plans[i], .., m_lo,
  * m_hi, ..).  The matrices must stay alive and unchanged while the batch is
- * used.  Creation allocates each plan's factor storage.  It then times both
- * outer panel widths (64 and 128 columns) on the batch itself, keeps the
- * faster graph, and leaves every plan factored as by msv_factor.  128 is only
- * a candidate when every order below the largest is a multiple of 128.
+ * used.  Creation allocates each plan's factor storage.  It then times the
+ * outer panel widths 64, 128 and 256 columns on the batch itself, keeps the
+ * fastest graph, and leaves every plan factored as by msv_factor.  128 and 256
+ * are candidates only when every order below the largest is a multiple of
+ * them.
  * It synchronizes `stream` and returns MSV_EINVAL for bad arguments, MSV_ENOMEM
  * and MSV_EHIP otherwise (message: msv_batch_last_error(NULL)).
  *
@@ -171,10 +172,10 @@ msv_status msv_batch_create(msv_batch **out, msv_plan *const *plans, msv_c128 *c
 msv_status msv_batch_factor(msv_batch *batch, void *stream);
 void msv_batch_destroy(msv_batch *batch);
 const char *msv_batch_last_error(const msv_batch *batch);
-/* outer panel width the autotuner chose (64 or 128) */
+/* outer panel width the autotuner chose (64, 128 or 256) */
 int32_t msv_batch_panel(const msv_batch *batch);
-/* the timed duration in ms of one batched factorization with panel width 64 or
- * 128 (-1 if that candidate was not run) */
+/* the timed duration in ms of one batched factorization with panel width 64,
+ * 128 or 256 (-1 if that candidate was not run) */
 float msv_batch_tuned_ms(const msv_batch *batch, int32_t panel);
 
 #ifdef __cplusplus

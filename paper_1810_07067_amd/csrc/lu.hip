@@ -760,10 +760,18 @@ template <typename R>
 hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce, hipStream_t s) {
   const int cmax = ce < 0 ? b.nmax : ce;
   if (cmax <= cb || h <= 0) return hipSuccess;
+  if (ce >= 0 && h > 64) {  // taller in-panel block: 64-row blocks, updates between
+    for (int kk = k; kk < k + h; kk += 64) {
+      const int hh = k + h - kk < 64 ? k + h - kk : 64;
+      hipError_t e = trsm<R>(b, kk, hh, cb, ce, s);
+      if (e != hipSuccess) return e;
+      if (kk + hh < k + h && (e = gemm<R>(b, kk + hh, k + h, cb, ce, kk, hh, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (h > 64) return hipErrorInvalidValue;
   if (ce >= 0) {  // inside a panel: register substitution, no inverse
-    if (ce - cb > 64) return hipErrorInvalidValue;
-    dim3 g(1, 1, b.nb);
+    dim3 g((ce - cb + 63) / 64, 1, b.nb);
     switch (h) {
       case 4: hipLaunchKernelGGL((trsm_small<R, 4>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
       case 8: hipLaunchKernelGGL((trsm_small<R, 8>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
@@ -844,11 +852,14 @@ template <typename R>
 hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
   const int n = b.nmax;
   if (n > kPanelThreads * kMaxRowsPerThread) return hipErrorInvalidValue;
-  if (NB != 64 && NB != 128) return hipErrorInvalidValue;
+  if (NB != 64 && NB != 128 && NB != 256) return hipErrorInvalidValue;
   hipLaunchKernelGGL(zero_info<typename V2<R>::T>, dim3(1), dim3(256), 0, s, b.d, b.nb);
   MSV_TRY(hipGetLastError());
-  for (int k = 0; k < n; k += NB) {
+  for (int k = 0; k < n; ) {
+    // panel widths are powers of two (the recursive panel halves them down to
+    // the register strips): the largest one not above what is left
     int w = n - k < NB ? n - k : NB;
+    while (w & (w - 1)) w &= w - 1;
     MSV_TRY(panel_rec<R>(b, k, w, s));
     MSV_TRY(swaps<R>(b, k, k + w, 0, k, s));
     MSV_TRY(swaps<R>(b, k, k + w, k + w, -1, s));
@@ -859,6 +870,7 @@ hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
       if (kk + h < k + w) MSV_TRY(gemm<R>(b, kk + h, k + w, k + w, -1, kk, h, s));
     }
     MSV_TRY(gemm<R>(b, k + w, -1, k + w, -1, k, w, s));
+    k += w;
   }
   return hipSuccess;
 }
@@ -867,11 +879,11 @@ hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
 
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
   Batch<double2> bt{Mats<double2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, static_cast<double2*>(work)};
-  return factor<double>(bt, 128, s);
+  return factor<double>(bt, 256, s);
 }
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
   Batch<float2> bt{Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, static_cast<float2*>(work)};
-  return factor<float>(bt, 128, s);
+  return factor<float>(bt, 256, s);
 }
 hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s) {
   Batch<float2> bt{Mats<float2>{nullptr, nullptr, nullptr, 0, nmax, d_list}, nb, nmax, static_cast<float2*>(work)};

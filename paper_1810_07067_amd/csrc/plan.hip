@@ -607,7 +607,7 @@ struct msv_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int panel = 128;
-  float tuned_ms[2] = {-1.f, -1.f};  // panel 64, panel 128
+  float tuned_ms[3] = {-1.f, -1.f, -1.f};  // panel 64, 128, 256
   std::string err;
 };
 
@@ -679,10 +679,13 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
       if (plans[j] == p) return batch_fail(nullptr, MSV_EINVAL, "a plan appears twice");
     nmax = std::max(nmax, 4 * p->N);
   }
-  bool ok128 = true;
+  // a panel width is a candidate when every order below the largest is a
+  // multiple of it (a panel then never straddles the end of a smaller matrix)
+  bool ok128 = true, ok256 = true;
   for (int i = 0; i < n_plans; ++i) {
     const int n = 4 * plans[i]->N;
     if (n != nmax && n % 128 != 0) ok128 = false;
+    if (n != nmax && n % 256 != 0) ok256 = false;
   }
   msv_batch* b = new msv_batch();
   b->plans.assign(plans, plans + n_plans);
@@ -715,9 +718,10 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
   }
   // autotune the outer panel width: capture, run once to warm up, time once
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  const int cands[2] = {64, 128};
-  for (int c = 0; c < 2 && e == hipSuccess; ++c) {
-    if (cands[c] == 128 && !ok128) continue;
+  const int cands[3] = {64, 128, 256};
+  int best_c = -1;
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    if ((cands[c] == 128 && !ok128) || (cands[c] == 256 && !ok256)) continue;
     hipGraph_t g = nullptr;
     hipGraphExec_t x = nullptr;
     e = batch_capture(b, cands[c], &g, &x);
@@ -727,8 +731,9 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
     if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->st);
     if (e == hipSuccess) e = hipEventSynchronize(b->ev_out);
     if (e == hipSuccess) e = hipEventElapsedTime(&b->tuned_ms[c], b->ev_in, b->ev_out);
-    const bool best = e == hipSuccess && (!b->exec || b->tuned_ms[c] < b->tuned_ms[c == 1 ? 0 : 1]);
+    const bool best = e == hipSuccess && (best_c < 0 || b->tuned_ms[c] < b->tuned_ms[best_c]);
     if (best) {
+      best_c = c;
       if (b->exec) (void)hipGraphExecDestroy(b->exec);
       if (b->graph) (void)hipGraphDestroy(b->graph);
       b->exec = x;
@@ -759,7 +764,7 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
 
 float msv_batch_tuned_ms(const msv_batch* b, int32_t panel) {
   if (!b) return -1.f;
-  return panel == 64 ? b->tuned_ms[0] : panel == 128 ? b->tuned_ms[1] : -1.f;
+  return panel == 64 ? b->tuned_ms[0] : panel == 128 ? b->tuned_ms[1] : panel == 256 ? b->tuned_ms[2] : -1.f;
 }
 
 msv_status msv_batch_factor(msv_batch* b, void* stream) {
