@@ -80,7 +80,7 @@ __device__ __forceinline__ void load_row16(const double2* p, double2 (&a)[16]) {
 // (cr, ci) += A[16 rows x 64 cols] * B[64 x 16], complex: the wave's 16 rows
 // start at Arow (leading dimension ld, 16-byte aligned rows), only columns
 // < kmax and rows with row_ok are read; B is a [64][kVB] tile in LDS with k at
-// row pk(k).  Two accumulator pairs halve the MFMA dependency chains.
+// row pk(k).
 template <typename R>
 __device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t ld, bool row_ok, int kmax,
                                          const typename C2<R>::T (*B)[kVB], typename Mf<R>::C4& cr,
@@ -96,22 +96,18 @@ __device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t l
 #pragma unroll
     for (int s = 0; s < 16; ++s) a[s] = load_or_zero(ap + s, row_ok && 16 * q + s < kmax);
   }
-  C4 r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
+  // three real products per complex one: t1 = Ar Br, t2 = Ai Bi,
+  // t3 = (Ar + Ai)(Br + Bi); Re = t1 - t2, Im = t3 - t1 - t2
+  C4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
-  for (int s = 0; s < 16; s += 2) {
+  for (int s = 0; s < 16; ++s) {
     const T b0 = B[4 * s + q][li];
-    const T b1 = B[4 * (s + 1) + q][li];
-    cr = Mf<R>::op(a[s].x, b0.x, cr);
-    r1 = Mf<R>::op(a[s + 1].x, b1.x, r1);
-    ci = Mf<R>::op(a[s].x, b0.y, ci);
-    i1 = Mf<R>::op(a[s + 1].x, b1.y, i1);
-    cr = Mf<R>::op(-a[s].y, b0.y, cr);
-    r1 = Mf<R>::op(-a[s + 1].y, b1.y, r1);
-    ci = Mf<R>::op(a[s].y, b0.x, ci);
-    i1 = Mf<R>::op(a[s + 1].y, b1.x, i1);
+    t1 = Mf<R>::op(a[s].x, b0.x, t1);
+    t2 = Mf<R>::op(a[s].y, b0.y, t2);
+    t3 = Mf<R>::op(a[s].x + a[s].y, b0.x + b0.y, t3);
   }
-  cr += r1;
-  ci += i1;
+  cr += t1 - t2;
+  ci += t3 - t1 - t2;
 }
 
 // Inverses of the 64 x 64 diagonal blocks of the unit-lower L and upper U
