@@ -26,6 +26,9 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kSeq = 2 * kTypes;  // 18 real sequences
+// LDS stride of one pair's folded samples: one double of padding puts the
+// pairs a wave reads at distinct banks
+constexpr int kEO = 2 * kSeq + 1;
 constexpr int kNSer = 13;  // |x| <= 2: the 13th term is below 1e-17 of the first
 
 struct SeriesCoef {
@@ -335,8 +338,8 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
   double* cos_tab = smem;                 // [L]
   double* s2_tab = cos_tab + L;           // [L/2 + 1]
   double* geo = s2_tab + (L / 2 + 2);     // [TP][4]: rt, dr, dz, valid flag
-  double* EO = geo + 4 * TP;              // [JC][TP][2][18]
-  double* Xh = EO + (size_t)JC * TP * 2 * kSeq;  // NEAR: [TP][2][Mq+1]
+  double* EO = geo + 4 * TP;              // [JC][TP][kEO]: 2 x 18 folded samples
+  double* Xh = EO + (size_t)JC * TP * kEO;  // NEAR: [TP][2][Mq+1]
   int* tgt = reinterpret_cast<int*>(NEAR ? Xh + (size_t)TP * 2 * (Mq + 1) : Xh);  // [TP] t, [TP] src
   int* srcs = tgt + TP;
 
@@ -420,7 +423,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
     for (int task = tid; task < JC * TP; task += kThreads) {
       int p = task % TP, jj = task / TP;
       int j = ch * JC + jj;
-      double* eo = EO + ((size_t)jj * TP + p) * 2 * kSeq;
+      double* eo = EO + ((size_t)jj * TP + p) * kEO;
       bool live = (j <= Lq) && (geo[4 * p + 3] == 1.0);
       if (!live) {
         for (int k = 0; k < 2 * kSeq; ++k) eo[k] = 0.0;
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
       int jmax = min(JC, Lq + 1 - ch * JC);
       for (int jj = 0; jj < jmax; ++jj) {
         int j = ch * JC + jj;
-        const double* v = EO + ((size_t)jj * TP + pp) * 2 * kSeq + par * kSeq;
+        const double* v = EO + ((size_t)jj * TP + pp) * kEO + par * kSeq;
         double cs[MB];
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
@@ -523,7 +526,7 @@ hipError_t launch_one(const TabParams& P, hipStream_t s) {
   const int Mq = P.Mq;
   auto lds_of = [&](int tp) {
     const int jc = kThreads / tp;
-    return sizeof(double) * ((size_t)P.L + (P.L / 2 + 2) + 4 * tp + (size_t)jc * tp * 2 * kSeq +
+    return sizeof(double) * ((size_t)P.L + (P.L / 2 + 2) + 4 * tp + (size_t)jc * tp * kEO +
                              (NEAR ? (size_t)tp * 2 * (Mq + 1) : 0)) +
            sizeof(int) * 2 * tp;
   };
@@ -557,11 +560,13 @@ hipError_t launch_pair(const TabParams& P, hipStream_t s) {
 
 }  // namespace
 
+// Three modes per accumulating thread: with the file compiled without
+// machine-level loop-invariant hoisting (which otherwise keeps the series and
+// sincos constants live in registers across the chunk loop) the real-k1
+// kernels fit 256 registers, two waves per SIMD.
 hipError_t launch_tabulate(const TabParams& P, hipStream_t s) {
-  const bool k1c = P.k1i != 0.0;
-  const bool small = P.M2 <= 24;
-  if (k1c) return small ? launch_pair<true, 3>(P, s) : launch_pair<true, 5>(P, s);
-  return small ? launch_pair<false, 3>(P, s) : launch_pair<false, 5>(P, s);
+  if (P.k1i != 0.0) return launch_pair<true, 3>(P, s);
+  return launch_pair<false, 3>(P, s);
 }
 
 }  // namespace msv
