@@ -31,6 +31,25 @@ FP32_MFMA_PEAK_TF = 157.3
 FP64_PEAK_TF = 78.6
 
 
+def lu_traffic():
+    """HBM bytes of one factorization from the committed rocprofv3 counter
+    summary, while the LU source is the one the counters were taken on
+    (its SHA-256 is recorded there); None otherwise."""
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(here, "profiles", "lu_spheroid1024_m64_traffic.md")).read()
+        src = open(os.path.join(here, "paper_1810_07067_amd", "csrc", "lu.hip"), "rb").read()
+    except OSError:
+        return None
+    h = re.search(r"lu\.hip sha256 = ([0-9a-f]{64})", text)
+    b = re.search(r"lu traffic bytes per factorization = (\d+)", text)
+    if not h or not b or h.group(1) != hashlib.sha256(src).hexdigest():
+        return None
+    return int(b.group(1))
+
+
 def workload():
     from workloads import geometry, incident, rules
     curve = geometry.spheroid(64, 3.0)
@@ -272,8 +291,8 @@ def main():
                     kernel="msv_tabulate (tabulate_kernel far + near launches)",
                     algorithmic_bytes=entries * 16)
     roof_lu = dict(bound="mfma", achieved=round(lu_tfs, 2), peak=FP32_MFMA_PEAK_TF, unit="TFLOP/s",
-                   frac=round(lu_tfs / FP32_MFMA_PEAK_TF, 4), traffic=None,
-                   kernel="msv_factor (complex64 LU: base_panel, laswp, trsm_lu, gemm_update)",
+                   frac=round(lu_tfs / FP32_MFMA_PEAK_TF, 4), traffic=lu_traffic(),
+                   kernel="msv_factor (complex64 LU: base_panel, laswp, trsm, gemm_update_c)",
                    algorithmic_flops=lu_flops)
     dominant = roof_lu if fac_ms >= tab_ms else roof_tab
 
