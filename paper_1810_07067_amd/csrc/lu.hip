@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void laswp(Mats<T> B, int k1, int k2, int cb, 
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int k, int h,
-                                                  typename V2<R>::T* linv) {
+                                                  typename V2<R>::T* linv, int slot) {
   using T = typename V2<R>::T;
   __shared__ T Ls[64][65];
   __shared__ T Y[64][65];
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  T* out = linv + (size_t)blockIdx.z * 64 * 64;
+  T* out = linv + ((size_t)blockIdx.z * kLinvSlots + slot) * 64 * 64;
   for (int e = tid; e < 64 * 64; e += 256) out[e] = Y[e >> 6][e & 63];
 }
 
@@ -375,7 +375,7 @@ template <typename R> struct Mfma;
 
 template <typename R>
 __global__ __launch_bounds__(256) void trsm_inv(Mats<typename V2<R>::T> B, int k, int h, int cb, int ce,
-                                                const typename V2<R>::T* linv) {
+                                                const typename V2<R>::T* linv, int slot) {
   using T = typename V2<R>::T;
   using C4 = typename Mfma<R>::C4;
   __shared__ T Xs[64][65];  // [row][col]
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void trsm_inv(Mats<typename V2<R>::T> B, int k
   if (k >= n) return;
   if (ce < 0) ce = n;
   T* M = mz.a;
-  const T* Li = linv + (size_t)blockIdx.z * 64 * 64;
+  const T* Li = linv + ((size_t)blockIdx.z * kLinvSlots + slot) * 64 * 64;
   const int c0 = cb + blockIdx.x * 64;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int e = tid; e < 64 * 64; e += 256) {
@@ -726,7 +726,7 @@ struct Batch {
   Mats<T> d;
   int nb;
   int nmax;
-  T* linv;  // [nb][64][64] workspace
+  T* linv;  // [nb][kLinvSlots][64][64] diagonal-block inverses
 };
 
 // C[r0:rend, c0:cend] -= A[r0:rend, k0:k0+K] * A[k0:k0+K, c0:cend]; rend or
@@ -753,38 +753,40 @@ hipError_t swaps(const Batch<typename V2<R>::T>& b, int k1, int k2, int cb, int 
   return hipGetLastError();
 }
 
-// X = A[k:k+h, cb:ce] <- L^{-1} X with L the unit-lower A[k:k+h, k:k+h];
-// ce -1 = the matrix order (row block of an outer step), otherwise the
-// columns lie inside a panel (at most 64).
+// X = A[k:k+h, cb:ce] <- L^{-1} X with L the unit-lower A[k:k+h, k:k+h]; ce -1
+// = the matrix order.  Blocks of 64 rows and more (64-aligned from the outer
+// panel start k0), and every row block of an outer step, go in 64-row pieces:
+// each piece is multiplied by the inverse of its diagonal block (formed when
+// its 64-column sub-panel was finished, or here for a shorter last piece),
+// with a GEMM update of the rows below in between.  Shorter in-panel blocks
+// are solved by register substitution.
 template <typename R>
-hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce, hipStream_t s) {
+hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce, int k0, hipStream_t s) {
   const int cmax = ce < 0 ? b.nmax : ce;
   if (cmax <= cb || h <= 0) return hipSuccess;
-  if (ce >= 0 && h > 64) {  // taller in-panel block: 64-row blocks, updates between
+  if (h >= 64 || ce < 0) {
+    if ((k - k0) % 64 != 0 || k + h - k0 > 64 * kLinvSlots) return hipErrorInvalidValue;
     for (int kk = k; kk < k + h; kk += 64) {
       const int hh = k + h - kk < 64 ? k + h - kk : 64;
-      hipError_t e = trsm<R>(b, kk, hh, cb, ce, s);
+      const int slot = (kk - k0) / 64;
+      if (hh < 64)
+        hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, kk, hh, b.linv, slot);
+      hipLaunchKernelGGL(trsm_inv<R>, dim3((cmax - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, b.d, kk, hh, cb, ce,
+                         b.linv, slot);
+      hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       if (kk + hh < k + h && (e = gemm<R>(b, kk + hh, k + h, cb, ce, kk, hh, s)) != hipSuccess) return e;
     }
     return hipSuccess;
   }
-  if (h > 64) return hipErrorInvalidValue;
-  if (ce >= 0) {  // inside a panel: register substitution, no inverse
-    dim3 g((ce - cb + 63) / 64, 1, b.nb);
-    switch (h) {
-      case 4: hipLaunchKernelGGL((trsm_small<R, 4>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
-      case 8: hipLaunchKernelGGL((trsm_small<R, 8>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
-      case 16: hipLaunchKernelGGL((trsm_small<R, 16>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
-      case 32: hipLaunchKernelGGL((trsm_small<R, 32>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
-      case 64: hipLaunchKernelGGL((trsm_small<R, 64>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
-      default: return hipErrorInvalidValue;  // panel halves are powers of two
-    }
-    return hipGetLastError();
+  dim3 g((ce - cb + 63) / 64, 1, b.nb);
+  switch (h) {
+    case 4: hipLaunchKernelGGL((trsm_small<R, 4>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+    case 8: hipLaunchKernelGGL((trsm_small<R, 8>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+    case 16: hipLaunchKernelGGL((trsm_small<R, 16>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+    case 32: hipLaunchKernelGGL((trsm_small<R, 32>), g, dim3(256), 0, s, b.d, k, cb, ce); break;
+    default: return hipErrorInvalidValue;  // panel halves are powers of two
   }
-  hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, k, h, b.linv);
-  hipLaunchKernelGGL(trsm_inv<R>, dim3((cmax - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, b.d, k, h, cb, ce,
-                     b.linv);
   return hipGetLastError();
 }
 
@@ -796,7 +798,7 @@ hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce,
 
 // Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
 template <typename R>
-hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, hipStream_t s) {
+hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, int k0, hipStream_t s) {
   // strips of 8 columns while they fit the registers (complex64 up to 4 rows
   // per thread, complex128 up to 2), else 4; every width <= 4 is a base case.
   // (16 columns fit at 2 rows per thread but ran slower: the unrolled column
@@ -830,13 +832,18 @@ hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, hipStream
     }
   }
   int h = w / 2;
-  MSV_TRY(panel_rec<R>(b, c0, h, s));
+  MSV_TRY(panel_rec<R>(b, c0, h, k0, s));
   MSV_TRY(swaps<R>(b, c0, c0 + h, c0 + h, c0 + w, s));
-  MSV_TRY(trsm<R>(b, c0, h, c0 + h, c0 + w, s));
+  MSV_TRY(trsm<R>(b, c0, h, c0 + h, c0 + w, k0, s));
   MSV_TRY(gemm<R>(b, c0 + h, -1, c0 + h, c0 + w, c0, h, s));
-  MSV_TRY(panel_rec<R>(b, c0 + h, w - h, s));
+  MSV_TRY(panel_rec<R>(b, c0 + h, w - h, k0, s));
   // swaps of the right half also apply to the left half of the panel
   MSV_TRY(swaps<R>(b, c0 + h, c0 + w, c0, c0 + h, s));
+  if (w == 64 && (c0 - k0) % 64 == 0) {
+    // a finished 64-wide sub-panel: keep the inverse of its unit-lower block
+    hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, c0, 64, b.linv, (c0 - k0) / 64);
+    MSV_TRY(hipGetLastError());
+  }
   return hipSuccess;
 }
 
@@ -860,15 +867,11 @@ hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
     // the register strips): the largest one not above what is left
     int w = n - k < NB ? n - k : NB;
     while (w & (w - 1)) w &= w - 1;
-    MSV_TRY(panel_rec<R>(b, k, w, s));
+    MSV_TRY(panel_rec<R>(b, k, w, k, s));
     MSV_TRY(swaps<R>(b, k, k + w, 0, k, s));
     MSV_TRY(swaps<R>(b, k, k + w, k + w, -1, s));
-    // U12 = L11^{-1} A12 in blocks of 64 rows, then A22
-    for (int kk = k; kk < k + w; kk += 64) {
-      int h = k + w - kk < 64 ? k + w - kk : 64;
-      MSV_TRY(trsm<R>(b, kk, h, k + w, -1, s));
-      if (kk + h < k + w) MSV_TRY(gemm<R>(b, kk + h, k + w, k + w, -1, kk, h, s));
-    }
+    // U12 = L11^{-1} A12 by 64-row pieces, then A22
+    MSV_TRY(trsm<R>(b, k, w, k + w, -1, k, s));
     MSV_TRY(gemm<R>(b, k + w, -1, k + w, -1, k, w, s));
     k += w;
   }

@@ -65,6 +65,11 @@ hipError_t launch_tabulate(const TabParams& p, hipStream_t s);
 hipError_t launch_assemble(const AsmParams& p, hipStream_t s);
 
 // Batched dense LU / solve (row-major, complex), see lu.hip.
+// Inverses of 64 x 64 unit-lower diagonal blocks kept per matrix by the LU:
+// one slot per 64-row piece of a 256-column outer panel.  The LU workspace
+// passed to lu_factor_* holds nb * kLinvSlots * 64 * 64 elements.
+constexpr int kLinvSlots = 4;
+
 struct LuBatch {
   int n;           // matrix order
   int nb;          // number of matrices
