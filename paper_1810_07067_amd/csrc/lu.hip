@@ -719,6 +719,172 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
       }
 }
 
+// complex64 trailing update on bf16 MFMA.  Every fp32 operand x is split as
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (|x - hi - lo| <=
+// 2^-17 |x|), and each real product is formed as hi hi + hi lo + lo hi in fp32
+// accumulators: about 16 bits of the product, against 24 of fp32.  With the
+// three real products of 3M (Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)) that is 9 bf16
+// MFMAs per complex product, at 16 times the fp32 MFMA rate.  The factors
+// only precondition the complex128 refinement, whose residual removes the
+// difference.
+//
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8 (l / 16) + t] and
+// B[8 (l / 16) + t][l % 16], t < 8, and holds C[4 (l / 16) + i][l % 16].
+// Both tiles are staged in LDS as six bf16 planes (re, im, re + im; hi, lo) of
+// [64][kBP] with k contiguous (B transposed), so each operand is one 16-byte
+// read; the row stride of 40 keeps the reads and writes of 16 lanes on
+// distinct banks.  K chunk 32, K a multiple of 32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kBK = 32, kBP = 40;
+
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const __bf16 h = (__bf16)x[t];
+    hi[t] = h;
+    lo[t] = (__bf16)(x[t] - (float)h);
+  }
+}
+
+__global__ __launch_bounds__(256) void gemm_update_bf(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
+                                                      int K) {
+  using C4 = Mfma<float>::C4;
+  __shared__ __attribute__((aligned(16))) __bf16 As[6][kGT][kBP];  // re hi, re lo, im hi, im lo, s hi, s lo
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[6][kGT][kBP];  // [col][k]
+  const Mz<float2> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (rend < 0) rend = n;
+  if (cend < 0) cend = n;
+  const int tr = r0 + blockIdx.y * kGT;
+  const int tc = c0 + blockIdx.x * kGT;
+  if (k0 >= n || tr >= rend || tc >= cend) return;
+  float2* M = mz.a;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lq = lane >> 4;
+  C4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      t1[a][b] = C4{0, 0, 0, 0};
+      t2[a][b] = C4{0, 0, 0, 0};
+      t3[a][b] = C4{0, 0, 0, 0};
+    }
+  const int kend = k0 + K;
+  // staging: thread -> (row or column rc, k range 8 kq .. 8 kq + 7); loads are
+  // unconditional (an out-of-range row or column reads row or column 0 of the
+  // tile's matrix) and masked when converted
+  const int rc = tid & 63, kq = tid >> 6;
+  const bool oka = tr + rc < rend, okb = tc + rc < cend;
+  const float2* pa = M + (size_t)(oka ? tr + rc : 0) * n + 8 * kq;
+  const float2* pb = M + (size_t)(8 * kq) * n + (okb ? tc + rc : 0);
+  float4 ra[4];
+  float2 rb[8];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = reinterpret_cast<const float4*>(pa + kc)[q];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) rb[t] = pb[(size_t)(kc + t) * n];
+  };
+  fetch(k0);
+  for (int kc = k0; kc < kend; kc += kBK) {
+    {
+      float re[8], im[8], sm[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        re[2 * q] = oka ? ra[q].x : 0.f;
+        im[2 * q] = oka ? ra[q].y : 0.f;
+        re[2 * q + 1] = oka ? ra[q].z : 0.f;
+        im[2 * q + 1] = oka ? ra[q].w : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) sm[t] = re[t] + im[t];
+      bf16x8 h, l;
+      split8(re, h, l);
+      *reinterpret_cast<bf16x8*>(&As[0][rc][8 * kq]) = h;
+      *reinterpret_cast<bf16x8*>(&As[1][rc][8 * kq]) = l;
+      split8(im, h, l);
+      *reinterpret_cast<bf16x8*>(&As[2][rc][8 * kq]) = h;
+      *reinterpret_cast<bf16x8*>(&As[3][rc][8 * kq]) = l;
+      split8(sm, h, l);
+      *reinterpret_cast<bf16x8*>(&As[4][rc][8 * kq]) = h;
+      *reinterpret_cast<bf16x8*>(&As[5][rc][8 * kq]) = l;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        re[t] = okb ? rb[t].x : 0.f;
+        im[t] = okb ? rb[t].y : 0.f;
+        sm[t] = re[t] + im[t];
+      }
+      split8(re, h, l);
+      *reinterpret_cast<bf16x8*>(&Bs[0][rc][8 * kq]) = h;
+      *reinterpret_cast<bf16x8*>(&Bs[1][rc][8 * kq]) = l;
+      split8(im, h, l);
+      *reinterpret_cast<bf16x8*>(&Bs[2][rc][8 * kq]) = h;
+      *reinterpret_cast<bf16x8*>(&Bs[3][rc][8 * kq]) = l;
+      split8(sm, h, l);
+      *reinterpret_cast<bf16x8*>(&Bs[4][rc][8 * kq]) = h;
+      *reinterpret_cast<bf16x8*>(&Bs[5][rc][8 * kq]) = l;
+    }
+    __syncthreads();
+    if (kc + kBK < kend) fetch(kc + kBK);
+    // the three real products; plane pairs (0, 1) re, (2, 3) im, (4, 5) re + im
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) {
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ah[a] = *reinterpret_cast<const bf16x8*>(&As[2 * pr][wr + 16 * a + li][8 * lq]);
+        al[a] = *reinterpret_cast<const bf16x8*>(&As[2 * pr + 1][wr + 16 * a + li][8 * lq]);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bh[b] = *reinterpret_cast<const bf16x8*>(&Bs[2 * pr][wc + 16 * b + li][8 * lq]);
+        bl[b] = *reinterpret_cast<const bf16x8*>(&Bs[2 * pr + 1][wc + 16 * b + li][8 * lq]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          C4& t = pr == 0 ? t1[a][b] : pr == 1 ? t2[a][b] : t3[a][b];
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], t, 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  // C -= A B: all 16 loads issued before the first subtraction
+  float2 cv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + 4 * lq + i;
+        const int gc = tc + wc + 16 * b + li;
+        const bool ok = gr < rend && gc < cend;
+        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
+      }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + 4 * lq + i;
+        const int gc = tc + wc + 16 * b + li;
+        if (gr < rend && gc < cend) {
+          float2 v = cv[a][b][i];
+          v.x -= t1[a][b][i] - t2[a][b][i];
+          v.y -= t3[a][b][i] - t1[a][b][i] - t2[a][b][i];
+          M[(size_t)gr * n + gc] = v;
+        }
+      }
+}
+
 // Host view of a batch: the device descriptor plus its count and the
 // largest order (which sizes the grids).
 template <typename T>
@@ -737,9 +903,12 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
   const int Mr = (rend < 0 ? b.nmax : rend) - r0, Nc = (cend < 0 ? b.nmax : cend) - c0;
   if (Mr <= 0 || Nc <= 0 || K <= 0) return hipSuccess;
   dim3 g((Nc + kGT - 1) / kGT, (Mr + kGT - 1) / kGT, b.nb);
-  if constexpr (sizeof(R) == 4)
-    hipLaunchKernelGGL(gemm_update_c, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
-  else
+  if constexpr (sizeof(R) == 4) {
+    if (K % kBK == 0)
+      hipLaunchKernelGGL(gemm_update_bf, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
+    else
+      hipLaunchKernelGGL(gemm_update_c, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
+  } else
     hipLaunchKernelGGL(gemm_update<R>, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
   return hipGetLastError();
 }
