@@ -732,10 +732,12 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
 // B[8 (l / 16) + t][l % 16], t < 8, and holds C[4 (l / 16) + i][l % 16].
 // Both tiles are staged in LDS as six bf16 planes (re, im, re + im; hi, lo) of
 // [64][kBP] with k contiguous (B transposed), so each operand is one 16-byte
-// read; the row stride of 40 keeps the reads and writes of 16 lanes on
-// distinct banks.  K chunk 32, K a multiple of 32.
+// read.  Rows are padded from 32 to 48 elements (96 bytes): measured on the
+// 128 x 128 kernel at K = 256, strides of 36 and 44 run at half the rate of
+// 40 and 48 (16-byte reads that straddle a 16-byte boundary), and 48 is a
+// little ahead of 40.  K chunk 32, K a multiple of 32.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int kBK = 32, kBP = 40;
+constexpr int kBK = 32, kBP = 48;
 
 __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
 #pragma unroll
@@ -885,6 +887,150 @@ __global__ __launch_bounds__(256) void gemm_update_bf(Mats<float2> B, int r0, in
       }
 }
 
+// The same product on 128 x 128 tiles for the large trailing updates: each
+// wave computes 64 x 64 (4 x 4 MFMA blocks), reading a third as many LDS
+// bytes per MFMA as the 64 x 64 tile.  Staging in dynamic LDS (2 x 6 planes
+// of [128][kBP] bf16, 144 KB), accumulators in AGPRs; one workgroup per CU.
+constexpr int kBT = 128;
+constexpr size_t kBfLds = 2 * 6 * kBT * kBP * sizeof(__bf16);
+
+__global__ __launch_bounds__(256) void gemm_update_bf2(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
+                                                       int K) {
+  using C4 = Mfma<float>::C4;
+  extern __shared__ __attribute__((aligned(16))) __bf16 lds_bf[];
+  __bf16 (*As)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf);
+  __bf16 (*Bs)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf + 6 * kBT * kBP);
+  const Mz<float2> mz = mat_at(B, blockIdx.z);
+  const int n = mz.n;
+  if (rend < 0) rend = n;
+  if (cend < 0) cend = n;
+  const int tr = r0 + blockIdx.y * kBT;
+  const int tc = c0 + blockIdx.x * kBT;
+  if (k0 >= n || tr >= rend || tc >= cend) return;
+  float2* M = mz.a;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int li = lane & 15, lq = lane >> 4;
+  C4 t1[4][4], t2[4][4], t3[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      t1[a][b] = C4{0, 0, 0, 0};
+      t2[a][b] = C4{0, 0, 0, 0};
+      t3[a][b] = C4{0, 0, 0, 0};
+    }
+  const int kend = k0 + K;
+  // staging: thread -> (row or column rc, k range 16 kh .. 16 kh + 15)
+  const int rc = tid & 127, kh = tid >> 7;
+  const bool oka = tr + rc < rend, okb = tc + rc < cend;
+  const float2* pa = M + (size_t)(oka ? tr + rc : 0) * n + 16 * kh;
+  const float2* pb = M + (size_t)(16 * kh) * n + (okb ? tc + rc : 0);
+  float4 ra[8];
+  float2 rb[16];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = reinterpret_cast<const float4*>(pa + kc)[q];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) rb[t] = pb[(size_t)(kc + t) * n];
+  };
+  fetch(k0);
+  for (int kc = k0; kc < kend; kc += kBK) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      float re[8], im[8], sm[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = ra[4 * g + q];
+        re[2 * q] = oka ? v.x : 0.f;
+        im[2 * q] = oka ? v.y : 0.f;
+        re[2 * q + 1] = oka ? v.z : 0.f;
+        im[2 * q + 1] = oka ? v.w : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) sm[t] = re[t] + im[t];
+      const int kk = 16 * kh + 8 * g;
+      bf16x8 h, l;
+      split8(re, h, l);
+      *reinterpret_cast<bf16x8*>(&As[0][rc][kk]) = h;
+      *reinterpret_cast<bf16x8*>(&As[1][rc][kk]) = l;
+      split8(im, h, l);
+      *reinterpret_cast<bf16x8*>(&As[2][rc][kk]) = h;
+      *reinterpret_cast<bf16x8*>(&As[3][rc][kk]) = l;
+      split8(sm, h, l);
+      *reinterpret_cast<bf16x8*>(&As[4][rc][kk]) = h;
+      *reinterpret_cast<bf16x8*>(&As[5][rc][kk]) = l;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        re[t] = okb ? rb[8 * g + t].x : 0.f;
+        im[t] = okb ? rb[8 * g + t].y : 0.f;
+        sm[t] = re[t] + im[t];
+      }
+      split8(re, h, l);
+      *reinterpret_cast<bf16x8*>(&Bs[0][rc][kk]) = h;
+      *reinterpret_cast<bf16x8*>(&Bs[1][rc][kk]) = l;
+      split8(im, h, l);
+      *reinterpret_cast<bf16x8*>(&Bs[2][rc][kk]) = h;
+      *reinterpret_cast<bf16x8*>(&Bs[3][rc][kk]) = l;
+      split8(sm, h, l);
+      *reinterpret_cast<bf16x8*>(&Bs[4][rc][kk]) = h;
+      *reinterpret_cast<bf16x8*>(&Bs[5][rc][kk]) = l;
+    }
+    __syncthreads();
+    if (kc + kBK < kend) fetch(kc + kBK);
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) {
+      bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        ah[a] = *reinterpret_cast<const bf16x8*>(&As[2 * pr][wr + 16 * a + li][8 * lq]);
+        al[a] = *reinterpret_cast<const bf16x8*>(&As[2 * pr + 1][wr + 16 * a + li][8 * lq]);
+        bh[a] = *reinterpret_cast<const bf16x8*>(&Bs[2 * pr][wc + 16 * a + li][8 * lq]);
+        bl[a] = *reinterpret_cast<const bf16x8*>(&Bs[2 * pr + 1][wc + 16 * a + li][8 * lq]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          C4& t = pr == 0 ? t1[a][b] : pr == 1 ? t2[a][b] : t3[a][b];
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], t, 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  // C -= A B, one block row at a time: its 16 loads issued before the first
+  // subtraction
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float2 cv[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + 4 * lq + i;
+        const int gc = tc + wc + 16 * b + li;
+        const bool ok = gr < rend && gc < cend;
+        cv[b][i] = M[ok ? (size_t)gr * n + gc : 0];
+      }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + 4 * lq + i;
+        const int gc = tc + wc + 16 * b + li;
+        if (gr < rend && gc < cend) {
+          float2 v = cv[b][i];
+          v.x -= t1[a][b][i] - t2[a][b][i];
+          v.y -= t3[a][b][i] - t1[a][b][i] - t2[a][b][i];
+          M[(size_t)gr * n + gc] = v;
+        }
+      }
+  }
+}
+
 // Host view of a batch: the device descriptor plus its count and the
 // largest order (which sizes the grids).
 template <typename T>
@@ -904,7 +1050,13 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
   if (Mr <= 0 || Nc <= 0 || K <= 0) return hipSuccess;
   dim3 g((Nc + kGT - 1) / kGT, (Mr + kGT - 1) / kGT, b.nb);
   if constexpr (sizeof(R) == 4) {
-    if (K % kBK == 0)
+    if (K % kBK == 0 && Mr >= 2 * kBT && Nc >= 2 * kBT) {
+      static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_update_bf2),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBfLds);
+      if (attr != hipSuccess) return attr;
+      dim3 g2((Nc + kBT - 1) / kBT, (Mr + kBT - 1) / kBT, b.nb);
+      hipLaunchKernelGGL(gemm_update_bf2, g2, dim3(256), kBfLds, s, b.d, r0, rend, c0, cend, k0, K);
+    } else if (K % kBK == 0)
       hipLaunchKernelGGL(gemm_update_bf, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
     else
       hipLaunchKernelGGL(gemm_update_c, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
