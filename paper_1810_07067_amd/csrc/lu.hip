@@ -887,25 +887,117 @@ __global__ __launch_bounds__(256) void gemm_update_bf(Mats<float2> B, int r0, in
       }
 }
 
-// The same product on 128 x 128 tiles for the large trailing updates: each
-// wave computes 64 x 64 (4 x 4 MFMA blocks), reading a third as many LDS
-// bytes per MFMA as the 64 x 64 tile.  Staging in dynamic LDS (2 x 6 planes
-// of [128][kBP] bf16, 144 KB), accumulators in AGPRs; one workgroup per CU.
-constexpr int kBT = 128;
-constexpr size_t kBfLds = 2 * 6 * kBT * kBP * sizeof(__bf16);
-
-__global__ __launch_bounds__(256) void gemm_update_bf2(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
-                                                       int K) {
-  using C4 = Mfma<float>::C4;
-  extern __shared__ __attribute__((aligned(16))) __bf16 lds_bf[];
-  __bf16 (*As)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf);
-  __bf16 (*Bs)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf + 6 * kBT * kBP);
+// The same product on 128 x 128 tiles for the large trailing updates, fed
+// from operands split once per update instead of once per tile.
+// split_planes writes A = M[r0:rend, k0:k0+K] and B = M[k0:k0+K, c0:cend]
+// as six bf16 planes each (re hi, re lo, im hi, im lo, (re + im) hi,
+// (re + im) lo): P[c][p][i][t] is plane p of element 32 c + t of row i of A,
+// or of column i of B, with rows (columns) past the block zero up to RA (RB),
+// multiples of 128.  Per matrix the planes of A take 6 RA K elements, those
+// of B the next 6 RB K; matrices are ws_stride elements apart.  The values
+// are those the tile kernels form, so the products are the same bit for bit.
+__global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
+                                                    int K, __bf16* ws, size_t ws_stride, int RA, int RB) {
   const Mz<float2> mz = mat_at(B, blockIdx.z);
   const int n = mz.n;
   if (rend < 0) rend = n;
   if (cend < 0) cend = n;
-  const int tr = r0 + blockIdx.y * kBT;
-  const int tc = c0 + blockIdx.x * kBT;
+  const int c = blockIdx.y;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const bool live = k0 < n;
+  __bf16* w = global_ptr(ws + blockIdx.z * ws_stride);
+  float re[8], im[8], sm[8];
+  __bf16* out;
+  size_t pstride;
+  if (g < 4 * RA) {
+    // A: 4 threads per row, 8 consecutive k each
+    const int i = g >> 2, q = g & 3;
+    const bool ok = live && r0 + i < rend;
+    const float4* src = reinterpret_cast<const float4*>(mz.a + (size_t)(ok ? r0 + i : 0) * n + k0 + 32 * c + 8 * q);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float4 v = src[t];
+      re[2 * t] = ok ? v.x : 0.f;
+      im[2 * t] = ok ? v.y : 0.f;
+      re[2 * t + 1] = ok ? v.z : 0.f;
+      im[2 * t + 1] = ok ? v.w : 0.f;
+    }
+    out = w + ((size_t)c * 6 * RA + i) * 32 + 8 * q;
+    pstride = (size_t)RA * 32;
+  } else {
+    // B: consecutive threads take consecutive columns
+    const int gb = g - 4 * RA;
+    const int j = gb % RB, q = gb / RB;
+    const bool ok = live && c0 + j < cend;
+    const float2* src = mz.a + (size_t)(k0 + 32 * c + 8 * q) * n + (ok ? c0 + j : 0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const float2 v = ok ? src[(size_t)t * n] : make_float2(0.f, 0.f);
+      re[t] = v.x;
+      im[t] = v.y;
+    }
+    out = w + (size_t)6 * RA * K + ((size_t)c * 6 * RB + j) * 32 + 8 * q;
+    pstride = (size_t)RB * 32;
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) sm[t] = re[t] + im[t];
+  bf16x8 h, l;
+  split8(re, h, l);
+  *reinterpret_cast<bf16x8*>(out) = h;
+  *reinterpret_cast<bf16x8*>(out + pstride) = l;
+  split8(im, h, l);
+  *reinterpret_cast<bf16x8*>(out + 2 * pstride) = h;
+  *reinterpret_cast<bf16x8*>(out + 3 * pstride) = l;
+  split8(sm, h, l);
+  *reinterpret_cast<bf16x8*>(out + 4 * pstride) = h;
+  *reinterpret_cast<bf16x8*>(out + 5 * pstride) = l;
+}
+
+// C -= A B on 128 x 128 tiles from the planes: each wave computes 64 x 64
+// (4 x 4 MFMA blocks), reading a third as many LDS bytes per MFMA as the
+// 64 x 64 tile.  A K chunk is 12 16-byte pieces of A and 12 of B per thread,
+// loaded one chunk ahead and copied to LDS unchanged; staging in dynamic LDS
+// (2 x 6 planes of [128][kBP] bf16, 144 KB), accumulators in AGPRs; one
+// workgroup per CU.
+constexpr int kBT = 128;
+constexpr size_t kBfLds = 2 * 6 * kBT * kBP * sizeof(__bf16);
+
+// Workgroup -> (column tile x, row tile y, matrix z) of a 1-D grid of
+// nb TY TX tiles.  The hardware hands workgroups to the 8 XCDs round-robin
+// (id mod 8); each XCD instead takes a contiguous range of tiles, walked down
+// a group of kGY row tiles, then across the columns.  The workgroups resident
+// on one XCD then share a few row tiles of A and column tiles of B in its L2,
+// where round-robin order spreads every tile over all eight.
+constexpr int kGY = 4;
+__device__ __forceinline__ void update_tile(int TX, int TY, int& x, int& y, int& z) {
+  const int T = (int)gridDim.x, L = (int)blockIdx.x;
+  const int base = T >> 3, rem = T & 7, xcd = L & 7;
+  const int id = xcd * base + (xcd < rem ? xcd : rem) + (L >> 3);
+  const int per = TX * TY;
+  z = id / per;
+  const int l = id - z * per;
+  const int y0 = l / (kGY * TX) * kGY;
+  const int gh = TY - y0 < kGY ? TY - y0 : kGY;
+  const int r = l - y0 * TX;
+  y = y0 + r % gh;
+  x = r / gh;
+}
+
+__global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
+                                                          int K, const __bf16* ws, size_t ws_stride, int RA,
+                                                          int RB) {
+  using C4 = Mfma<float>::C4;
+  extern __shared__ __attribute__((aligned(16))) __bf16 lds_bf[];
+  __bf16 (*As)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf);
+  __bf16 (*Bs)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf + 6 * kBT * kBP);
+  int bx, by, bz;
+  update_tile(RB / kBT, RA / kBT, bx, by, bz);
+  const Mz<float2> mz = mat_at(B, bz);
+  const int n = mz.n;
+  if (rend < 0) rend = n;
+  if (cend < 0) cend = n;
+  const int tr = r0 + by * kBT;
+  const int tc = c0 + bx * kBT;
   if (k0 >= n || tr >= rend || tc >= cend) return;
   float2* M = mz.a;
   const int tid = threadIdx.x;
@@ -921,64 +1013,27 @@ __global__ __launch_bounds__(256) void gemm_update_bf2(Mats<float2> B, int r0, i
       t2[a][b] = C4{0, 0, 0, 0};
       t3[a][b] = C4{0, 0, 0, 0};
     }
-  const int kend = k0 + K;
-  // staging: thread -> (row or column rc, k range 16 kh .. 16 kh + 15)
-  const int rc = tid & 127, kh = tid >> 7;
-  const bool oka = tr + rc < rend, okb = tc + rc < cend;
-  const float2* pa = M + (size_t)(oka ? tr + rc : 0) * n + 16 * kh;
-  const float2* pb = M + (size_t)(16 * kh) * n + (okb ? tc + rc : 0);
-  float4 ra[8];
-  float2 rb[16];
-  auto fetch = [&](int kc) {
+  // piece v of a chunk: plane v / 2, row 64 (v % 2) + tid / 4, k 8 (tid % 4)
+  const int sr = tid >> 2, sq = 8 * (tid & 3);
+  const __bf16* wa = global_ptr(ws + bz * ws_stride) + ((size_t)by * kBT + sr) * 32 + sq;
+  const __bf16* wb = global_ptr(ws + bz * ws_stride) + (size_t)6 * RA * K + ((size_t)bx * kBT + sr) * 32 + sq;
+  bf16x8 ra[12], rb[12];
+  auto fetch = [&](int c) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) ra[q] = reinterpret_cast<const float4*>(pa + kc)[q];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) rb[t] = pb[(size_t)(kc + t) * n];
-  };
-  fetch(k0);
-  for (int kc = k0; kc < kend; kc += kBK) {
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      float re[8], im[8], sm[8];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 v = ra[4 * g + q];
-        re[2 * q] = oka ? v.x : 0.f;
-        im[2 * q] = oka ? v.y : 0.f;
-        re[2 * q + 1] = oka ? v.z : 0.f;
-        im[2 * q + 1] = oka ? v.w : 0.f;
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) sm[t] = re[t] + im[t];
-      const int kk = 16 * kh + 8 * g;
-      bf16x8 h, l;
-      split8(re, h, l);
-      *reinterpret_cast<bf16x8*>(&As[0][rc][kk]) = h;
-      *reinterpret_cast<bf16x8*>(&As[1][rc][kk]) = l;
-      split8(im, h, l);
-      *reinterpret_cast<bf16x8*>(&As[2][rc][kk]) = h;
-      *reinterpret_cast<bf16x8*>(&As[3][rc][kk]) = l;
-      split8(sm, h, l);
-      *reinterpret_cast<bf16x8*>(&As[4][rc][kk]) = h;
-      *reinterpret_cast<bf16x8*>(&As[5][rc][kk]) = l;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        re[t] = okb ? rb[8 * g + t].x : 0.f;
-        im[t] = okb ? rb[8 * g + t].y : 0.f;
-        sm[t] = re[t] + im[t];
-      }
-      split8(re, h, l);
-      *reinterpret_cast<bf16x8*>(&Bs[0][rc][kk]) = h;
-      *reinterpret_cast<bf16x8*>(&Bs[1][rc][kk]) = l;
-      split8(im, h, l);
-      *reinterpret_cast<bf16x8*>(&Bs[2][rc][kk]) = h;
-      *reinterpret_cast<bf16x8*>(&Bs[3][rc][kk]) = l;
-      split8(sm, h, l);
-      *reinterpret_cast<bf16x8*>(&Bs[4][rc][kk]) = h;
-      *reinterpret_cast<bf16x8*>(&Bs[5][rc][kk]) = l;
+    for (int v = 0; v < 12; ++v) {
+      ra[v] = *reinterpret_cast<const bf16x8*>(wa + ((size_t)(6 * c + (v >> 1)) * RA + 64 * (v & 1)) * 32);
+      rb[v] = *reinterpret_cast<const bf16x8*>(wb + ((size_t)(6 * c + (v >> 1)) * RB + 64 * (v & 1)) * 32);
     }
-    __syncthreads();
-    if (kc + kBK < kend) fetch(kc + kBK);
+  };
+  const int nc = K / kBK;
+  auto stage = [&]() {
+#pragma unroll
+    for (int v = 0; v < 12; ++v) {
+      *reinterpret_cast<bf16x8*>(&As[v >> 1][64 * (v & 1) + sr][sq]) = ra[v];
+      *reinterpret_cast<bf16x8*>(&Bs[v >> 1][64 * (v & 1) + sr][sq]) = rb[v];
+    }
+  };
+  auto products = [&]() {
 #pragma unroll
     for (int pr = 0; pr < 3; ++pr) {
       bf16x8 ah[4], al[4], bh[4], bl[4];
@@ -999,13 +1054,22 @@ __global__ __launch_bounds__(256) void gemm_update_bf2(Mats<float2> B, int r0, i
           t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], t, 0, 0, 0);
         }
     }
+  };
+  fetch(0);
+  for (int c = 0; c + 1 < nc; ++c) {
+    stage();
+    __syncthreads();
+    fetch(c + 1);
+    products();
     __syncthreads();
   }
-  // C -= A B, one block row at a time: its 16 loads issued before the first
-  // subtraction
+  stage();
+  __syncthreads();
+  // the wave's 64 x 64 block of C is loaded while the last chunk's products
+  // run, in one round trip to memory
+  float2 cv[4][4][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    float2 cv[4][4];
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -1013,8 +1077,11 @@ __global__ __launch_bounds__(256) void gemm_update_bf2(Mats<float2> B, int r0, i
         const int gr = tr + wr + 16 * a + 4 * lq + i;
         const int gc = tc + wc + 16 * b + li;
         const bool ok = gr < rend && gc < cend;
-        cv[b][i] = M[ok ? (size_t)gr * n + gc : 0];
+        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
       }
+  products();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -1022,13 +1089,12 @@ __global__ __launch_bounds__(256) void gemm_update_bf2(Mats<float2> B, int r0, i
         const int gr = tr + wr + 16 * a + 4 * lq + i;
         const int gc = tc + wc + 16 * b + li;
         if (gr < rend && gc < cend) {
-          float2 v = cv[b][i];
+          float2 v = cv[a][b][i];
           v.x -= t1[a][b][i] - t2[a][b][i];
           v.y -= t3[a][b][i] - t1[a][b][i] - t2[a][b][i];
           M[(size_t)gr * n + gc] = v;
         }
       }
-  }
 }
 
 // Host view of a batch: the device descriptor plus its count and the
@@ -1039,7 +1105,25 @@ struct Batch {
   int nb;
   int nmax;
   T* linv;  // [nb][kLinvSlots][64][64] diagonal-block inverses
+  __bf16* planes = nullptr;  // bf16 operand planes of the large complex64 updates
+  size_t planes_stride = 0;  // elements per matrix
 };
+
+// Workspace split: diagonal-block inverses, then (complex64) room for the
+// planes of one trailing update per matrix, 6 (RA + RB) K <= 12 R 256 with R
+// the largest order rounded up to 128.
+size_t linv_bytes(int nb, size_t elem) { return ((size_t)nb * kLinvSlots * 64 * 64 * elem + 255) / 256 * 256; }
+size_t planes_per_matrix(int n) { return (size_t)12 * ((n + kBT - 1) / kBT * kBT) * 256; }
+
+template <typename T>
+Batch<T> make_batch(const Mats<T>& d, int nb, int nmax, void* work) {
+  Batch<T> bt{d, nb, nmax, static_cast<T*>(work)};
+  if constexpr (sizeof(T) == 8) {
+    bt.planes = reinterpret_cast<__bf16*>(static_cast<char*>(work) + linv_bytes(nb, sizeof(T)));
+    bt.planes_stride = planes_per_matrix(nmax);
+  }
+  return bt;
+}
 
 // C[r0:rend, c0:cend] -= A[r0:rend, k0:k0+K] * A[k0:k0+K, c0:cend]; rend or
 // cend -1 = the matrix order.  The grid covers the largest order.
@@ -1050,12 +1134,16 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
   if (Mr <= 0 || Nc <= 0 || K <= 0) return hipSuccess;
   dim3 g((Nc + kGT - 1) / kGT, (Mr + kGT - 1) / kGT, b.nb);
   if constexpr (sizeof(R) == 4) {
-    if (K % kBK == 0 && Mr >= 2 * kBT && Nc >= 2 * kBT) {
-      static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_update_bf2),
+    const int RA = (Mr + kBT - 1) / kBT * kBT, RB = (Nc + kBT - 1) / kBT * kBT;
+    if (K % kBK == 0 && Mr >= 2 * kBT && Nc >= 2 * kBT && b.planes &&
+        (size_t)6 * (RA + RB) * K <= b.planes_stride) {
+      static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_update_planes),
                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBfLds);
       if (attr != hipSuccess) return attr;
-      dim3 g2((Nc + kBT - 1) / kBT, (Mr + kBT - 1) / kBT, b.nb);
-      hipLaunchKernelGGL(gemm_update_bf2, g2, dim3(256), kBfLds, s, b.d, r0, rend, c0, cend, k0, K);
+      hipLaunchKernelGGL(split_planes, dim3(4 * (RA + RB) / 256, K / kBK, b.nb), dim3(256), 0, s, b.d, r0, rend, c0,
+                         cend, k0, K, b.planes, b.planes_stride, RA, RB);
+      hipLaunchKernelGGL(gemm_update_planes, dim3((RB / kBT) * (RA / kBT) * b.nb), dim3(256), kBfLds, s, b.d, r0,
+                         rend, c0, cend, k0, K, b.planes, b.planes_stride, RA, RB);
     } else if (K % kBK == 0)
       hipLaunchKernelGGL(gemm_update_bf, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
     else
@@ -1074,31 +1162,39 @@ hipError_t swaps(const Batch<typename V2<R>::T>& b, int k1, int k2, int cb, int 
   return hipGetLastError();
 }
 
+#define MSV_TRY(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
 // X = A[k:k+h, cb:ce] <- L^{-1} X with L the unit-lower A[k:k+h, k:k+h]; ce -1
 // = the matrix order.  Blocks of 64 rows and more (64-aligned from the outer
-// panel start k0), and every row block of an outer step, go in 64-row pieces:
-// each piece is multiplied by the inverse of its diagonal block (formed when
-// its 64-column sub-panel was finished, or here for a shorter last piece),
-// with a GEMM update of the rows below in between.  Shorter in-panel blocks
-// are solved by register substitution.
+// panel start k0), and every row block of an outer step, are halved down to
+// 64-row pieces, with a GEMM update of the lower half by the upper one in
+// between; each piece is multiplied by the inverse of its diagonal block
+// (formed when its 64-column sub-panel was finished, or here for a shorter
+// last piece).  Shorter in-panel blocks are solved by register substitution.
 template <typename R>
 hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce, int k0, hipStream_t s) {
   const int cmax = ce < 0 ? b.nmax : ce;
   if (cmax <= cb || h <= 0) return hipSuccess;
   if (h >= 64 || ce < 0) {
     if ((k - k0) % 64 != 0 || k + h - k0 > 64 * kLinvSlots) return hipErrorInvalidValue;
-    for (int kk = k; kk < k + h; kk += 64) {
-      const int hh = k + h - kk < 64 ? k + h - kk : 64;
-      const int slot = (kk - k0) / 64;
-      if (hh < 64)
-        hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, kk, hh, b.linv, slot);
-      hipLaunchKernelGGL(trsm_inv<R>, dim3((cmax - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, b.d, kk, hh, cb, ce,
-                         b.linv, slot);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      if (kk + hh < k + h && (e = gemm<R>(b, kk + hh, k + h, cb, ce, kk, hh, s)) != hipSuccess) return e;
+    if (h > 64) {
+      // halves (the upper one a multiple of 64): solve the upper rows, update
+      // the lower ones with them, solve the lower rows -- the rows of the
+      // block pass through a product about log2(h / 64) times
+      const int h1 = (h / 2 + 63) / 64 * 64;
+      MSV_TRY(trsm<R>(b, k, h1, cb, ce, k0, s));
+      MSV_TRY(gemm<R>(b, k + h1, k + h, cb, ce, k, h1, s));
+      return trsm<R>(b, k + h1, h - h1, cb, ce, k0, s);
     }
-    return hipSuccess;
+    const int slot = (k - k0) / 64;
+    if (h < 64) hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, k, h, b.linv, slot);
+    hipLaunchKernelGGL(trsm_inv<R>, dim3((cmax - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, b.d, k, h, cb, ce, b.linv,
+                       slot);
+    return hipGetLastError();
   }
   dim3 g((ce - cb + 63) / 64, 1, b.nb);
   switch (h) {
@@ -1110,12 +1206,6 @@ hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce,
   }
   return hipGetLastError();
 }
-
-#define MSV_TRY(x)                      \
-  do {                                  \
-    hipError_t e_ = (x);                \
-    if (e_ != hipSuccess) return e_;    \
-  } while (0)
 
 // Recursive factorization of the panel rows [c0, n) x columns [c0, c0 + w).
 template <typename R>
@@ -1201,16 +1291,17 @@ hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
 
 }  // namespace
 
+size_t lu_work_bytes(int n, int nb, bool c128) {
+  return c128 ? linv_bytes(nb, sizeof(double2)) : linv_bytes(nb, sizeof(float2)) + nb * planes_per_matrix(n) * 2;
+}
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
-  Batch<double2> bt{Mats<double2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, static_cast<double2*>(work)};
-  return factor<double>(bt, 256, s);
+  return factor<double>(make_batch(Mats<double2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, work), 256, s);
 }
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
-  Batch<float2> bt{Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, static_cast<float2*>(work)};
-  return factor<float>(bt, 256, s);
+  return factor<float>(make_batch(Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, work), 256, s);
 }
 hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s) {
-  Batch<float2> bt{Mats<float2>{nullptr, nullptr, nullptr, 0, nmax, d_list}, nb, nmax, static_cast<float2*>(work)};
-  return factor<float>(bt, panel, s);
+  return factor<float>(make_batch(Mats<float2>{nullptr, nullptr, nullptr, 0, nmax, d_list}, nb, nmax, work), panel,
+                       s);
 }
 }  // namespace msv

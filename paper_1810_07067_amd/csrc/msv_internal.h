@@ -67,8 +67,10 @@ hipError_t launch_assemble(const AsmParams& p, hipStream_t s);
 // Batched dense LU / solve (row-major, complex), see lu.hip.
 // Inverses of 64 x 64 unit-lower diagonal blocks kept per matrix by the LU:
 // one slot per 64-row piece of a 256-column outer panel.  The LU workspace
-// passed to lu_factor_* holds nb * kLinvSlots * 64 * 64 elements.
+// passed to lu_factor_* holds them and, for complex64, the bf16 planes of the
+// large trailing updates: lu_work_bytes(largest order, nb, complex128?).
 constexpr int kLinvSlots = 4;
+size_t lu_work_bytes(int n, int nb, bool c128);
 
 struct LuBatch {
   int n;           // matrix order
@@ -107,7 +109,7 @@ struct LuMat {
   int32_t n;
   int32_t pad;
 };
-// work: nb * 64 * 64 complex elements of the factor's precision
+// work: lu_work_bytes(n, nb, complex128?) bytes
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 // complex64 factorization of a listed batch (d_list on the device) with outer

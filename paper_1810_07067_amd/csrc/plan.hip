@@ -43,7 +43,7 @@ struct msv_plan {
   int32_t* d_perm = nullptr;   // row permutation of each factor
   void* d_inv = nullptr;       // inverses of the 64 x 64 diagonal blocks of L and U
   size_t inv_bytes = 0;
-  void* d_luw = nullptr;       // LU workspace: kLinvSlots 64 x 64 blocks per matrix
+  void* d_luw = nullptr;       // LU workspace (block inverses, complex64 update planes)
   size_t luw_bytes = 0;
   size_t ipiv_elems = 0;
   bool info_checked = false;
@@ -528,7 +528,7 @@ static msv_status factor_buffers(msv_plan* p, int n, int nb) {
       return fail(p, MSV_ENOMEM, "pivot allocation failed");
     p->ipiv_elems = (size_t)nb * n;
   }
-  const size_t luw_bytes = (size_t)nb * msv::kLinvSlots * 64 * 64 * 16;
+  const size_t luw_bytes = msv::lu_work_bytes(n, nb, p->precision == 0);
   if (luw_bytes > p->luw_bytes) {
     if (p->d_luw) (void)hipFree(p->d_luw);
     p->d_luw = nullptr;
@@ -709,7 +709,7 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
       list.push_back(msv::LuMat{p->d_fac32 + (size_t)k * n * n, p->d_ipiv + (size_t)k * n, p->d_info + k, n, 0});
   }
   if (hipMalloc(&b->d_list, sizeof(msv::LuMat) * list.size()) != hipSuccess ||
-      hipMalloc(&b->d_work, (size_t)b->nb * msv::kLinvSlots * 64 * 64 * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&b->d_work, msv::lu_work_bytes(nmax, b->nb, false)) != hipSuccess ||
       hipMemcpy(b->d_list, list.data(), sizeof(msv::LuMat) * list.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&b->ev_in) != hipSuccess || hipEventCreate(&b->ev_out) != hipSuccess) {
