@@ -887,15 +887,15 @@ __global__ __launch_bounds__(256) void gemm_update_bf(Mats<float2> B, int r0, in
       }
 }
 
-// The same product on 128 x 128 tiles for the large trailing updates, fed
-// from operands split once per update instead of once per tile.
-// split_planes writes A = M[r0:rend, k0:k0+K] and B = M[k0:k0+K, c0:cend]
-// as six bf16 planes each (re hi, re lo, im hi, im lo, (re + im) hi,
-// (re + im) lo): P[c][p][i][t] is plane p of element 32 c + t of row i of A,
-// or of column i of B, with rows (columns) past the block zero up to RA (RB),
-// multiples of 128.  Per matrix the planes of A take 6 RA K elements, those
-// of B the next 6 RB K; matrices are ws_stride elements apart.  The values
-// are those the tile kernels form, so the products are the same bit for bit.
+// The large trailing updates on 128 x 128 tiles, fed from operands split
+// once per update instead of once per tile.  split_planes writes
+// A = M[r0:rend, k0:k0+K] and B = M[k0:k0+K, c0:cend] as four bf16 planes
+// each (re hi, re lo, im hi, im lo): P[c][p][i][t] is plane p of element
+// 32 c + t of row i of A, or of column i of B, with rows (columns) past the
+// block zero up to RA (RB), multiples of 128.  Per matrix the planes of A take
+// 4 RA K elements, those of B the next 4 RB K; matrices are ws_stride
+// elements apart.
+constexpr int kPlanes = 4;
 __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
                                                     int K, __bf16* ws, size_t ws_stride, int RA, int RB) {
   const Mz<float2> mz = mat_at(B, blockIdx.z);
@@ -906,14 +906,15 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
   const int g = blockIdx.x * 256 + threadIdx.x;
   const bool live = k0 < n;
   __bf16* w = global_ptr(ws + blockIdx.z * ws_stride);
-  float re[8], im[8], sm[8];
+  float re[8], im[8];
   __bf16* out;
   size_t pstride;
   if (g < 4 * RA) {
     // A: 4 threads per row, 8 consecutive k each
     const int i = g >> 2, q = g & 3;
     const bool ok = live && r0 + i < rend;
-    const float4* src = reinterpret_cast<const float4*>(mz.a + (size_t)(ok ? r0 + i : 0) * n + k0 + 32 * c + 8 * q);
+    const float4* src =
+        reinterpret_cast<const float4*>(mz.a + (ok ? (size_t)(r0 + i) * n + k0 + 32 * c + 8 * q : 0));
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const float4 v = src[t];
@@ -922,7 +923,7 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
       re[2 * t + 1] = ok ? v.z : 0.f;
       im[2 * t + 1] = ok ? v.w : 0.f;
     }
-    out = w + ((size_t)c * 6 * RA + i) * 32 + 8 * q;
+    out = w + ((size_t)c * kPlanes * RA + i) * 32 + 8 * q;
     pstride = (size_t)RA * 32;
   } else {
     // B: consecutive threads take consecutive columns
@@ -936,11 +937,9 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
       re[t] = v.x;
       im[t] = v.y;
     }
-    out = w + (size_t)6 * RA * K + ((size_t)c * 6 * RB + j) * 32 + 8 * q;
+    out = w + (size_t)kPlanes * RA * K + ((size_t)c * kPlanes * RB + j) * 32 + 8 * q;
     pstride = (size_t)RB * 32;
   }
-#pragma unroll
-  for (int t = 0; t < 8; ++t) sm[t] = re[t] + im[t];
   bf16x8 h, l;
   split8(re, h, l);
   *reinterpret_cast<bf16x8*>(out) = h;
@@ -948,19 +947,19 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
   split8(im, h, l);
   *reinterpret_cast<bf16x8*>(out + 2 * pstride) = h;
   *reinterpret_cast<bf16x8*>(out + 3 * pstride) = l;
-  split8(sm, h, l);
-  *reinterpret_cast<bf16x8*>(out + 4 * pstride) = h;
-  *reinterpret_cast<bf16x8*>(out + 5 * pstride) = l;
 }
 
-// C -= A B on 128 x 128 tiles from the planes: each wave computes 64 x 64
-// (4 x 4 MFMA blocks), reading a third as many LDS bytes per MFMA as the
-// 64 x 64 tile.  A K chunk is 12 16-byte pieces of A and 12 of B per thread,
-// loaded one chunk ahead and copied to LDS unchanged; staging in dynamic LDS
-// (2 x 6 planes of [128][kBP] bf16, 144 KB), accumulators in AGPRs; one
-// workgroup per CU.
+// C -= A B on 128 x 128 tiles from the planes, with the four real products
+// of the complex product (re = Ar Br - Ai Bi, im = Ar Bi + Ai Br; the minus
+// sign flips the sign bits of the Ai operands) and each as hi hi + hi lo +
+// lo hi: 12 bf16 MFMAs per complex product, into two accumulators instead of
+// the three of 3M.  The 128 accumulator registers this leaves free hold two
+// K chunks of operands in flight (8 16-byte pieces of A and 8 of B per thread
+// and chunk), so each chunk's loads have two chunks of products to arrive.
+// Each wave computes 64 x 64 (4 x 4 MFMA blocks); staging in dynamic LDS
+// (2 x 4 planes of [128][kBP] bf16, 96 KB); one workgroup per CU.
 constexpr int kBT = 128;
-constexpr size_t kBfLds = 2 * 6 * kBT * kBP * sizeof(__bf16);
+constexpr size_t kBfLds = 2 * kPlanes * kBT * kBP * sizeof(__bf16);
 
 // Workgroup -> (column tile x, row tile y, matrix z) of a 1-D grid of
 // nb TY TX tiles.  The hardware hands workgroups to the 8 XCDs round-robin
@@ -983,13 +982,20 @@ __device__ __forceinline__ void update_tile(int TX, int TY, int& x, int& y, int&
   x = r / gh;
 }
 
+__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
 __global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
                                                           int K, const __bf16* ws, size_t ws_stride, int RA,
                                                           int RB) {
   using C4 = Mfma<float>::C4;
   extern __shared__ __attribute__((aligned(16))) __bf16 lds_bf[];
   __bf16 (*As)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf);
-  __bf16 (*Bs)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf + 6 * kBT * kBP);
+  __bf16 (*Bs)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf + kPlanes * kBT * kBP);
   int bx, by, bz;
   update_tile(RB / kBT, RA / kBT, bx, by, bz);
   const Mz<float2> mz = mat_at(B, bz);
@@ -1004,66 +1010,109 @@ __global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
   const int li = lane & 15, lq = lane >> 4;
-  C4 t1[4][4], t2[4][4], t3[4][4];
+  C4 tre[4][4], tim[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      t1[a][b] = C4{0, 0, 0, 0};
-      t2[a][b] = C4{0, 0, 0, 0};
-      t3[a][b] = C4{0, 0, 0, 0};
+      tre[a][b] = C4{0, 0, 0, 0};
+      tim[a][b] = C4{0, 0, 0, 0};
     }
   // piece v of a chunk: plane v / 2, row 64 (v % 2) + tid / 4, k 8 (tid % 4)
   const int sr = tid >> 2, sq = 8 * (tid & 3);
   const __bf16* wa = global_ptr(ws + bz * ws_stride) + ((size_t)by * kBT + sr) * 32 + sq;
-  const __bf16* wb = global_ptr(ws + bz * ws_stride) + (size_t)6 * RA * K + ((size_t)bx * kBT + sr) * 32 + sq;
-  bf16x8 ra[12], rb[12];
-  auto fetch = [&](int c) {
+  const __bf16* wb =
+      global_ptr(ws + bz * ws_stride) + (size_t)kPlanes * RA * K + ((size_t)bx * kBT + sr) * 32 + sq;
+  bf16x8 ra0[8], rb0[8], ra1[8], rb1[8];
+  auto fetch = [&](int c, bf16x8(&ra)[8], bf16x8(&rb)[8]) {
 #pragma unroll
-    for (int v = 0; v < 12; ++v) {
-      ra[v] = *reinterpret_cast<const bf16x8*>(wa + ((size_t)(6 * c + (v >> 1)) * RA + 64 * (v & 1)) * 32);
-      rb[v] = *reinterpret_cast<const bf16x8*>(wb + ((size_t)(6 * c + (v >> 1)) * RB + 64 * (v & 1)) * 32);
+    for (int v = 0; v < 8; ++v) {
+      ra[v] = *reinterpret_cast<const bf16x8*>(wa + ((size_t)(kPlanes * c + (v >> 1)) * RA + 64 * (v & 1)) * 32);
+      rb[v] = *reinterpret_cast<const bf16x8*>(wb + ((size_t)(kPlanes * c + (v >> 1)) * RB + 64 * (v & 1)) * 32);
     }
   };
-  const int nc = K / kBK;
-  auto stage = [&]() {
+  auto stage = [&](const bf16x8(&ra)[8], const bf16x8(&rb)[8]) {
 #pragma unroll
-    for (int v = 0; v < 12; ++v) {
+    for (int v = 0; v < 8; ++v) {
       *reinterpret_cast<bf16x8*>(&As[v >> 1][64 * (v & 1) + sr][sq]) = ra[v];
       *reinterpret_cast<bf16x8*>(&Bs[v >> 1][64 * (v & 1) + sr][sq]) = rb[v];
     }
   };
   auto products = [&]() {
+    bf16x8 brh[4], brl[4], bih[4], bil[4];
 #pragma unroll
-    for (int pr = 0; pr < 3; ++pr) {
-      bf16x8 ah[4], al[4], bh[4], bl[4];
+    for (int b = 0; b < 4; ++b) {
+      brh[b] = *reinterpret_cast<const bf16x8*>(&Bs[0][wc + 16 * b + li][8 * lq]);
+      brl[b] = *reinterpret_cast<const bf16x8*>(&Bs[1][wc + 16 * b + li][8 * lq]);
+      bih[b] = *reinterpret_cast<const bf16x8*>(&Bs[2][wc + 16 * b + li][8 * lq]);
+      bil[b] = *reinterpret_cast<const bf16x8*>(&Bs[3][wc + 16 * b + li][8 * lq]);
+    }
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      // part 0: Ar (re += Ar Br, im += Ar Bi); part 1: Ai (im += Ai Br,
+      // re += (-Ai) Bi)
+      bf16x8 ah[4], al[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        ah[a] = *reinterpret_cast<const bf16x8*>(&As[2 * pr][wr + 16 * a + li][8 * lq]);
-        al[a] = *reinterpret_cast<const bf16x8*>(&As[2 * pr + 1][wr + 16 * a + li][8 * lq]);
-        bh[a] = *reinterpret_cast<const bf16x8*>(&Bs[2 * pr][wc + 16 * a + li][8 * lq]);
-        bl[a] = *reinterpret_cast<const bf16x8*>(&Bs[2 * pr + 1][wc + 16 * a + li][8 * lq]);
+        ah[a] = *reinterpret_cast<const bf16x8*>(&As[2 * part][wr + 16 * a + li][8 * lq]);
+        al[a] = *reinterpret_cast<const bf16x8*>(&As[2 * part + 1][wr + 16 * a + li][8 * lq]);
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          C4& t = pr == 0 ? t1[a][b] : pr == 1 ? t2[a][b] : t3[a][b];
-          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], t, 0, 0, 0);
+          C4& tb = part == 0 ? tre[a][b] : tim[a][b];  // the product with Br
+          tb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brh[b], tb, 0, 0, 0);
+          tb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brl[b], tb, 0, 0, 0);
+          tb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], brh[b], tb, 0, 0, 0);
+        }
+      if (part == 1)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ah[a] = neg8(ah[a]);
+          al[a] = neg8(al[a]);
+        }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          C4& ti = part == 0 ? tim[a][b] : tre[a][b];  // the product with Bi
+          ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bih[b], ti, 0, 0, 0);
+          ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bil[b], ti, 0, 0, 0);
+          ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bih[b], ti, 0, 0, 0);
         }
     }
   };
-  fetch(0);
-  for (int c = 0; c + 1 < nc; ++c) {
-    stage();
+  // chunk c is staged from (ra0, rb0) for even c and (ra1, rb1) for odd c;
+  // after staging, the same registers take chunk c + 2
+  const int nc = K / kBK;
+  fetch(0, ra0, rb0);
+  if (nc > 1) fetch(1, ra1, rb1);
+  int c = 0;
+  for (; c + 2 < nc; c += 2) {
+    stage(ra0, rb0);
     __syncthreads();
-    fetch(c + 1);
+    fetch(c + 2, ra0, rb0);
+    products();
+    __syncthreads();
+    stage(ra1, rb1);
+    __syncthreads();
+    if (c + 3 < nc) fetch(c + 3, ra1, rb1);
     products();
     __syncthreads();
   }
-  stage();
+  if (nc - c == 2) {
+    stage(ra0, rb0);
+    __syncthreads();
+    products();
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      ra0[v] = ra1[v];
+      rb0[v] = rb1[v];
+    }
+  }
+  stage(ra0, rb0);
   __syncthreads();
   // the wave's 64 x 64 block of C is loaded while the last chunk's products
   // run, in one round trip to memory
@@ -1090,8 +1139,8 @@ __global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0
         const int gc = tc + wc + 16 * b + li;
         if (gr < rend && gc < cend) {
           float2 v = cv[a][b][i];
-          v.x -= t1[a][b][i] - t2[a][b][i];
-          v.y -= t3[a][b][i] - t1[a][b][i] - t2[a][b][i];
+          v.x -= tre[a][b][i];
+          v.y -= tim[a][b][i];
           M[(size_t)gr * n + gc] = v;
         }
       }
@@ -1110,10 +1159,10 @@ struct Batch {
 };
 
 // Workspace split: diagonal-block inverses, then (complex64) room for the
-// planes of one trailing update per matrix, 6 (RA + RB) K <= 12 R 256 with R
+// planes of one trailing update per matrix, 4 (RA + RB) K <= 8 R 256 with R
 // the largest order rounded up to 128.
 size_t linv_bytes(int nb, size_t elem) { return ((size_t)nb * kLinvSlots * 64 * 64 * elem + 255) / 256 * 256; }
-size_t planes_per_matrix(int n) { return (size_t)12 * ((n + kBT - 1) / kBT * kBT) * 256; }
+size_t planes_per_matrix(int n) { return (size_t)2 * kPlanes * ((n + kBT - 1) / kBT * kBT) * 256; }
 
 template <typename T>
 Batch<T> make_batch(const Mats<T>& d, int nb, int nmax, void* work) {
@@ -1136,7 +1185,7 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
   if constexpr (sizeof(R) == 4) {
     const int RA = (Mr + kBT - 1) / kBT * kBT, RB = (Nc + kBT - 1) / kBT * kBT;
     if (K % kBK == 0 && Mr >= 2 * kBT && Nc >= 2 * kBT && b.planes &&
-        (size_t)6 * (RA + RB) * K <= b.planes_stride) {
+        (size_t)kPlanes * (RA + RB) * K <= b.planes_stride) {
       static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_update_planes),
                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBfLds);
       if (attr != hipSuccess) return attr;
