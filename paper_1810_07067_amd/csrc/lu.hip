@@ -951,15 +951,21 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
 
 // C -= A B on 128 x 128 tiles from the planes, with the four real products
 // of the complex product (re = Ar Br - Ai Bi, im = Ar Bi + Ai Br; the minus
-// sign flips the sign bits of the Ai operands) and each as hi hi + hi lo +
+// sign flips the sign bits of the Bi operands) and each as hi hi + hi lo +
 // lo hi: 12 bf16 MFMAs per complex product, into two accumulators instead of
-// the three of 3M.  The 128 accumulator registers this leaves free hold two
-// K chunks of operands in flight (8 16-byte pieces of A and 8 of B per thread
-// and chunk), so each chunk's loads have two chunks of products to arrive.
-// Each wave computes 64 x 64 (4 x 4 MFMA blocks); staging in dynamic LDS
-// (2 x 4 planes of [128][kBP] bf16, 96 KB); one workgroup per CU.
+// the three of 3M.  Each wave computes 64 x 64 (4 x 4 MFMA blocks).  K chunks
+// of 32 go through two LDS buffers, each 4 planes of A and 4 of B as
+// [128][32] bf16 rows with the 16-byte quarters of a row permuted by bits 2-3
+// of the row (q ^ (r >> 2 & 3)): the 16-byte reads of 8 consecutive lanes
+// (8 rows, one quarter) and the writes of 8 (2 rows, 4 quarters) fall on
+// distinct banks without padding.  Chunk c + 1 is staged while chunk c's
+// products run, one barrier per chunk; the registers freed by the two
+// accumulators hold two more chunks in flight (8 16-byte pieces of A and 8 of
+// B per thread and chunk), so each chunk's loads have two chunks of products
+// to arrive.  128 KB of dynamic LDS; one workgroup per CU.
 constexpr int kBT = 128;
-constexpr size_t kBfLds = 2 * kPlanes * kBT * kBP * sizeof(__bf16);
+constexpr int kChunkElems = 2 * kPlanes * kBT * 32;  // one LDS buffer: A then B
+constexpr size_t kBfLds = 2 * kChunkElems * sizeof(__bf16);
 
 // Workgroup -> (column tile x, row tile y, matrix z) of a 1-D grid of
 // nb TY TX tiles.  The hardware hands workgroups to the 8 XCDs round-robin
@@ -994,8 +1000,6 @@ __global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0
                                                           int RB) {
   using C4 = Mfma<float>::C4;
   extern __shared__ __attribute__((aligned(16))) __bf16 lds_bf[];
-  __bf16 (*As)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf);
-  __bf16 (*Bs)[kBT][kBP] = reinterpret_cast<__bf16 (*)[kBT][kBP]>(lds_bf + kPlanes * kBT * kBP);
   int bx, by, bz;
   update_tile(RB / kBT, RA / kBT, bx, by, bz);
   const Mz<float2> mz = mat_at(B, bz);
@@ -1018,104 +1022,103 @@ __global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0
       tre[a][b] = C4{0, 0, 0, 0};
       tim[a][b] = C4{0, 0, 0, 0};
     }
-  // piece v of a chunk: plane v / 2, row 64 (v % 2) + tid / 4, k 8 (tid % 4)
-  const int sr = tid >> 2, sq = 8 * (tid & 3);
-  const __bf16* wa = global_ptr(ws + bz * ws_stride) + ((size_t)by * kBT + sr) * 32 + sq;
-  const __bf16* wb =
-      global_ptr(ws + bz * ws_stride) + (size_t)kPlanes * RA * K + ((size_t)bx * kBT + sr) * 32 + sq;
+  // piece v of a chunk: plane v / 2, row 64 (v % 2) + tid / 4, quarter tid % 4;
+  // global addresses a uniform base per piece plus one 32-bit lane offset
+  const int sr = tid >> 2, sq = tid & 3;
+  const unsigned lofs = (unsigned)(sr * 32 + 8 * sq);
+  const __bf16* wa = global_ptr(ws + bz * ws_stride) + (size_t)by * kBT * 32;
+  const __bf16* wb = global_ptr(ws + bz * ws_stride) + (size_t)kPlanes * RA * K + (size_t)bx * kBT * 32;
+  // LDS element offsets (within a buffer) of this thread's pieces and reads
+  const int st_ofs = sr * 32 + 8 * (sq ^ ((sr >> 2) & 3));
+  const int rd_ofs = li * 32 + 8 * (lq ^ ((li >> 2) & 3));
   bf16x8 ra0[8], rb0[8], ra1[8], rb1[8];
   auto fetch = [&](int c, bf16x8(&ra)[8], bf16x8(&rb)[8]) {
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-      ra[v] = *reinterpret_cast<const bf16x8*>(wa + ((size_t)(kPlanes * c + (v >> 1)) * RA + 64 * (v & 1)) * 32);
-      rb[v] = *reinterpret_cast<const bf16x8*>(wb + ((size_t)(kPlanes * c + (v >> 1)) * RB + 64 * (v & 1)) * 32);
+      const __bf16* pa = wa + ((size_t)(kPlanes * c + (v >> 1)) * RA + 64 * (v & 1)) * 32;
+      const __bf16* pb = wb + ((size_t)(kPlanes * c + (v >> 1)) * RB + 64 * (v & 1)) * 32;
+      ra[v] = *reinterpret_cast<const bf16x8*>(pa + lofs);
+      rb[v] = *reinterpret_cast<const bf16x8*>(pb + lofs);
     }
   };
-  auto stage = [&](const bf16x8(&ra)[8], const bf16x8(&rb)[8]) {
+  auto stage = [&](const bf16x8(&ra)[8], const bf16x8(&rb)[8], int buf) {
+    __bf16* x = lds_bf + buf * kChunkElems + st_ofs;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-      *reinterpret_cast<bf16x8*>(&As[v >> 1][64 * (v & 1) + sr][sq]) = ra[v];
-      *reinterpret_cast<bf16x8*>(&Bs[v >> 1][64 * (v & 1) + sr][sq]) = rb[v];
+      const int o = ((v >> 1) * kBT + 64 * (v & 1)) * 32;
+      *reinterpret_cast<bf16x8*>(x + o) = ra[v];
+      *reinterpret_cast<bf16x8*>(x + kPlanes * kBT * 32 + o) = rb[v];
     }
   };
-  auto products = [&]() {
-    bf16x8 brh[4], brl[4], bih[4], bil[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      brh[b] = *reinterpret_cast<const bf16x8*>(&Bs[0][wc + 16 * b + li][8 * lq]);
-      brl[b] = *reinterpret_cast<const bf16x8*>(&Bs[1][wc + 16 * b + li][8 * lq]);
-      bih[b] = *reinterpret_cast<const bf16x8*>(&Bs[2][wc + 16 * b + li][8 * lq]);
-      bil[b] = *reinterpret_cast<const bf16x8*>(&Bs[3][wc + 16 * b + li][8 * lq]);
-    }
+  auto products = [&](int buf) {
+    const __bf16* xa = lds_bf + buf * kChunkElems + rd_ofs + wr * 32;
+    const __bf16* xb = lds_bf + buf * kChunkElems + kPlanes * kBT * 32 + rd_ofs + wc * 32;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
-      // part 0: Ar (re += Ar Br, im += Ar Bi); part 1: Ai (im += Ai Br,
-      // re += (-Ai) Bi)
+      // part 0: A = Ar (re += Ar Br, im += Ar Bi); part 1: A = Ai (im += Ai Br,
+      // re += Ai (-Bi)).  The A operands stay in registers while the column
+      // blocks of B stream through; consecutive MFMAs rotate over 8
+      // accumulators, so none waits on the one before.
       bf16x8 ah[4], al[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        ah[a] = *reinterpret_cast<const bf16x8*>(&As[2 * part][wr + 16 * a + li][8 * lq]);
-        al[a] = *reinterpret_cast<const bf16x8*>(&As[2 * part + 1][wr + 16 * a + li][8 * lq]);
+        ah[a] = *reinterpret_cast<const bf16x8*>(xa + ((2 * part) * kBT + 16 * a) * 32);
+        al[a] = *reinterpret_cast<const bf16x8*>(xa + ((2 * part + 1) * kBT + 16 * a) * 32);
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          C4& tb = part == 0 ? tre[a][b] : tim[a][b];  // the product with Br
-          tb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brh[b], tb, 0, 0, 0);
-          tb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brl[b], tb, 0, 0, 0);
-          tb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], brh[b], tb, 0, 0, 0);
+      for (int b = 0; b < 4; ++b) {
+        const bf16x8 brh = *reinterpret_cast<const bf16x8*>(xb + (0 * kBT + 16 * b) * 32);
+        const bf16x8 brl = *reinterpret_cast<const bf16x8*>(xb + (1 * kBT + 16 * b) * 32);
+        bf16x8 xh = *reinterpret_cast<const bf16x8*>(xb + (2 * kBT + 16 * b) * 32);
+        bf16x8 xl = *reinterpret_cast<const bf16x8*>(xb + (3 * kBT + 16 * b) * 32);
+        if (part == 1) {
+          xh = neg8(xh);
+          xl = neg8(xl);
         }
-      if (part == 1)
+        C4(&tb)[4][4] = part == 0 ? tre : tim;  // the products with Br
+        C4(&tx)[4][4] = part == 0 ? tim : tre;  // the products with +-Bi
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          ah[a] = neg8(ah[a]);
-          al[a] = neg8(al[a]);
-        }
+        for (int a = 0; a < 4; ++a) tb[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brh, tb[a][b], 0, 0, 0);
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) tx[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], xh, tx[a][b], 0, 0, 0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          C4& ti = part == 0 ? tim[a][b] : tre[a][b];  // the product with Bi
-          ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bih[b], ti, 0, 0, 0);
-          ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bil[b], ti, 0, 0, 0);
-          ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bih[b], ti, 0, 0, 0);
-        }
+        for (int a = 0; a < 4; ++a) tb[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brl, tb[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) tx[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], xl, tx[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) tb[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], brh, tb[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) tx[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], xh, tx[a][b], 0, 0, 0);
+      }
     }
   };
-  // chunk c is staged from (ra0, rb0) for even c and (ra1, rb1) for odd c;
-  // after staging, the same registers take chunk c + 2
-  const int nc = K / kBK;
+  // chunk c is in LDS buffer c % 2; while its products run, chunk c + 1 is
+  // staged into the other buffer from the registers that then take chunk c + 3.
+  // The fetches are unconditional (past the end they repeat the last chunk):
+  // behind a branch, the wait before each staging would also have to cover
+  // the path without them and would wait for every load in flight.
+  const int nc = K / kBK, last = nc - 1;
   fetch(0, ra0, rb0);
-  if (nc > 1) fetch(1, ra1, rb1);
+  fetch(min(1, last), ra1, rb1);
+  stage(ra0, rb0, 0);
+  fetch(min(2, last), ra0, rb0);
+  __syncthreads();
   int c = 0;
   for (; c + 2 < nc; c += 2) {
-    stage(ra0, rb0);
+    stage(ra1, rb1, 1);
+    fetch(min(c + 3, last), ra1, rb1);
+    products(0);
     __syncthreads();
-    fetch(c + 2, ra0, rb0);
-    products();
-    __syncthreads();
-    stage(ra1, rb1);
-    __syncthreads();
-    if (c + 3 < nc) fetch(c + 3, ra1, rb1);
-    products();
+    stage(ra0, rb0, 0);
+    fetch(min(c + 4, last), ra0, rb0);
+    products(1);
     __syncthreads();
   }
-  if (nc - c == 2) {
-    stage(ra0, rb0);
-    __syncthreads();
-    products();
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      ra0[v] = ra1[v];
-      rb0[v] = rb1[v];
-    }
-  }
-  stage(ra0, rb0);
-  __syncthreads();
-  // the wave's 64 x 64 block of C is loaded while the last chunk's products
-  // run, in one round trip to memory
+  // one or two chunks left, the first in buffer 0, a second in (ra1, rb1)
+  const bool two = nc - c == 2;
+  if (two) stage(ra1, rb1, 1);
+  // the wave's 64 x 64 block of C is loaded while the last products run, in
+  // one round trip to memory
   float2 cv[4][4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -1128,7 +1131,11 @@ __global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0
         const bool ok = gr < rend && gc < cend;
         cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
       }
-  products();
+  products(0);
+  if (two) {
+    __syncthreads();
+    products(1);
+  }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
