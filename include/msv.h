@@ -154,10 +154,10 @@ int32_t msv_last_ir_iterations(const msv_plan *plan);
  * d_A[i] = [m_hi-m_lo+1][4N_i][4N_i] from msv_assemble(plans[i], .., m_lo,
  * m_hi, ..).  The matrices must stay alive and unchanged while the batch is
  * used.  Creation allocates each plan's factor storage.  It then times the
- * outer panel widths 64, 128 and 256 columns on the batch itself, keeps the
- * fastest graph, and leaves every plan factored as by msv_factor.  128 and 256
- * are candidates only when every order below the largest is a multiple of
- * them.
+ * outer panel widths 64, 128, 256 and 512 columns on the batch itself, keeps
+ * the fastest graph, and leaves every plan factored as by msv_factor.  128,
+ * 256 and 512 are candidates only when every order below the largest is a
+ * multiple of them.
  * It synchronizes `stream` and returns MSV_EINVAL for bad arguments, MSV_ENOMEM
  * and MSV_EHIP otherwise (message: msv_batch_last_error(NULL)).
  *
@@ -172,10 +172,10 @@ msv_status msv_batch_create(msv_batch **out, msv_plan *const *plans, msv_c128 *c
 msv_status msv_batch_factor(msv_batch *batch, void *stream);
 void msv_batch_destroy(msv_batch *batch);
 const char *msv_batch_last_error(const msv_batch *batch);
-/* outer panel width the autotuner chose (64, 128 or 256) */
+/* outer panel width the autotuner chose (64, 128, 256 or 512) */
 int32_t msv_batch_panel(const msv_batch *batch);
 /* the timed duration in ms of one batched factorization with panel width 64,
- * 128 or 256 (-1 if that candidate was not run) */
+ * 128, 256 or 512 (-1 if that candidate was not run) */
 float msv_batch_tuned_ms(const msv_batch *batch, int32_t panel);
 
 #ifdef __cplusplus

@@ -973,7 +973,7 @@ constexpr size_t kBfLds = 2 * kChunkElems * sizeof(__bf16);
 // a group of kGY row tiles, then across the columns.  The workgroups resident
 // on one XCD then share a few row tiles of A and column tiles of B in its L2,
 // where round-robin order spreads every tile over all eight.
-constexpr int kGY = 4;
+constexpr int kGY = 2;
 __device__ __forceinline__ void update_tile(int TX, int TY, int& x, int& y, int& z) {
   const int T = (int)gridDim.x, L = (int)blockIdx.x;
   const int base = T >> 3, rem = T & 7, xcd = L & 7;
@@ -1166,10 +1166,10 @@ struct Batch {
 };
 
 // Workspace split: diagonal-block inverses, then (complex64) room for the
-// planes of one trailing update per matrix, 4 (RA + RB) K <= 8 R 256 with R
+// planes of one trailing update per matrix, 4 (RA + RB) K <= 8 R 512 with R
 // the largest order rounded up to 128.
 size_t linv_bytes(int nb, size_t elem) { return ((size_t)nb * kLinvSlots * 64 * 64 * elem + 255) / 256 * 256; }
-size_t planes_per_matrix(int n) { return (size_t)2 * kPlanes * ((n + kBT - 1) / kBT * kBT) * 256; }
+size_t planes_per_matrix(int n) { return (size_t)2 * kPlanes * ((n + kBT - 1) / kBT * kBT) * 512; }
 
 template <typename T>
 Batch<T> make_batch(const Mats<T>& d, int nb, int nmax, void* work) {
@@ -1319,14 +1319,15 @@ __global__ void zero_info(Mats<T> B, int nb) {
   for (int i = threadIdx.x; i < nb; i += blockDim.x) *mat_at(B, i).info = 0;
 }
 
-// Outer panels of NB = 64 or 128 columns.  In a listed batch every order
+// Outer panels of NB = 64, 128, 256 or 512 columns (complex64 alone: 512,
+// complex128: 256).  In a listed batch every order
 // below the largest must be a multiple of NB, so that a panel is never cut
 // short for one matrix and not for another.
 template <typename R>
 hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
   const int n = b.nmax;
   if (n > kPanelThreads * kMaxRowsPerThread) return hipErrorInvalidValue;
-  if (NB != 64 && NB != 128 && NB != 256) return hipErrorInvalidValue;
+  if (NB != 64 && NB != 128 && NB != 256 && NB != 512) return hipErrorInvalidValue;
   hipLaunchKernelGGL(zero_info<typename V2<R>::T>, dim3(1), dim3(256), 0, s, b.d, b.nb);
   MSV_TRY(hipGetLastError());
   for (int k = 0; k < n; ) {
@@ -1354,7 +1355,7 @@ hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& 
   return factor<double>(make_batch(Mats<double2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, work), 256, s);
 }
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
-  return factor<float>(make_batch(Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, work), 256, s);
+  return factor<float>(make_batch(Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, work), 512, s);
 }
 hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s) {
   return factor<float>(make_batch(Mats<float2>{nullptr, nullptr, nullptr, 0, nmax, d_list}, nb, nmax, work), panel,

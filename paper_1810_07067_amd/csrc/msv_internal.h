@@ -66,10 +66,10 @@ hipError_t launch_assemble(const AsmParams& p, hipStream_t s);
 
 // Batched dense LU / solve (row-major, complex), see lu.hip.
 // Inverses of 64 x 64 unit-lower diagonal blocks kept per matrix by the LU:
-// one slot per 64-row piece of a 256-column outer panel.  The LU workspace
+// one slot per 64-row piece of a 512-column outer panel.  The LU workspace
 // passed to lu_factor_* holds them and, for complex64, the bf16 planes of the
 // large trailing updates: lu_work_bytes(largest order, nb, complex128?).
-constexpr int kLinvSlots = 4;
+constexpr int kLinvSlots = 8;
 size_t lu_work_bytes(int n, int nb, bool c128);
 
 struct LuBatch {
@@ -113,7 +113,7 @@ struct LuMat {
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 // complex64 factorization of a listed batch (d_list on the device) with outer
-// panels of `panel` = 64 or 128 columns; nmax is the largest order, every
+// panels of `panel` = 64, 128, 256 or 512 columns; nmax is the largest order, every
 // other order a multiple of `panel`
 hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s);
 

@@ -607,7 +607,7 @@ struct msv_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int panel = 128;
-  float tuned_ms[3] = {-1.f, -1.f, -1.f};  // panel 64, 128, 256
+  float tuned_ms[4] = {-1.f, -1.f, -1.f, -1.f};  // panel 64, 128, 256, 512
   std::string err;
 };
 
@@ -681,11 +681,12 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
   }
   // a panel width is a candidate when every order below the largest is a
   // multiple of it (a panel then never straddles the end of a smaller matrix)
-  bool ok128 = true, ok256 = true;
+  bool ok128 = true, ok256 = true, ok512 = true;
   for (int i = 0; i < n_plans; ++i) {
     const int n = 4 * plans[i]->N;
     if (n != nmax && n % 128 != 0) ok128 = false;
     if (n != nmax && n % 256 != 0) ok256 = false;
+    if (n != nmax && n % 512 != 0) ok512 = false;
   }
   msv_batch* b = new msv_batch();
   b->plans.assign(plans, plans + n_plans);
@@ -718,10 +719,10 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
   }
   // autotune the outer panel width: capture, run once to warm up, time once
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  const int cands[3] = {64, 128, 256};
+  const int cands[4] = {64, 128, 256, 512};
   int best_c = -1;
-  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
-    if ((cands[c] == 128 && !ok128) || (cands[c] == 256 && !ok256)) continue;
+  for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+    if ((cands[c] == 128 && !ok128) || (cands[c] == 256 && !ok256) || (cands[c] == 512 && !ok512)) continue;
     hipGraph_t g = nullptr;
     hipGraphExec_t x = nullptr;
     e = batch_capture(b, cands[c], &g, &x);
@@ -764,7 +765,8 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
 
 float msv_batch_tuned_ms(const msv_batch* b, int32_t panel) {
   if (!b) return -1.f;
-  return panel == 64 ? b->tuned_ms[0] : panel == 128 ? b->tuned_ms[1] : panel == 256 ? b->tuned_ms[2] : -1.f;
+  return panel == 64 ? b->tuned_ms[0] : panel == 128 ? b->tuned_ms[1] : panel == 256 ? b->tuned_ms[2]
+         : panel == 512 ? b->tuned_ms[3] : -1.f;
 }
 
 msv_status msv_batch_factor(msv_batch* b, void* stream) {

@@ -50,11 +50,11 @@ def test_batched_factor_matches_plain_path():
         mats.append(A1)
         rhss.append(rhs)
     batch = msv.Batch(plans, mats, 0, M)
-    print(f"[batch] panel {batch.panel}: " + ", ".join(f"{batch.tuned_ms(w):.3f} ms ({w})" for w in (64, 128, 256)),
+    print(f"[batch] panel {batch.panel}: " + ", ".join(f"{batch.tuned_ms(w):.3f} ms ({w})" for w in (64, 128, 256, 512)),
           flush=True)
-    assert batch.panel in (64, 128, 256) and batch.tuned_ms(batch.panel) > 0
+    assert batch.panel in (64, 128, 256, 512) and batch.tuned_ms(batch.panel) > 0
     # a timed candidate is never faster than the one kept
-    assert all(batch.tuned_ms(w) < 0 or batch.tuned_ms(w) >= batch.tuned_ms(batch.panel) for w in (64, 128, 256))
+    assert all(batch.tuned_ms(w) < 0 or batch.tuned_ms(w) >= batch.tuned_ms(batch.panel) for w in (64, 128, 256, 512))
     first = []
     for p, rhs, ref in zip(plans, rhss, refs):
         x = p.solve(-M, M, rhs).cpu().numpy()
