@@ -907,10 +907,10 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
   const bool live = k0 < n;
   __bf16* w = global_ptr(ws + blockIdx.z * ws_stride);
   float re[8], im[8];
-  __bf16* out;
-  size_t pstride;
+  bf16x8 h, l;
   if (g < 4 * RA) {
-    // A: 4 threads per row, 8 consecutive k each
+    // A: 4 threads per row, 8 consecutive k each (a row's 64 bytes per plane
+    // from 4 neighbouring lanes)
     const int i = g >> 2, q = g & 3;
     const bool ok = live && r0 + i < rend;
     const float4* src =
@@ -923,30 +923,38 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
       re[2 * t + 1] = ok ? v.z : 0.f;
       im[2 * t + 1] = ok ? v.w : 0.f;
     }
-    out = w + ((size_t)c * kPlanes * RA + i) * 32 + 8 * q;
-    pstride = (size_t)RA * 32;
-  } else {
-    // B: consecutive threads take consecutive columns
-    const int gb = g - 4 * RA;
-    const int j = gb % RB, q = gb / RB;
+    __bf16* out = w + ((size_t)c * kPlanes * RA + i) * 32 + 8 * q;
+    const size_t ps = (size_t)RA * 32;
+    split8(re, h, l);
+    *reinterpret_cast<bf16x8*>(out) = h;
+    *reinterpret_cast<bf16x8*>(out + ps) = l;
+    split8(im, h, l);
+    *reinterpret_cast<bf16x8*>(out + 2 * ps) = h;
+    *reinterpret_cast<bf16x8*>(out + 3 * ps) = l;
+  } else if (g < 4 * RA + RB) {
+    // B: one thread per column, all 32 k of the chunk (consecutive lanes read
+    // consecutive columns and write consecutive 64-byte rows of each plane)
+    const int j = g - 4 * RA;
     const bool ok = live && c0 + j < cend;
-    const float2* src = mz.a + (size_t)(k0 + 32 * c + 8 * q) * n + (ok ? c0 + j : 0);
+    const float2* src = mz.a + (size_t)(k0 + 32 * c) * n + (ok ? c0 + j : 0);
+    __bf16* out = w + (size_t)kPlanes * RA * K + ((size_t)c * kPlanes * RB + j) * 32;
+    const size_t ps = (size_t)RB * 32;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const float2 v = ok ? src[(size_t)t * n] : make_float2(0.f, 0.f);
-      re[t] = v.x;
-      im[t] = v.y;
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float2 v = ok ? src[(size_t)(8 * q + t) * n] : make_float2(0.f, 0.f);
+        re[t] = v.x;
+        im[t] = v.y;
+      }
+      split8(re, h, l);
+      *reinterpret_cast<bf16x8*>(out + 8 * q) = h;
+      *reinterpret_cast<bf16x8*>(out + ps + 8 * q) = l;
+      split8(im, h, l);
+      *reinterpret_cast<bf16x8*>(out + 2 * ps + 8 * q) = h;
+      *reinterpret_cast<bf16x8*>(out + 3 * ps + 8 * q) = l;
     }
-    out = w + (size_t)kPlanes * RA * K + ((size_t)c * kPlanes * RB + j) * 32 + 8 * q;
-    pstride = (size_t)RB * 32;
   }
-  bf16x8 h, l;
-  split8(re, h, l);
-  *reinterpret_cast<bf16x8*>(out) = h;
-  *reinterpret_cast<bf16x8*>(out + pstride) = l;
-  split8(im, h, l);
-  *reinterpret_cast<bf16x8*>(out + 2 * pstride) = h;
-  *reinterpret_cast<bf16x8*>(out + 3 * pstride) = l;
 }
 
 // C -= A B on 128 x 128 tiles from the planes, with the four real products
@@ -1196,7 +1204,7 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
       static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_update_planes),
                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBfLds);
       if (attr != hipSuccess) return attr;
-      hipLaunchKernelGGL(split_planes, dim3(4 * (RA + RB) / 256, K / kBK, b.nb), dim3(256), 0, s, b.d, r0, rend, c0,
+      hipLaunchKernelGGL(split_planes, dim3((4 * RA + RB + 255) / 256, K / kBK, b.nb), dim3(256), 0, s, b.d, r0, rend, c0,
                          cend, k0, K, b.planes, b.planes_stride, RA, RB);
       hipLaunchKernelGGL(gemm_update_planes, dim3((RB / kBT) * (RA / kBT) * b.nb), dim3(256), kBfLds, s, b.d, r0,
                          rend, c0, cend, k0, K, b.planes, b.planes_stride, RA, RB);
