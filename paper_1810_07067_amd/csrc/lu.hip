@@ -107,6 +107,33 @@ __device__ __forceinline__ void strip_store(double2* rowp, int w, const double2 
 // Thread tid owns rows c0 + tid + i * kPanelThreads, i < kRowsPerThread; the
 // column loop is unrolled so the strip is indexed with constants.
 // ---------------------------------------------------------------------------
+// Largest 64-bit key over the wave, returned to every lane: DPP within each
+// row of 16 lanes (quad swaps, half-row and row mirrors), then the four row
+// results read as scalars.  (A shuffle ladder goes through the LDS crossbar,
+// about a hundred cycles per dependent step.)
+template <int kCtrl>
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), kCtrl, 0xf, 0xf, false);
+  const unsigned long long y = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+  return y > x ? y : x;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  k = dpp_max_u64<0xb1>(k);   // quad_perm [1, 0, 3, 2]
+  k = dpp_max_u64<0x4e>(k);   // quad_perm [2, 3, 0, 1]
+  k = dpp_max_u64<0x141>(k);  // row_half_mirror
+  k = dpp_max_u64<0x140>(k);  // row_mirror
+  unsigned long long r = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)k, 16 * q);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k >> 32), 16 * q);
+    const unsigned long long y = ((unsigned long long)hi << 32) | lo;
+    r = y > r ? y : r;
+  }
+  return r;
+}
+
 template <typename R, int kRowsPerThread, int kBaseW>
 __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>::T> B, int c0, int w) {
   using T = typename V2<R>::T;
@@ -115,9 +142,11 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
   if (c0 >= n) return;
   T* M = mz.a;
   int32_t* piv = mz.piv;
-  __shared__ unsigned long long red_k[kPanelThreads / 64];
-  __shared__ T prow[kBaseW];
-  __shared__ T oldj[kBaseW];
+  // per column (two sets, by column parity): each wave's best key and the
+  // row it names, and row j as it was
+  __shared__ unsigned long long red_k[2][kPanelThreads / 64];
+  __shared__ T red_row[2][kPanelThreads / 64][kBaseW];
+  __shared__ T oldj[2][kBaseW];
   const int tid = threadIdx.x;
   const int rows = n - c0;
   // rows owned: r = c0 + tid + i * kPanelThreads
@@ -153,70 +182,72 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
           ((unsigned long long)__float_as_uint(a) << 32) | (unsigned)(0x7fffffff - r);
       best = (r >= j && r < rows && key > best) ? key : best;
     }
+    best = wave_max_u64(best);
+    // publish, before the one barrier of the column: the wave's best key,
+    // the row it names (from the lane that holds it), and row j (thread j
+    // holds it: j < kBaseW <= kPanelThreads)
+    const int pb = j & 1;
+    {
+      const int rb = 0x7fffffff - (int)(unsigned)(best & 0xffffffffu);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(best, off);
-      best = o > best ? o : best;
+      for (int i = 0; i < kRowsPerThread; ++i)
+        if (best != 0 && tid + i * kPanelThreads == rb) {
+#pragma unroll
+          for (int c = 0; c < kBaseW; ++c) red_row[pb][tid >> 6][c] = v[i][c];
+        }
     }
-    if ((tid & 63) == 0) red_k[tid >> 6] = best;
+    if ((tid & 63) == 0) red_k[pb][tid >> 6] = best;
+    if (tid == j) {
+#pragma unroll
+      for (int c = 0; c < kBaseW; ++c) oldj[pb][c] = v[0][c];
+    }
+    // The sets alternate by column parity: a thread writes column j + 1's set
+    // only after this barrier, which every thread passes only once done with
+    // column j - 1's reads of that set.
     __syncthreads();
     // every thread picks the pivot from the per-wave keys
     unsigned long long kq[kPanelThreads / 64];
 #pragma unroll
-    for (int q = 0; q < kPanelThreads / 64; ++q) kq[q] = red_k[q];
+    for (int q = 0; q < kPanelThreads / 64; ++q) kq[q] = red_k[pb][q];
 #pragma unroll
-    for (int q = 1; q < kPanelThreads / 64; ++q) best = kq[q] > best ? kq[q] : best;
-    best = kq[0] > best ? kq[0] : best;
+    for (int h = kPanelThreads / 128; h > 0; h >>= 1)  // tree: depth 4, not a chain of 16
+#pragma unroll
+      for (int q = 0; q < h; ++q) kq[q] = kq[q + h] > kq[q] ? kq[q + h] : kq[q];
+    best = kq[0];
     int p = 0x7fffffff - (int)(unsigned)(best & 0xffffffffu);
-    if ((best >> 32) == 0 || p >= rows) {  // no candidate, or a zero column
+    const int qb = (p % kPanelThreads) >> 6;  // the wave that holds row p
+    const bool none = (best >> 32) == 0 || p >= rows;  // no candidate, or a zero column
+    if (none) {
       if (tid == 0 && *mz.info == 0) *mz.info = c0 + j + 1;
       p = j;
     }
     if (tid == 0) piv[c0 + j] = c0 + p;
-    // swap local rows j and p through LDS: prow <- row p, oldj <- row j
-    const int oj = j % kPanelThreads, ij = j / kPanelThreads;
-    const int op = p % kPanelThreads, ip = p / kPanelThreads;
-    if (tid == op) {
+    T prow[kBaseW];
 #pragma unroll
-      for (int i = 0; i < kRowsPerThread; ++i)
-        if (i == ip) {
-#pragma unroll
-          for (int c = 0; c < kBaseW; ++c) prow[c] = v[i][c];
-        }
-    }
-    if (tid == oj) {
-#pragma unroll
-      for (int i = 0; i < kRowsPerThread; ++i)
-        if (i == ij) {
-#pragma unroll
-          for (int c = 0; c < kBaseW; ++c) oldj[c] = v[i][c];
-        }
-    }
-    __syncthreads();
+    for (int c = 0; c < kBaseW; ++c) prow[c] = none ? oldj[pb][c] : red_row[pb][qb][c];
+    // the interchange: the holder of row p takes row j, thread j takes row p
     if (p != j) {
+      const int op = p % kPanelThreads, ip = p / kPanelThreads;
       if (tid == op) {
 #pragma unroll
         for (int i = 0; i < kRowsPerThread; ++i)
           if (i == ip) {
 #pragma unroll
-            for (int c = 0; c < kBaseW; ++c) v[i][c] = oldj[c];
+            for (int c = 0; c < kBaseW; ++c) v[i][c] = oldj[pb][c];
           }
       }
-      if (tid == oj) {
+      if (tid == j) {
 #pragma unroll
-        for (int i = 0; i < kRowsPerThread; ++i)
-          if (i == ij) {
-#pragma unroll
-            for (int c = 0; c < kBaseW; ++c) v[i][c] = prow[c];
-          }
+        for (int c = 0; c < kBaseW; ++c) v[0][c] = prow[c];
       }
     }
     // pivot and multipliers
     T pv = prow[j];
-    R den = pv.x * pv.x + pv.y * pv.y;
+    const R den = pv.x * pv.x + pv.y * pv.y;
+    const R rden = den != 0 ? (R)1 / den : (R)0;
     T inv;
-    inv.x = den != 0 ? pv.x / den : (R)0;
-    inv.y = den != 0 ? -pv.y / den : (R)0;
+    inv.x = pv.x * rden;
+    inv.y = -pv.y * rden;
 #pragma unroll
     for (int i = 0; i < kRowsPerThread; ++i) {
       int r = tid + i * kPanelThreads;
@@ -235,8 +266,6 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
           }
       }
     }
-    // no barrier here: the next column's LDS writes come after its first
-    // barrier, which every thread reaches only once done with prow and red_*
   }
 #pragma unroll
   for (int i = 0; i < kRowsPerThread; ++i) {
