@@ -297,6 +297,27 @@ __global__ __launch_bounds__(256) void laswp(Mats<T> B, int k1, int k2, int cb, 
   }
 }
 
+// Sum over the 4 lanes of a quad, returned to each, in the order of a
+// butterfly (x_t + x_t^1) + (x_t^2 + x_t^3): two DPP quad permutations in
+// place of two LDS-permute shuffles.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, false));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename R>
+__device__ __forceinline__ R quad_sum(R x) {
+  x += dpp_move<0xb1>(x);  // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4e>(x);  // quad_perm [2, 3, 0, 1]
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // X <- L^{-1} X, L = unit lower A[k:k+h, k:k+h] (h <= 64), X = A[k:k+h, cb:ce]:
 // linv_block forms L^{-1} (identity-padded to 64 x 64) once per matrix, then
@@ -320,8 +341,8 @@ __global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int
   }
   __syncthreads();
   // column j by lanes 4j .. 4j + 3 of one wave: lane t sums the terms q = t
-  // (mod 4) of y_rj = [r == j] - sum_{j <= q < r} L[r][q] y_qj, two shuffles
-  // combine them, and lane t = 0 stores y_rj, which the four lanes read in
+  // (mod 4) of y_rj = [r == j] - sum_{j <= q < r} L[r][q] y_qj, a quad sum
+  // combines them, and lane t = 0 stores y_rj, which the four lanes read in
   // later rows (LDS accesses of a wave complete in order)
   const int j = tid >> 2, t = tid & 3;
   for (int r = 0; r < 64; ++r) {
@@ -332,10 +353,8 @@ __global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int
         sx -= l.x * x.x - l.y * x.y;
         sy -= l.x * x.y + l.y * x.x;
       }
-    sx += __shfl_xor(sx, 1);
-    sy += __shfl_xor(sy, 1);
-    sx += __shfl_xor(sx, 2);
-    sy += __shfl_xor(sy, 2);
+    sx = quad_sum(sx);
+    sy = quad_sum(sy);
     if (t == 0) {
       T y;
       y.x = r == j ? (R)1 : (r > j && r < h ? sx : (R)0);
@@ -386,10 +405,8 @@ __global__ __launch_bounds__(256) void trsm_small(Mats<typename V2<R>::T> B, int
         sr += l.x * x[q].x - l.y * x[q].y;
         si += l.x * x[q].y + l.y * x[q].x;
       }
-    sr += __shfl_xor(sr, 1);
-    si += __shfl_xor(si, 1);
-    sr += __shfl_xor(sr, 2);
-    si += __shfl_xor(si, 2);
+    sr = quad_sum(sr);
+    si = quad_sum(si);
     if ((i & 3) == t) {
       x[i >> 2].x -= sr;
       x[i >> 2].y -= si;
