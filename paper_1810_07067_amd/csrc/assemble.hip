@@ -170,7 +170,7 @@ constexpr int kFarThreads = 64;
 // give each XCD one contiguous range of items: the three modes that read a
 // table slice (m - 1, m, m + 1) then run back to back on one XCD and find the
 // slice in its L2, instead of reading it from HBM three times.
-__global__ __launch_bounds__(kFarThreads) void assemble_far(AsmParams P, int n_items) {
+__global__ __launch_bounds__(kFarThreads, 3) void assemble_far(AsmParams P, int n_items) {
   const int per = (n_items + 7) / 8;
   const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (item >= n_items) return;
@@ -179,23 +179,39 @@ __global__ __launch_bounds__(kFarThreads) void assemble_far(AsmParams P, int n_i
   const int mi = item % nm;
   const int jb = (item / nm) % njb;
   const int t = item / nm / njb;
-  const int j = jb * kFarThreads + threadIdx.x;
+  const int j0 = jb * kFarThreads, j = j0 + threadIdx.x;
   const int m = P.m_lo + mi;
-  if (j >= P.N) return;
-  if (near_panel(P, t / kOrder, j / kOrder)) return;
-  const Consts C = make_consts(P);
-  cd T[3][kTypes];
-  load_T(P, m, t, j, T);
+  const int pt = t / kOrder;
+  const bool mine = j < P.N && !near_panel(P, pt, j / kOrder);
   cd B[4][4];
-  block4(T, m, P.r[t], P.tr[t], P.tz[t], P.r[j], P.tr[j], P.tz[j], C, B);
-  const double sc = P.sqw[t] * P.sqw[j];  // w_j * sqrt(w_t / w_j)
+  double sc = 0.0;
+  if (mine) {
+    const Consts C = make_consts(P);
+    cd T[3][kTypes];
+    load_T(P, m, t, j, T);
+    block4(T, m, P.r[t], P.tr[t], P.tz[t], P.r[j], P.tr[j], P.tz[j], C, B);
+    sc = P.sqw[t] * P.sqw[j];  // w_j * sqrt(w_t / w_j)
+  }
+  // each row of the blocks goes out through LDS, so that a store instruction
+  // writes 64 consecutive entries of the row (1 KB) instead of 16 bytes
+  // every 64 (the workgroup is one wave)
+  __shared__ double2 S[4 * kFarThreads];
   const size_t n = 4 * (size_t)P.N;
   double2* A = P.A + (size_t)mi * n * n;
 #pragma unroll
   for (int al = 0; al < 4; ++al) {
-    double2* row = A + (4 * (size_t)t + al) * n + 4 * (size_t)j;
+    if (mine)
 #pragma unroll
-    for (int be = 0; be < 4; ++be) row[be] = make_double2(sc * B[al][be].re, sc * B[al][be].im);
+      for (int be = 0; be < 4; ++be) S[4 * threadIdx.x + be] = make_double2(sc * B[al][be].re, sc * B[al][be].im);
+    __syncthreads();
+    double2* row = A + (4 * (size_t)t + al) * n + 4 * (size_t)j0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e = v * kFarThreads + threadIdx.x;  // entry 4 (j - j0) + beta
+      const int je = j0 + (e >> 2);
+      if (je < P.N && !near_panel(P, pt, je / kOrder)) row[e] = S[e];
+    }
+    __syncthreads();
   }
 }
 
