@@ -217,10 +217,17 @@ __global__ __launch_bounds__(kFarThreads, 3) void assemble_far(AsmParams P, int 
 
 constexpr int kNearThreads = 256;
 
-__global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P) {
+// Work items (mode, target), mode fastest, each XCD a contiguous range (as
+// for the far blocks): the three modes that read a support slice of the table
+// run back to back on one XCD.
+__global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P, int n_items) {
   extern __shared__ double smem[];
-  const int t = blockIdx.x;
-  const int mi = blockIdx.y;
+  const int per = (n_items + 7) / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= n_items) return;
+  const int nm = P.m_hi - P.m_lo + 1;
+  const int mi = item % nm;
+  const int t = item / nm;
   const int m = P.m_lo + mi;
   const int S = P.S;
   double2* Bw = reinterpret_cast<double2*>(smem);  // [S][16]
@@ -293,7 +300,8 @@ hipError_t launch_assemble(const AsmParams& P, hipStream_t s) {
   if (e != hipSuccess) return e;
   size_t lds = sizeof(double2) * 16 * (size_t)P.S;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(assemble_near, dim3(P.N, nm), dim3(kNearThreads), lds, s, P);
+  const int n_near = nm * P.N;
+  hipLaunchKernelGGL(assemble_near, dim3(8 * ((n_near + 7) / 8)), dim3(kNearThreads), lds, s, P, n_near);
   return hipGetLastError();
 }
 
