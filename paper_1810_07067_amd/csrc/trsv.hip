@@ -81,21 +81,29 @@ __device__ __forceinline__ void load_row16(const double2* p, double2 (&a)[16]) {
 // start at Arow (leading dimension ld, 16-byte aligned rows), only columns
 // < kmax and rows with row_ok are read; B is a [64][kVB] tile in LDS with k at
 // row pk(k).
+// The lane's 16 operands of a 16 x 64 tile of A (rows Arow + li ld, columns
+// 16 q .. 16 q + 15), zero past kmax or where !row_ok.
 template <typename R>
-__device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t ld, bool row_ok, int kmax,
-                                         const typename C2<R>::T (*B)[kVB], typename Mf<R>::C4& cr,
-                                         typename Mf<R>::C4& ci) {
+__device__ __forceinline__ void tile_load(const typename C2<R>::T* Arow, size_t ld, bool row_ok, int kmax,
+                                          typename C2<R>::T (&a)[16]) {
   using T = typename C2<R>::T;
-  using C4 = typename Mf<R>::C4;
   const int lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
   const T* ap = Arow + (size_t)li * ld + 16 * q;
-  T a[16];
   if (row_ok && 16 * q + 16 <= kmax) {
     load_row16(ap, a);
   } else {
 #pragma unroll
     for (int s = 0; s < 16; ++s) a[s] = load_or_zero(ap + s, row_ok && 16 * q + s < kmax);
   }
+}
+
+// (cr, ci) += A B for the tile loaded by tile_load and the vector tile B
+template <typename R>
+__device__ __forceinline__ void tile_mul(const typename C2<R>::T (&a)[16], const typename C2<R>::T (*B)[kVB],
+                                         typename Mf<R>::C4& cr, typename Mf<R>::C4& ci) {
+  using T = typename C2<R>::T;
+  using C4 = typename Mf<R>::C4;
+  const int lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
   // three real products per complex one: t1 = Ar Br, t2 = Ai Bi,
   // t3 = (Ar + Ai)(Br + Bi); Re = t1 - t2, Im = t3 - t1 - t2
   C4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
@@ -108,6 +116,15 @@ __device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t l
   }
   cr += t1 - t2;
   ci += t3 - t1 - t2;
+}
+
+template <typename R>
+__device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t ld, bool row_ok, int kmax,
+                                         const typename C2<R>::T (*B)[kVB], typename Mf<R>::C4& cr,
+                                         typename Mf<R>::C4& ci) {
+  typename C2<R>::T a[16];
+  tile_load<R>(Arow, ld, row_ok, kmax, a);
+  tile_mul<R>(a, B, cr, ci);
 }
 
 // Inverses of the 64 x 64 diagonal blocks of the unit-lower L and upper U
@@ -227,35 +244,46 @@ __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, con
       xt[pk(r)][v] = T{cr[i], ci[i]};
       if (blockIdx.x == 0 && v < nv && r < h) Y[(size_t)s_off[v] * n + rb + r] = T{cr[i], ci[i]};
     }
-  } else {
+  }
+  // this workgroup's chunk: its tile of the factor and its entries of X do
+  // not depend on x_blk, so they are loaded before x_blk is staged
+  const int chunks = FWD ? nblk - 1 - blk : blk;
+  const bool active = (int)blockIdx.x < chunks;
+  const int c = FWD ? blk + 1 + (int)blockIdx.x : blk - 1 - (int)blockIdx.x;
+  const int cb = c * 64;
+  const int hc = min(64, n - cb);
+  const T* M = LU + (size_t)b.fac * stride;
+  const int r0 = 16 * w;
+  T a[16];
+  T o[4];
+  if (active) {
+    tile_load<R>(M + (size_t)(cb + r0) * n + rb, n, r0 + v < hc, h, a);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + Mf<R>::row(lane, i);
+      o[i] = load_or_zero(X + (size_t)s_off[v] * n + cb + r, v < nv && r < hc);
+    }
+  }
+  if (!first) {
     for (int e = tid; e < kVB * 64; e += 256) {
       const int vv = e >> 6, k = e & 63;
       xt[pk(k)][vv] = load_or_zero(Y + (size_t)s_off[vv] * n + rb + k, vv < nv && k < h);
     }
   }
   __syncthreads();
-  const int chunks = FWD ? nblk - 1 - blk : blk;
-  if ((int)blockIdx.x >= chunks) return;
-  const int c = FWD ? blk + 1 + (int)blockIdx.x : blk - 1 - (int)blockIdx.x;
-  const int cb = c * 64;
-  const int hc = min(64, n - cb);
-  const T* M = LU + (size_t)b.fac * stride;
+  if (!active) return;
   C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  const int r0 = 16 * w;
-  tile_mma<R>(M + (size_t)(cb + r0) * n + rb, n, r0 + v < hc, h, xt, cr, ci);
+  tile_mul<R>(a, xt, cr, ci);
   const bool next = blockIdx.x == 0;  // chunk c is the next block to solve
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = r0 + Mf<R>::row(lane, i);
-    T o = {0, 0};
     if (v < nv && r < hc) {
-      T* xp = X + (size_t)s_off[v] * n + cb + r;
-      o = *xp;
-      o.x -= cr[i];
-      o.y -= ci[i];
-      *xp = o;
+      o[i].x -= cr[i];
+      o[i].y -= ci[i];
+      X[(size_t)s_off[v] * n + cb + r] = o[i];
     }
-    if (next) xn[pk(r)][v] = o;
+    if (next) xn[pk(r)][v] = o[i];
   }
   if (!next) return;
   __syncthreads();
