@@ -134,7 +134,14 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k)
   return r;
 }
 
-template <typename R, int kRowsPerThread, int kBaseW>
+//
+// kLeft: the strip is the right half of a node of width 2 kBaseW whose left
+// strip [c0 - kBaseW, c0) has just been factored, and this kernel also does
+// that node's steps between the two strips: the left strip's interchanges
+// (composed, so that each row is loaded once from where it ends up coming
+// from), U12 = L11^{-1} A12 for rows [c0 - kBaseW, c0), and A22 -= L21 U12
+// for the rows below, before the strip is factored.
+template <typename R, int kRowsPerThread, int kBaseW, bool kLeft>
 __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>::T> B, int c0, int w) {
   using T = typename V2<R>::T;
   const Mz<T> mz = mat_at(B, blockIdx.z);
@@ -151,7 +158,79 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
   const int rows = n - c0;
   // rows owned: r = c0 + tid + i * kPanelThreads
   T v[kRowsPerThread][kBaseW];
-  if (sizeof(T) == 8 && (w & 1)) {
+  if constexpr (kLeft) {
+    __shared__ T u12[kBaseW][kBaseW];  // rows [cl, c0) of the strip, then U12
+    __shared__ T l11[kBaseW][kBaseW];
+    const int cl = c0 - kBaseW;
+    // after the interchanges (cl + k <-> pk[k], k = 0, 1, ...) row g holds
+    // what row sigma(g) held: sigma applies them in reverse order
+    int pk[kBaseW];
+#pragma unroll
+    for (int k = 0; k < kBaseW; ++k) pk[k] = piv[cl + k];
+    auto sigma = [&](int g) {
+#pragma unroll
+      for (int k = kBaseW - 1; k >= 0; --k) g = g == cl + k ? pk[k] : (g == pk[k] ? cl + k : g);
+      return g;
+    };
+    // L21 rows (the left strip's columns) of the thread's rows, loaded with
+    // the strip (the registers allow it at 2 rows per thread; at 4 rows per
+    // thread loading them a column at a time was slower than the separate
+    // launches this replaces)
+    static_assert(kRowsPerThread <= 2, "the fused strip holds L21 in registers");
+    T l21[kRowsPerThread][kBaseW];
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+      const int r = tid + i * kPanelThreads;
+      const bool rok = r < rows;
+      strip_load(M + (size_t)(rok ? sigma(c0 + r) : c0) * n + c0, kBaseW, rok, v[i]);
+      strip_load(M + (size_t)(c0 + (rok ? r : 0)) * n + cl, kBaseW, rok, l21[i]);
+    }
+    if (tid < kBaseW * kBaseW) {
+      const int r = tid / kBaseW, c = tid % kBaseW;
+      u12[r][c] = M[(size_t)sigma(cl + r) * n + c0 + c];
+      l11[r][c] = M[(size_t)(cl + r) * n + cl + c];
+    }
+    __syncthreads();
+    if (tid < kBaseW) {  // column tid of U12 by substitution
+#pragma unroll
+      for (int r = 1; r < kBaseW; ++r) {
+        T acc = u12[r][tid];
+#pragma unroll
+        for (int q = 0; q < r; ++q) {
+          const T l = l11[r][q], u = u12[q][tid];
+          acc.x -= l.x * u.x - l.y * u.y;
+          acc.y -= l.x * u.y + l.y * u.x;
+        }
+        u12[r][tid] = acc;
+      }
+    }
+    __syncthreads();
+    // A22 -= L21 U12 one row q of U12 at a time (a loop the compiler keeps,
+    // so that only one row of U12 is in registers)
+#pragma unroll 1
+    for (int q = 0; q < kBaseW; ++q) {
+      T u[kBaseW];
+#pragma unroll
+      for (int c = 0; c < kBaseW; ++c) u[c] = u12[q][c];
+#pragma unroll
+      for (int i = 0; i < kRowsPerThread; ++i) {
+        T l = l21[i][0];
+#pragma unroll
+        for (int t = 1; t < kBaseW; ++t) l = q == t ? l21[i][t] : l;
+#pragma unroll
+        for (int c = 0; c < kBaseW; ++c) {
+          v[i][c].x -= l.x * u[c].x - l.y * u[c].y;
+          v[i][c].y -= l.x * u[c].y + l.y * u[c].x;
+        }
+      }
+    }
+    // (every row of the strip was loaded before the first barrier, so the
+    // rows of U12 can be stored now)
+    if (tid < kBaseW * kBaseW) {
+      const int r = tid / kBaseW, c = tid % kBaseW;
+      M[(size_t)(cl + r) * n + c0 + c] = u12[r][c];
+    }
+  } else if (sizeof(T) == 8 && (w & 1)) {
     // odd width (not produced by the blocking used here): element loads
 #pragma unroll
     for (int i = 0; i < kRowsPerThread; ++i) {
@@ -1328,32 +1407,42 @@ hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, int k0, h
   const dim3 g(1, 1, b.nb), t(kPanelThreads);
   if constexpr (sizeof(R) == 4) {
     if (rows <= 2 * kPanelThreads && w <= 8) {
-      hipLaunchKernelGGL((base_panel<R, 2, 8>), g, t, 0, s, b.d, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 2, 8, false>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
     if (rows > 2 * kPanelThreads && rows <= 4 * kPanelThreads && w <= 8) {
-      hipLaunchKernelGGL((base_panel<R, 4, 8>), g, t, 0, s, b.d, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 4, 8, false>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
     if (rows > 4 * kPanelThreads && w <= 4) {
-      hipLaunchKernelGGL((base_panel<R, 8, 4>), g, t, 0, s, b.d, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 8, 4, false>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
   } else {
     if (rows <= 2 * kPanelThreads && w <= 8) {
-      hipLaunchKernelGGL((base_panel<R, 2, 8>), g, t, 0, s, b.d, c0, w);
+      hipLaunchKernelGGL((base_panel<R, 2, 8, false>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
     if (rows > 2 * kPanelThreads && w <= 4) {
       if (rows <= 4 * kPanelThreads)
-        hipLaunchKernelGGL((base_panel<R, 4, 4>), g, t, 0, s, b.d, c0, w);
+        hipLaunchKernelGGL((base_panel<R, 4, 4, false>), g, t, 0, s, b.d, c0, w);
       else
-        hipLaunchKernelGGL((base_panel<R, 8, 4>), g, t, 0, s, b.d, c0, w);
+        hipLaunchKernelGGL((base_panel<R, 8, 4, false>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
   }
   int h = w / 2;
   MSV_TRY(panel_rec<R>(b, c0, h, k0, s));
+  if constexpr (sizeof(R) == 4) {
+    // two 8-column base strips of at most 2048 rows: the right strip's kernel
+    // also applies the left strip's interchanges, U12 and the update of its
+    // rows (one launch in place of four)
+    if (w == 16 && h == 8 && rows <= 2 * kPanelThreads) {
+      hipLaunchKernelGGL((base_panel<R, 2, 8, true>), g, t, 0, s, b.d, c0 + h, h);
+      MSV_TRY(hipGetLastError());
+      return swaps<R>(b, c0 + h, c0 + w, c0, c0 + h, s);
+    }
+  }
   MSV_TRY(swaps<R>(b, c0, c0 + h, c0 + h, c0 + w, s));
   MSV_TRY(trsm<R>(b, c0, h, c0 + h, c0 + w, k0, s));
   MSV_TRY(gemm<R>(b, c0 + h, -1, c0 + h, c0 + w, c0, h, s));
