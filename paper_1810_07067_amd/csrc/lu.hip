@@ -765,6 +765,20 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
     return make_float4(ok ? r.x : 0.f, ok ? r.y : 0.f, ok ? r.z : 0.f, ok ? r.w : 0.f);
   };
   fetch(k0);
+  // the tile's block of C, loaded with the first chunk (it lies outside the
+  // operands, and the tile is this workgroup's alone): one round trip less
+  float2 cv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + Mfma<float>::row(lane, i);
+        const int gc = tc + wc + 16 * b + li;
+        const bool ok = gr < rend && gc < cend;
+        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
+      }
   for (int kc = k0; kc < kend; kc += kGK) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -814,19 +828,7 @@ __global__ __launch_bounds__(256) void gemm_update_c(Mats<float2> B, int r0, int
     }
     __syncthreads();
   }
-  // C -= A B: all 16 loads issued before the first subtraction
-  float2 cv[2][2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = tr + wr + 16 * a + Mfma<float>::row(lane, i);
-        const int gc = tc + wc + 16 * b + li;
-        const bool ok = gr < rend && gc < cend;
-        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
-      }
+  // C -= A B
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -916,6 +918,20 @@ __global__ __launch_bounds__(256) void gemm_update_bf(Mats<float2> B, int r0, in
     for (int t = 0; t < 8; ++t) rb[t] = pb[(size_t)(kc + t) * n];
   };
   fetch(k0);
+  // the tile's block of C, loaded with the first chunk (it lies outside the
+  // operands, and the tile is this workgroup's alone): one round trip less
+  float2 cv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = tr + wr + 16 * a + 4 * lq + i;
+        const int gc = tc + wc + 16 * b + li;
+        const bool ok = gr < rend && gc < cend;
+        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
+      }
   for (int kc = k0; kc < kend; kc += kBK) {
     {
       float re[8], im[8], sm[8];
@@ -982,19 +998,7 @@ __global__ __launch_bounds__(256) void gemm_update_bf(Mats<float2> B, int r0, in
     }
     __syncthreads();
   }
-  // C -= A B: all 16 loads issued before the first subtraction
-  float2 cv[2][2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = tr + wr + 16 * a + 4 * lq + i;
-        const int gc = tc + wc + 16 * b + li;
-        const bool ok = gr < rend && gc < cend;
-        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
-      }
+  // C -= A B
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
