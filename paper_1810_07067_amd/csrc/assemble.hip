@@ -231,6 +231,13 @@ __global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P, int n
   const int m = P.m_lo + mi;
   const int S = P.S;
   double2* Bw = reinterpret_cast<double2*>(smem);  // [S][16]
+  // the Lagrange rows this target uses: its own panel's row kt, then the
+  // adjacent panels' rows ([n][16] each), read from LDS in the contraction
+  double* Ls = smem + 2 * 16 * (size_t)S;
+  const int pt = t / kOrder, kt = t % kOrder;
+  for (int e = threadIdx.x; e < P.n_self * kOrder; e += kNearThreads)
+    Ls[e] = P.lag_self[(size_t)kt * P.n_self * kOrder + e];
+  for (int e = threadIdx.x; e < P.n_adj * kOrder; e += kNearThreads) Ls[P.n_self * kOrder + e] = P.lag_adj[e];
   const Consts C = make_consts(P);
   const double rt = P.r[t], trt = P.tr[t], tzt = P.tz[t];
   for (int s = threadIdx.x; s < S; s += kNearThreads) {
@@ -251,7 +258,6 @@ __global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P, int n
         Bw[s * 16 + al * 4 + be] = make_double2(wq * B[al][be].re, wq * B[al][be].im);
   }
   __syncthreads();
-  const int pt = t / kOrder, kt = t % kOrder;
   const int panels[3] = {pt, P.left[pt], P.right[pt]};
   const int s0[3] = {0, P.n_self, P.n_self + P.n_adj};
   const int ns[3] = {P.n_self, P.n_adj, P.n_adj};
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P, int n
     const int pi = e >> 8;
     const int ps = panels[pi];
     if (ps < 0) continue;
-    const double* lag = (pi == 0) ? P.lag_self + (size_t)kt * P.n_self * kOrder : P.lag_adj;
+    const double* lag = (pi == 0) ? Ls : Ls + P.n_self * kOrder;
     double re = 0.0, im = 0.0;
     for (int q = 0; q < ns[pi]; ++q) {
       double l = lag[q * kOrder + k];
@@ -298,8 +304,11 @@ hipError_t launch_assemble(const AsmParams& P, hipStream_t s) {
   hipLaunchKernelGGL(assemble_far, dim3(8 * ((n_items + 7) / 8)), dim3(kFarThreads), 0, s, P, n_items);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  size_t lds = sizeof(double2) * 16 * (size_t)P.S;
+  size_t lds = sizeof(double2) * 16 * (size_t)P.S + sizeof(double) * kOrder * (size_t)(P.n_self + P.n_adj);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&assemble_near), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+  if (e != hipSuccess) return e;
   const int n_near = nm * P.N;
   hipLaunchKernelGGL(assemble_near, dim3(8 * ((n_near + 7) / 8)), dim3(kNearThreads), lds, s, P, n_near);
   return hipGetLastError();
