@@ -376,26 +376,6 @@ __global__ __launch_bounds__(256) void laswp(Mats<T> B, int k1, int k2, int cb, 
   }
 }
 
-// Sum over the 4 lanes of a quad, returned to each, in the order of a
-// butterfly (x_t + x_t^1) + (x_t^2 + x_t^3): two DPP quad permutations in
-// place of two LDS-permute shuffles.
-template <int kCtrl>
-__device__ __forceinline__ float dpp_move(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, false));
-}
-template <int kCtrl>
-__device__ __forceinline__ double dpp_move(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-template <typename R>
-__device__ __forceinline__ R quad_sum(R x) {
-  x += dpp_move<0xb1>(x);  // quad_perm [1, 0, 3, 2]
-  x += dpp_move<0x4e>(x);  // quad_perm [2, 3, 0, 1]
-  return x;
-}
 
 // ---------------------------------------------------------------------------
 // X <- L^{-1} X, L = unit lower A[k:k+h, k:k+h] (h <= 64), X = A[k:k+h, cb:ce]:

@@ -34,13 +34,6 @@ template <typename R> struct C2;
 template <> struct C2<double> { using T = double2; };
 template <> struct C2<float> { using T = float2; };
 
-template <typename T>
-__device__ __forceinline__ T cfms(T acc, T a, T b) {  // acc - a b
-  acc.x -= a.x * b.x - a.y * b.y;
-  acc.y -= a.x * b.y + a.y * b.x;
-  return acc;
-}
-
 // 16x16x4 MFMA per real type.  Operands: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator element i of lane l is C[row(l, i)][l % 16].
 template <typename R> struct Mf;
@@ -129,46 +122,77 @@ __device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t l
 
 // Inverses of the 64 x 64 diagonal blocks of the unit-lower L and upper U
 // (zero beyond the matrix order), inv[f][blk][0] = L^-1, inv[f][blk][1] = U^-1.
-// Thread j forms column j by substitution; columns live in LDS.
+// Column j by the lanes 4j .. 4j + 3 of one wave: lane t sums the terms
+// k = t (mod 4) of the substitution, a quad sum combines them and lane t = 0
+// stores y, which the four lanes read in later rows (LDS accesses of a wave
+// complete in order).
 template <typename R>
-__global__ __launch_bounds__(64) void inv_diag(const typename C2<R>::T* LU, long long stride, int n,
-                                               typename C2<R>::T* inv) {
+__global__ __launch_bounds__(256) void inv_diag(const typename C2<R>::T* LU, long long stride, int n,
+                                                typename C2<R>::T* inv) {
   using T = typename C2<R>::T;
   __shared__ T D[64][65];
-  __shared__ T Y[64][64];
-  const int blk = blockIdx.x, f = blockIdx.y, j = threadIdx.x;
+  __shared__ T Y[64][65];
+  const int blk = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
+  const int j = tid >> 2, t = tid & 3;
   const int nblk = (n + 63) / 64;
   const int rb = blk * 64;
   const int h = min(64, n - rb);
   const T* M = LU + (size_t)f * stride;
-  const T zero = {0, 0};
-  for (int r = 0; r < 64; ++r) D[r][j] = load_or_zero(M + (size_t)(rb + r) * n + rb + j, r < h && j < h);
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    D[r][c] = load_or_zero(M + (size_t)(rb + r) * n + rb + c, r < h && c < h);
+  }
   __syncthreads();
   T* out = inv + ((size_t)f * nblk + blk) * 2 * 64 * 64;
   // L^-1 column j: y_r = [r == j] - sum_{j <= k < r} L[r][k] y_k
   for (int r = 0; r < 64; ++r) {
-    T y = (r == j && r < h) ? T{1, 0} : zero;
-    if (r < h && r > j)
-      for (int k = j; k < r; ++k) y = cfms(y, D[r][k], Y[k][j]);
-    Y[r][j] = y;
+    R sx = 0, sy = 0;
+    if (r > j && r < h)
+      for (int k = j + t; k < r; k += 4) {
+        const T l = D[r][k], y = Y[k][j];
+        sx += l.x * y.x - l.y * y.y;
+        sy += l.x * y.y + l.y * y.x;
+      }
+    sx = quad_sum(sx);
+    sy = quad_sum(sy);
+    if (t == 0) {
+      T y;
+      y.x = r == j && r < h ? (R)1 : (r > j && r < h ? -sx : (R)0);
+      y.y = r > j && r < h ? -sy : (R)0;
+      Y[r][j] = y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
-  for (int r = 0; r < 64; ++r) out[r * 64 + j] = Y[r][j];
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) out[e] = Y[e >> 6][e & 63];
+  __syncthreads();
   // U^-1 column j: y_r = ([r == j] - sum_{r < k <= j} U[r][k] y_k) / U[r][r]
   for (int r = 63; r >= 0; --r) {
-    T y = zero;
-    if (r < h && r <= j && j < h) {
-      y = (r == j) ? T{1, 0} : zero;
-      for (int k = r + 1; k <= j; ++k) y = cfms(y, D[r][k], Y[k][j]);
-      const T d = D[r][r];
-      const R den = d.x * d.x + d.y * d.y;
-      T q;
-      q.x = (y.x * d.x + y.y * d.y) / den;
-      q.y = (y.y * d.x - y.x * d.y) / den;
-      y = q;
+    R sx = 0, sy = 0;
+    const bool live = r < h && r <= j && j < h;
+    if (live)
+      for (int k = r + 1 + t; k <= j; k += 4) {
+        const T u = D[r][k], y = Y[k][j];
+        sx += u.x * y.x - u.y * y.y;
+        sy += u.x * y.y + u.y * y.x;
+      }
+    sx = quad_sum(sx);
+    sy = quad_sum(sy);
+    if (t == 0) {
+      T y = {0, 0};
+      if (live) {
+        const R bx = (r == j ? (R)1 : (R)0) - sx, by = -sy;
+        const T d = D[r][r];
+        const R den = d.x * d.x + d.y * d.y;
+        y.x = (bx * d.x + by * d.y) / den;
+        y.y = (by * d.x - bx * d.y) / den;
+      }
+      Y[r][j] = y;
     }
-    Y[r][j] = y;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
-  for (int r = 0; r < 64; ++r) out[64 * 64 + r * 64 + j] = Y[r][j];
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) out[64 * 64 + e] = Y[e >> 6][e & 63];
 }
 
 // perm[f][i]: source row of row i after the LAPACK-style interchanges ipiv[f]
@@ -378,11 +402,11 @@ hipError_t gather_c(const double2* in, float2* out, const int32_t* perm, const V
 }
 
 hipError_t lu_inv_diag_z(const double2* LU, long long stride, int n, int nfac, double2* inv, hipStream_t s) {
-  hipLaunchKernelGGL(inv_diag<double>, dim3((n + 63) / 64, nfac), dim3(64), 0, s, LU, stride, n, inv);
+  hipLaunchKernelGGL(inv_diag<double>, dim3((n + 63) / 64, nfac), dim3(256), 0, s, LU, stride, n, inv);
   return hipGetLastError();
 }
 hipError_t lu_inv_diag_c(const float2* LU, long long stride, int n, int nfac, float2* inv, hipStream_t s) {
-  hipLaunchKernelGGL(inv_diag<float>, dim3((n + 63) / 64, nfac), dim3(64), 0, s, LU, stride, n, inv);
+  hipLaunchKernelGGL(inv_diag<float>, dim3((n + 63) / 64, nfac), dim3(256), 0, s, LU, stride, n, inv);
   return hipGetLastError();
 }
 
