@@ -158,6 +158,11 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
   const int rows = n - c0;
   // rows owned: r = c0 + tid + i * kPanelThreads
   T v[kRowsPerThread][kBaseW];
+  // Global stores wait out at the next barrier (the workgroup release waits
+  // for them), so the pivots and U12 are stored after the column loop: thread
+  // j keeps column j's pivot row.
+  int my_piv = 0;
+  T my_u12 = {0, 0};  // kLeft: entry (tid / W, tid % W) of U12, tid < W^2
   if constexpr (kLeft) {
     __shared__ T u12[kBaseW][kBaseW];  // rows [cl, c0) of the strip, then U12
     __shared__ T l11[kBaseW][kBaseW];
@@ -205,6 +210,7 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
       }
     }
     __syncthreads();
+    if (tid < kBaseW * kBaseW) my_u12 = u12[tid / kBaseW][tid % kBaseW];
     // A22 -= L21 U12 one row q of U12 at a time (a loop the compiler keeps,
     // so that only one row of U12 is in registers)
 #pragma unroll 1
@@ -223,12 +229,6 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
           v[i][c].y -= l.x * u[c].y + l.y * u[c].x;
         }
       }
-    }
-    // (every row of the strip was loaded before the first barrier, so the
-    // rows of U12 can be stored now)
-    if (tid < kBaseW * kBaseW) {
-      const int r = tid / kBaseW, c = tid % kBaseW;
-      M[(size_t)(cl + r) * n + c0 + c] = u12[r][c];
     }
   } else if (sizeof(T) == 8 && (w & 1)) {
     // odd width (not produced by the blocking used here): element loads
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
       if (tid == 0 && *mz.info == 0) *mz.info = c0 + j + 1;
       p = j;
     }
-    if (tid == 0) piv[c0 + j] = c0 + p;
+    if (tid == j) my_piv = c0 + p;
     T prow[kBaseW];
 #pragma unroll
     for (int c = 0; c < kBaseW; ++c) prow[c] = none ? oldj[pb][c] : red_row[pb][qb][c];
@@ -344,6 +344,15 @@ __global__ __launch_bounds__(kPanelThreads) void base_panel(Mats<typename V2<R>:
             v[i][c].y -= l.x * u.y + l.y * u.x;
           }
       }
+    }
+  }
+  if (tid < w) piv[c0 + tid] = my_piv;
+  if constexpr (kLeft) {
+    // the rows of U12 (every row of the strip was loaded before the first
+    // barrier, so they may be overwritten)
+    if (tid < kBaseW * kBaseW) {
+      const int r = tid / kBaseW, c = tid % kBaseW;
+      M[(size_t)(c0 - kBaseW + r) * n + c0 + c] = my_u12;
     }
   }
 #pragma unroll
