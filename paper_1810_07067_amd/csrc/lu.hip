@@ -416,6 +416,7 @@ __global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int
   for (int r = 0; r < 64; ++r) {
     R sx = 0, sy = 0;
     if (r > j && r < h)
+#pragma unroll 4
       for (int q = j + t; q < r; q += 4) {
         const T l = Ls[r][q], x = Y[q][j];
         sx -= l.x * x.x - l.y * x.y;

@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void inv_diag(const typename C2<R>::T* LU, lon
   for (int r = 0; r < 64; ++r) {
     R sx = 0, sy = 0;
     if (r > j && r < h)
+#pragma unroll 4
       for (int k = j + t; k < r; k += 4) {
         const T l = D[r][k], y = Y[k][j];
         sx += l.x * y.x - l.y * y.y;
@@ -171,6 +172,7 @@ __global__ __launch_bounds__(256) void inv_diag(const typename C2<R>::T* LU, lon
     R sx = 0, sy = 0;
     const bool live = r < h && r <= j && j < h;
     if (live)
+#pragma unroll 4
       for (int k = r + 1 + t; k <= j; k += 4) {
         const T u = D[r][k], y = Y[k][j];
         sx += u.x * y.x - u.y * y.y;
