@@ -393,8 +393,8 @@ __global__ __launch_bounds__(256) void laswp(Mats<T> B, int k1, int k2, int cb, 
 // workgroup reads its whole tile into LDS before writing it back).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int k, int h,
-                                                  typename V2<R>::T* linv, int slot) {
+__global__ __launch_bounds__(1024) void linv_block(Mats<typename V2<R>::T> B, int k, int h,
+                                                   typename V2<R>::T* linv, int slot) {
   using T = typename V2<R>::T;
   __shared__ T Ls[64][65];
   __shared__ T Y[64][65];
@@ -403,27 +403,48 @@ __global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int
   if (k >= n) return;
   const T* M = mz.a;
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    Ls[r][c] = load_or_zero(M + (size_t)(k + r) * n + k + c, r < h && c < h);
+  // the four loads of a thread are issued together (elements outside the
+  // block read the corner element and are zeroed afterwards)
+  T v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + 1024 * i, r = e >> 6, c = e & 63;
+    v[i] = M[(size_t)k * n + k + (r < h && c < h ? (size_t)r * n + c : 0)];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + 1024 * i, r = e >> 6, c = e & 63;
+    if (!(r < h && c < h)) v[i].x = v[i].y = 0;
+    Ls[r][c] = v[i];
   }
   __syncthreads();
-  // column j by lanes 4j .. 4j + 3 of one wave: lane t sums the terms q = t
-  // (mod 4) of y_rj = [r == j] - sum_{j <= q < r} L[r][q] y_qj, a quad sum
-  // combines them, and lane t = 0 stores y_rj, which the four lanes read in
-  // later rows (LDS accesses of a wave complete in order)
-  const int j = tid >> 2, t = tid & 3;
+  // column j by the 16 lanes 16j .. 16j + 15 of one wave: lane t sums the
+  // terms q = j + t + 16i (i < 4) of y_rj = [r == j] - sum_{j <= q < r}
+  // L[r][q] y_qj, four DPP steps add the 16 partial sums, and lane t = 0
+  // stores y_rj, which the lanes read in later rows (LDS accesses of a wave
+  // complete in order).  Terms past r read a column element already known
+  // (y_jj) times zero, so the four loads of a row are issued together.
+  const int j = tid >> 4, t = tid & 15;
   for (int r = 0; r < 64; ++r) {
     R sx = 0, sy = 0;
-    if (r > j && r < h)
-#pragma unroll 4
-      for (int q = j + t; q < r; q += 4) {
-        const T l = Ls[r][q], x = Y[q][j];
-        sx -= l.x * x.x - l.y * x.y;
-        sy -= l.x * x.y + l.y * x.x;
+    if (r > j && r < h) {
+      T l[4], x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = j + t + 16 * i;
+        const int qc = q < r ? q : j;
+        l[i] = Ls[r][qc];
+        x[i] = Y[qc][j];
       }
-    sx = quad_sum(sx);
-    sy = quad_sum(sy);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const R m = j + t + 16 * i < r ? (R)1 : (R)0;
+        sx -= m * (l[i].x * x[i].x - l[i].y * x[i].y);
+        sy -= m * (l[i].x * x[i].y + l[i].y * x[i].x);
+      }
+    }
+    sx = row_sum(sx);
+    sy = row_sum(sy);
     if (t == 0) {
       T y;
       y.x = r == j ? (R)1 : (r > j && r < h ? sx : (R)0);
@@ -435,7 +456,7 @@ __global__ __launch_bounds__(256) void linv_block(Mats<typename V2<R>::T> B, int
   }
   __syncthreads();
   T* out = linv + ((size_t)blockIdx.z * kLinvSlots + slot) * 64 * 64;
-  for (int e = tid; e < 64 * 64; e += 256) out[e] = Y[e >> 6][e & 63];
+  for (int e = tid; e < 64 * 64; e += 1024) out[e] = Y[e >> 6][e & 63];
 }
 
 // In-panel TRSM (at most 64 columns right of a block of h = 4..64 rows):
@@ -502,9 +523,23 @@ __global__ __launch_bounds__(256) void trsm_inv(Mats<typename V2<R>::T> B, int k
   const T* Li = linv + ((size_t)blockIdx.z * kLinvSlots + slot) * 64 * 64;
   const int c0 = cb + blockIdx.x * 64;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    Xs[r][c] = load_or_zero(M + (size_t)(k + r) * n + c0 + c, r < h && c0 + c < ce);
+  // the tile's 16 loads per thread and the 16 inverse elements of the
+  // thread's MFMA operands are all issued before the first wait (tile
+  // elements outside the block read its first element and are zeroed)
+  T v[16], a[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = tid + 256 * i, r = e >> 6, c = e & 63;
+    v[i] = M[(size_t)k * n + c0 + (r < h && c0 + c < ce ? (size_t)r * n + c : 0)];
+  }
+  const T* Lrow = Li + (size_t)(16 * wave + (lane & 15)) * 64 + (lane >> 4);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) a[s] = Lrow[4 * s];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = tid + 256 * i, r = e >> 6, c = e & 63;
+    if (!(r < h && c0 + c < ce)) v[i].x = v[i].y = 0;
+    Xs[r][c] = v[i];
   }
   __syncthreads();
   if (16 * wave >= h) return;
@@ -514,18 +549,16 @@ __global__ __launch_bounds__(256) void trsm_inv(Mats<typename V2<R>::T> B, int k
     cr[j] = C4{0, 0, 0, 0};
     ci[j] = C4{0, 0, 0, 0};
   }
-  const T* Lrow = Li + (size_t)(16 * wave + (lane & 15)) * 64 + (lane >> 4);
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     const int kk = 4 * s + (lane >> 4);
-    const T a = Lrow[4 * s];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const T bb = Xs[kk][16 * j + (lane & 15)];
-      cr[j] = Mfma<R>::op(a.x, bb.x, cr[j]);
-      cr[j] = Mfma<R>::op(-a.y, bb.y, cr[j]);
-      ci[j] = Mfma<R>::op(a.x, bb.y, ci[j]);
-      ci[j] = Mfma<R>::op(a.y, bb.x, ci[j]);
+      cr[j] = Mfma<R>::op(a[s].x, bb.x, cr[j]);
+      cr[j] = Mfma<R>::op(-a[s].y, bb.y, cr[j]);
+      ci[j] = Mfma<R>::op(a[s].x, bb.y, ci[j]);
+      ci[j] = Mfma<R>::op(a[s].y, bb.x, ci[j]);
     }
   }
 #pragma unroll
@@ -1050,29 +1083,29 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
     split8(im, h, l);
     *reinterpret_cast<bf16x8*>(out + 2 * ps) = h;
     *reinterpret_cast<bf16x8*>(out + 3 * ps) = l;
-  } else if (g < 4 * RA + RB) {
-    // B: one thread per column, all 32 k of the chunk (consecutive lanes read
-    // consecutive columns and write consecutive 64-byte rows of each plane)
-    const int j = g - 4 * RA;
+  } else if (g < 4 * (RA + RB)) {
+    // B: 4 threads per column, 8 consecutive k each; a wave takes 64
+    // consecutive columns at one k quarter (512-byte row segments read, the
+    // 16-byte quarter q of 64 consecutive 64-byte rows written per plane)
+    const int gb = g - 4 * RA;
+    const int q = (gb >> 6) & 3;
+    const int j = ((gb >> 8) << 6) + (gb & 63);
     const bool ok = live && c0 + j < cend;
-    const float2* src = mz.a + (size_t)(k0 + 32 * c) * n + (ok ? c0 + j : 0);
-    __bf16* out = w + (size_t)kPlanes * RA * K + ((size_t)c * kPlanes * RB + j) * 32;
+    const float2* src = mz.a + (size_t)(k0 + 32 * c + 8 * q) * n + (ok ? c0 + j : 0);
+    __bf16* out = w + (size_t)kPlanes * RA * K + ((size_t)c * kPlanes * RB + j) * 32 + 8 * q;
     const size_t ps = (size_t)RB * 32;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const float2 v = ok ? src[(size_t)(8 * q + t) * n] : make_float2(0.f, 0.f);
-        re[t] = v.x;
-        im[t] = v.y;
-      }
-      split8(re, h, l);
-      *reinterpret_cast<bf16x8*>(out + 8 * q) = h;
-      *reinterpret_cast<bf16x8*>(out + ps + 8 * q) = l;
-      split8(im, h, l);
-      *reinterpret_cast<bf16x8*>(out + 2 * ps + 8 * q) = h;
-      *reinterpret_cast<bf16x8*>(out + 3 * ps + 8 * q) = l;
+    for (int t = 0; t < 8; ++t) {
+      const float2 v = ok ? src[(size_t)t * n] : make_float2(0.f, 0.f);
+      re[t] = v.x;
+      im[t] = v.y;
     }
+    split8(re, h, l);
+    *reinterpret_cast<bf16x8*>(out) = h;
+    *reinterpret_cast<bf16x8*>(out + ps) = l;
+    split8(im, h, l);
+    *reinterpret_cast<bf16x8*>(out + 2 * ps) = h;
+    *reinterpret_cast<bf16x8*>(out + 3 * ps) = l;
   }
 }
 
@@ -1323,7 +1356,7 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
       static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_update_planes),
                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBfLds);
       if (attr != hipSuccess) return attr;
-      hipLaunchKernelGGL(split_planes, dim3((4 * RA + RB + 255) / 256, K / kBK, b.nb), dim3(256), 0, s, b.d, r0, rend, c0,
+      hipLaunchKernelGGL(split_planes, dim3((4 * (RA + RB) + 255) / 256, K / kBK, b.nb), dim3(256), 0, s, b.d, r0, rend, c0,
                          cend, k0, K, b.planes, b.planes_stride, RA, RB);
       hipLaunchKernelGGL(gemm_update_planes, dim3((RB / kBT) * (RA / kBT) * b.nb), dim3(256), kBfLds, s, b.d, r0,
                          rend, c0, cend, k0, K, b.planes, b.planes_stride, RA, RB);
@@ -1374,7 +1407,7 @@ hipError_t trsm(const Batch<typename V2<R>::T>& b, int k, int h, int cb, int ce,
       return trsm<R>(b, k + h1, h - h1, cb, ce, k0, s);
     }
     const int slot = (k - k0) / 64;
-    if (h < 64) hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, k, h, b.linv, slot);
+    if (h < 64) hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(1024), 0, s, b.d, k, h, b.linv, slot);
     hipLaunchKernelGGL(trsm_inv<R>, dim3((cmax - cb + 63) / 64, 1, b.nb), dim3(256), 0, s, b.d, k, h, cb, ce, b.linv,
                        slot);
     return hipGetLastError();
@@ -1445,7 +1478,7 @@ hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, int k0, h
   MSV_TRY(swaps<R>(b, c0 + h, c0 + w, c0, c0 + h, s));
   if (w == 64 && (c0 - k0) % 64 == 0) {
     // a finished 64-wide sub-panel: keep the inverse of its unit-lower block
-    hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(256), 0, s, b.d, c0, 64, b.linv, (c0 - k0) / 64);
+    hipLaunchKernelGGL(linv_block<R>, dim3(1, 1, b.nb), dim3(1024), 0, s, b.d, c0, 64, b.linv, (c0 - k0) / 64);
     MSV_TRY(hipGetLastError());
   }
   return hipSuccess;

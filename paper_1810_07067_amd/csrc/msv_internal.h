@@ -122,6 +122,15 @@ __device__ __forceinline__ R quad_sum(R x) {
   x += dpp_move<0x4e>(x);  // quad_perm [2, 3, 0, 1]
   return x;
 }
+// Sum over the 16 lanes of a DPP row, returned to each: the quad sums, then
+// quads paired by the half-row mirror and halves by the row mirror.
+template <typename R>
+__device__ __forceinline__ R row_sum(R x) {
+  x = quad_sum(x);
+  x += dpp_move<0x141>(x);  // row_half_mirror
+  x += dpp_move<0x140>(x);  // row_mirror
+  return x;
+}
 
 struct LuMat {
   void* a;

@@ -55,6 +55,27 @@ template <> struct Mf<float> {
 // LDS row of element k of a 64 x kVB vector tile.
 __device__ __forceinline__ int pk(int k) { return 4 * (k & 15) + (k >> 4); }
 
+// xs[pk(k)][v] = V[off[v] n + rb + k] for the batch's vectors v < nv and
+// k < h, zero elsewhere (256 threads, four elements each).  The four loads of
+// a thread are issued before any is used: elements outside read element rb of
+// the batch's first vector (off[v] = 0 past nv) and are zeroed afterwards.
+template <typename T>
+__device__ __forceinline__ void stage_vectors(T (*xs)[kVB], const T* V, const int* off, int nv, int n, int rb,
+                                              int h) {
+  T t[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = threadIdx.x + 256 * i, vv = e >> 6, k = e & 63;
+    t[i] = V[(size_t)off[vv] * n + rb + (k < h ? k : 0)];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = threadIdx.x + 256 * i, vv = e >> 6, k = e & 63;
+    if (!(vv < nv && k < h)) t[i].x = t[i].y = 0;
+    xs[pk(k)][vv] = t[i];
+  }
+}
+
 // a[s] = p[s], s < 16, with 16-byte loads (p 16-byte aligned).
 __device__ __forceinline__ void load_row16(const float2* p, float2 (&a)[16]) {
   const float4* q = reinterpret_cast<const float4*>(p);
@@ -122,40 +143,62 @@ __device__ __forceinline__ void tile_mma(const typename C2<R>::T* Arow, size_t l
 
 // Inverses of the 64 x 64 diagonal blocks of the unit-lower L and upper U
 // (zero beyond the matrix order), inv[f][blk][0] = L^-1, inv[f][blk][1] = U^-1.
-// Column j by the lanes 4j .. 4j + 3 of one wave: lane t sums the terms
-// k = t (mod 4) of the substitution, a quad sum combines them and lane t = 0
-// stores y, which the four lanes read in later rows (LDS accesses of a wave
-// complete in order).
+// Column j by the 16 lanes 16j .. 16j + 15 of one wave: lane t sums the terms
+// k = t (mod 16) of the substitution (at most four), four DPP steps add the
+// 16 partial sums and lane t = 0 stores y, which the lanes read in later rows
+// (LDS accesses of a wave complete in order).  Terms outside the sum read a
+// known element of the column times zero, so a row's loads issue together.
 template <typename R>
-__global__ __launch_bounds__(256) void inv_diag(const typename C2<R>::T* LU, long long stride, int n,
-                                                typename C2<R>::T* inv) {
+__global__ __launch_bounds__(1024) void inv_diag(const typename C2<R>::T* LU, long long stride, int n,
+                                                 typename C2<R>::T* inv) {
   using T = typename C2<R>::T;
   __shared__ T D[64][65];
   __shared__ T Y[64][65];
   const int blk = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
-  const int j = tid >> 2, t = tid & 3;
+  const int j = tid >> 4, t = tid & 15;
   const int nblk = (n + 63) / 64;
   const int rb = blk * 64;
   const int h = min(64, n - rb);
   const T* M = LU + (size_t)f * stride;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    D[r][c] = load_or_zero(M + (size_t)(rb + r) * n + rb + c, r < h && c < h);
+  {
+    // four loads per thread issued together; elements outside the block read
+    // its corner and are zeroed afterwards
+    T v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 1024 * i, r = e >> 6, c = e & 63;
+      v[i] = M[(size_t)rb * n + rb + (r < h && c < h ? (size_t)r * n + c : 0)];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 1024 * i, r = e >> 6, c = e & 63;
+      if (!(r < h && c < h)) v[i].x = v[i].y = 0;
+      D[r][c] = v[i];
+    }
   }
   __syncthreads();
   T* out = inv + ((size_t)f * nblk + blk) * 2 * 64 * 64;
   // L^-1 column j: y_r = [r == j] - sum_{j <= k < r} L[r][k] y_k
   for (int r = 0; r < 64; ++r) {
     R sx = 0, sy = 0;
-    if (r > j && r < h)
-#pragma unroll 4
-      for (int k = j + t; k < r; k += 4) {
-        const T l = D[r][k], y = Y[k][j];
-        sx += l.x * y.x - l.y * y.y;
-        sy += l.x * y.y + l.y * y.x;
+    if (r > j && r < h) {
+      T l[4], y[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = j + t + 16 * i;
+        const int kc = k < r ? k : j;
+        l[i] = D[r][kc];
+        y[i] = Y[kc][j];
       }
-    sx = quad_sum(sx);
-    sy = quad_sum(sy);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const R m = j + t + 16 * i < r ? (R)1 : (R)0;
+        sx += m * (l[i].x * y[i].x - l[i].y * y[i].y);
+        sy += m * (l[i].x * y[i].y + l[i].y * y[i].x);
+      }
+    }
+    sx = row_sum(sx);
+    sy = row_sum(sy);
     if (t == 0) {
       T y;
       y.x = r == j && r < h ? (R)1 : (r > j && r < h ? -sx : (R)0);
@@ -163,23 +206,34 @@ __global__ __launch_bounds__(256) void inv_diag(const typename C2<R>::T* LU, lon
       Y[r][j] = y;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  for (int e = tid; e < 64 * 64; e += 256) out[e] = Y[e >> 6][e & 63];
+  for (int e = tid; e < 64 * 64; e += 1024) out[e] = Y[e >> 6][e & 63];
   __syncthreads();
-  // U^-1 column j: y_r = ([r == j] - sum_{r < k <= j} U[r][k] y_k) / U[r][r]
+  // U^-1 column j: y_r = ([r == j] - sum_{r < k <= j} U[r][k] y_k) / U[r][r];
+  // every Y element holds a finite value from the pass above when first read
   for (int r = 63; r >= 0; --r) {
     R sx = 0, sy = 0;
     const bool live = r < h && r <= j && j < h;
-    if (live)
-#pragma unroll 4
-      for (int k = r + 1 + t; k <= j; k += 4) {
-        const T u = D[r][k], y = Y[k][j];
-        sx += u.x * y.x - u.y * y.y;
-        sy += u.x * y.y + u.y * y.x;
+    if (live) {
+      T u[4], y[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = r + 1 + t + 16 * i;
+        const int kc = k <= j ? k : j;
+        u[i] = D[r][kc];
+        y[i] = Y[kc][j];
       }
-    sx = quad_sum(sx);
-    sy = quad_sum(sy);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const R m = r + 1 + t + 16 * i <= j ? (R)1 : (R)0;
+        sx += m * (u[i].x * y[i].x - u[i].y * y[i].y);
+        sy += m * (u[i].x * y[i].y + u[i].y * y[i].x);
+      }
+    }
+    sx = row_sum(sx);
+    sy = row_sum(sy);
     if (t == 0) {
       T y = {0, 0};
       if (live) {
@@ -192,9 +246,10 @@ __global__ __launch_bounds__(256) void inv_diag(const typename C2<R>::T* LU, lon
       Y[r][j] = y;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  for (int e = tid; e < 64 * 64; e += 256) out[64 * 64 + e] = Y[e >> 6][e & 63];
+  for (int e = tid; e < 64 * 64; e += 1024) out[64 * 64 + e] = Y[e >> 6][e & 63];
 }
 
 // perm[f][i]: source row of row i after the LAPACK-style interchanges ipiv[f]
@@ -257,10 +312,7 @@ __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, con
   const T* inv_f = inv + (size_t)b.fac * nblk * inv_blk + (FWD ? 0 : 64 * 64);
   if (first) {
     // x_blk = inv(T_blk,blk) b_blk, in every workgroup; workgroup 0 stores it
-    for (int e = tid; e < kVB * 64; e += 256) {
-      const int vv = e >> 6, k = e & 63;
-      xn[pk(k)][vv] = load_or_zero(X + (size_t)s_off[vv] * n + rb + k, vv < nv && k < h);
-    }
+    stage_vectors(xn, X, s_off, nv, n, rb, h);
     __syncthreads();
     C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
     tile_mma<R>(inv_f + blk * inv_blk + (size_t)(16 * w) * 64, 64, true, 64, xn, cr, ci);
@@ -287,14 +339,14 @@ __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, con
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = r0 + Mf<R>::row(lane, i);
-      o[i] = load_or_zero(X + (size_t)s_off[v] * n + cb + r, v < nv && r < hc);
+      o[i] = X[(size_t)s_off[v] * n + cb + (r < hc ? r : 0)];
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (!(v < nv && r0 + Mf<R>::row(lane, i) < hc)) o[i].x = o[i].y = 0;
   }
   if (!first) {
-    for (int e = tid; e < kVB * 64; e += 256) {
-      const int vv = e >> 6, k = e & 63;
-      xt[pk(k)][vv] = load_or_zero(Y + (size_t)s_off[vv] * n + rb + k, vv < nv && k < h);
-    }
+    stage_vectors(xt, Y, s_off, nv, n, rb, h);
   }
   __syncthreads();
   if (!active) return;
@@ -342,10 +394,7 @@ __global__ __launch_bounds__(256) void residual_b(const double2* A, long long st
   C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
   for (int k0 = 0; k0 < n; k0 += 64) {
     __syncthreads();
-    for (int e = tid; e < kVB * 64; e += 256) {
-      const int v = e >> 6, k = e & 63;
-      xt[pk(k)][v] = load_or_zero(x + (size_t)s_off[v] * n + k0 + k, v < nv);
-    }
+    stage_vectors(xt, x, s_off, nv, n, k0, 64);
     __syncthreads();
     tile_mma<double>(M + (size_t)r0 * n + k0, n, row_ok, 64, xt, cr, ci);
   }
@@ -404,11 +453,11 @@ hipError_t gather_c(const double2* in, float2* out, const int32_t* perm, const V
 }
 
 hipError_t lu_inv_diag_z(const double2* LU, long long stride, int n, int nfac, double2* inv, hipStream_t s) {
-  hipLaunchKernelGGL(inv_diag<double>, dim3((n + 63) / 64, nfac), dim3(256), 0, s, LU, stride, n, inv);
+  hipLaunchKernelGGL(inv_diag<double>, dim3((n + 63) / 64, nfac), dim3(1024), 0, s, LU, stride, n, inv);
   return hipGetLastError();
 }
 hipError_t lu_inv_diag_c(const float2* LU, long long stride, int n, int nfac, float2* inv, hipStream_t s) {
-  hipLaunchKernelGGL(inv_diag<float>, dim3((n + 63) / 64, nfac), dim3(256), 0, s, LU, stride, n, inv);
+  hipLaunchKernelGGL(inv_diag<float>, dim3((n + 63) / 64, nfac), dim3(1024), 0, s, LU, stride, n, inv);
   return hipGetLastError();
 }
 
