@@ -55,24 +55,34 @@ template <> struct Mf<float> {
 // LDS row of element k of a 64 x kVB vector tile.
 __device__ __forceinline__ int pk(int k) { return 4 * (k & 15) + (k >> 4); }
 
-// xs[pk(k)][v] = V[off[v] n + rb + k] for the batch's vectors v < nv and
-// k < h, zero elsewhere (256 threads, four elements each).  The four loads of
-// a thread are issued before any is used: elements outside read element rb of
-// the batch's first vector (off[v] = 0 past nv) and are zeroed afterwards.
+// A 64 x kVB vector tile xs[pk(k)][v] = V[off_v n + rb + k] (vectors v < nv,
+// k < h; zero elsewhere) staged by 256 threads in two steps, so that other
+// loads can be issued between them: load_vectors issues the thread's four
+// loads (element k = lane of the vectors v = wave + 4 i, whose offsets the
+// caller passes in offs, 0 past nv), store_vectors zeroes what lies outside
+// and writes the tile.
 template <typename T>
-__device__ __forceinline__ void stage_vectors(T (*xs)[kVB], const T* V, const int* off, int nv, int n, int rb,
-                                              int h) {
-  T t[4];
+__device__ __forceinline__ void load_vectors(T (&t)[4], const T* V, const int (&offs)[4], int n, int rb, int h) {
+  const int k = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t[i] = V[(size_t)offs[i] * n + rb + (k < h ? k : 0)];
+}
+template <typename T>
+__device__ __forceinline__ void store_vectors(T (*xs)[kVB], T (&t)[4], int nv, int h) {
+  const int k = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int e = threadIdx.x + 256 * i, vv = e >> 6, k = e & 63;
-    t[i] = V[(size_t)off[vv] * n + rb + (k < h ? k : 0)];
+    if (!(w + 4 * i < nv && k < h)) t[i].x = t[i].y = 0;
+    xs[pk(k)][w + 4 * i] = t[i];
   }
+}
+// offs[i] = offset of vector w + 4 i of the batch (0 past nv); w is uniform
+// over the wave, so these are scalar loads
+__device__ __forceinline__ void batch_offsets(const VecBatch& b, int nv, int w, int (&offs)[4]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int e = threadIdx.x + 256 * i, vv = e >> 6, k = e & 63;
-    if (!(vv < nv && k < h)) t[i].x = t[i].y = 0;
-    xs[pk(k)][vv] = t[i];
+    const int o = b.off[w + 4 * i];
+    offs[i] = w + 4 * i < nv ? o : 0;
   }
 }
 
@@ -298,81 +308,83 @@ __global__ __launch_bounds__(256) void tri_step(const typename C2<R>::T* LU, con
   using C4 = typename Mf<R>::C4;
   __shared__ T xt[64][kVB];  // x_blk
   __shared__ T xn[64][kVB];  // a right-hand-side block
-  __shared__ int s_off[kVB];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int v = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int v = lane & 15, q = lane >> 4;
   const VecBatch& b = vb[blockIdx.y];
   const int nv = b.nv;
-  if (tid < kVB) s_off[tid] = tid < nv ? b.off[tid] : 0;
-  __syncthreads();
-  const int nblk = (n + 63) / 64;
+  int offs[4];
+  batch_offsets(b, nv, w, offs);
+  const int nblk = n / 64;
   const int rb = blk * 64;
-  const int h = min(64, n - rb);
   const size_t inv_blk = 2 * 64 * 64;
   const T* inv_f = inv + (size_t)b.fac * nblk * inv_blk + (FWD ? 0 : 64 * 64);
-  if (first) {
-    // x_blk = inv(T_blk,blk) b_blk, in every workgroup; workgroup 0 stores it
-    stage_vectors(xn, X, s_off, nv, n, rb, h);
-    __syncthreads();
-    C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-    tile_mma<R>(inv_f + blk * inv_blk + (size_t)(16 * w) * 64, 64, true, 64, xn, cr, ci);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = 16 * w + Mf<R>::row(lane, i);
-      xt[pk(r)][v] = T{cr[i], ci[i]};
-      if (blockIdx.x == 0 && v < nv && r < h) Y[(size_t)s_off[v] * n + rb + r] = T{cr[i], ci[i]};
-    }
-  }
-  // this workgroup's chunk: its tile of the factor and its entries of X do
-  // not depend on x_blk, so they are loaded before x_blk is staged
+  // Every load that does not wait on another is issued up front: the lane's
+  // vector offset, x_blk (the previous launch's result), this workgroup's
+  // tile of the factor, its entries of X, and, in workgroup 0, the inverse of
+  // the next diagonal block.  A workgroup past the last chunk (only when
+  // there is a single block) reads block blk instead.
+  const int lo = b.off[v];
+  T t[4];
+  load_vectors(t, first ? X : Y, offs, n, rb, 64);
   const int chunks = FWD ? nblk - 1 - blk : blk;
   const bool active = (int)blockIdx.x < chunks;
-  const int c = FWD ? blk + 1 + (int)blockIdx.x : blk - 1 - (int)blockIdx.x;
+  const bool next = blockIdx.x == 0;  // chunk c is the next block to solve
+  const int c = active ? (FWD ? blk + 1 + (int)blockIdx.x : blk - 1 - (int)blockIdx.x) : blk;
   const int cb = c * 64;
-  const int hc = min(64, n - cb);
-  const T* M = LU + (size_t)b.fac * stride;
   const int r0 = 16 * w;
-  T a[16];
+  const T* M = LU + (size_t)b.fac * stride;
+  T a[16], ai[16];
+  load_row16(M + (size_t)(cb + r0 + v) * n + rb + 16 * q, a);
+  // (complex64 only: with complex128 operands the preloaded inverse would
+  // leave one wave per SIMD)
+  constexpr bool kPreInv = sizeof(R) == 4;
+  if (kPreInv && next) load_row16(inv_f + c * inv_blk + (size_t)(r0 + v) * 64 + 16 * q, ai);
+  const size_t vo = (size_t)(v < nv ? lo : 0) * n;
   T o[4];
-  if (active) {
-    tile_load<R>(M + (size_t)(cb + r0) * n + rb, n, r0 + v < hc, h, a);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o[i] = X[vo + cb + r0 + Mf<R>::row(lane, i)];
+  if (first) {
+    // x_blk = inv(T_blk,blk) b_blk, in every workgroup; workgroup 0 stores it
+    T ab[16];
+    load_row16(inv_f + blk * inv_blk + (size_t)(r0 + v) * 64 + 16 * q, ab);
+    store_vectors(xn, t, nv, 64);
+    __syncthreads();
+    C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    tile_mul<R>(ab, xn, cr, ci);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = r0 + Mf<R>::row(lane, i);
-      o[i] = X[(size_t)s_off[v] * n + cb + (r < hc ? r : 0)];
+      xt[pk(r)][v] = T{cr[i], ci[i]};
+      if (next && v < nv) Y[vo + rb + r] = T{cr[i], ci[i]};
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (!(v < nv && r0 + Mf<R>::row(lane, i) < hc)) o[i].x = o[i].y = 0;
-  }
-  if (!first) {
-    stage_vectors(xt, Y, s_off, nv, n, rb, h);
+  } else {
+    store_vectors(xt, t, nv, 64);
   }
   __syncthreads();
   if (!active) return;
   C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
   tile_mul<R>(a, xt, cr, ci);
-  const bool next = blockIdx.x == 0;  // chunk c is the next block to solve
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = r0 + Mf<R>::row(lane, i);
-    if (v < nv && r < hc) {
-      o[i].x -= cr[i];
-      o[i].y -= ci[i];
-      X[(size_t)s_off[v] * n + cb + r] = o[i];
-    }
-    if (next) xn[pk(r)][v] = o[i];
+    T y;
+    y.x = v < nv ? o[i].x - cr[i] : (R)0;
+    y.y = v < nv ? o[i].y - ci[i] : (R)0;
+    if (v < nv) X[vo + cb + r] = y;
+    if (next) xn[pk(r)][v] = y;
   }
   if (!next) return;
   __syncthreads();
   // x_c = inv(T_cc) b_c
   cr = C4{0, 0, 0, 0};
   ci = C4{0, 0, 0, 0};
-  tile_mma<R>(inv_f + c * inv_blk + (size_t)(16 * w) * 64, 64, true, 64, xn, cr, ci);
+  if (!kPreInv) load_row16(inv_f + c * inv_blk + (size_t)(r0 + v) * 64 + 16 * q, ai);
+  tile_mul<R>(ai, xn, cr, ci);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = 16 * w + Mf<R>::row(lane, i);
-    if (v < nv && r < hc) Y[(size_t)s_off[v] * n + cb + r] = T{cr[i], ci[i]};
+    const int r = r0 + Mf<R>::row(lane, i);
+    if (v < nv) Y[vo + cb + r] = T{cr[i], ci[i]};
   }
 }
 
@@ -384,17 +396,22 @@ __global__ __launch_bounds__(256) void residual_b(const double2* A, long long st
   using C4 = Mf<double>::C4;
   __shared__ double2 xt[64][kVB];
   __shared__ int s_off[kVB];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const VecBatch& b = vb[blockIdx.y];
   const int nv = b.nv;
   if (tid < kVB) s_off[tid] = tid < nv ? b.off[tid] : 0;
+  int offs[4];
+  batch_offsets(b, nv, w, offs);
   const double2* M = A + (size_t)b.fac * stride;
   const int r0 = blockIdx.x * 64 + 16 * w;
   const bool row_ok = r0 + (lane & 15) < n;
   C4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
   for (int k0 = 0; k0 < n; k0 += 64) {
     __syncthreads();
-    stage_vectors(xt, x, s_off, nv, n, k0, 64);
+    double2 t[4];
+    load_vectors(t, x, offs, n, k0, 64);
+    store_vectors(xt, t, nv, 64);
     __syncthreads();
     tile_mma<double>(M + (size_t)r0 * n + k0, n, row_ok, 64, xt, cr, ci);
   }
@@ -415,7 +432,8 @@ template <typename R>
 hipError_t solve_batches(const typename C2<R>::T* LU, const typename C2<R>::T* inv, long long stride, int n,
                          const VecBatch* d_vb, int nvb, typename C2<R>::T* X, typename C2<R>::T* Y,
                          hipStream_t s) {
-  const int nblk = (n + 63) / 64;
+  if (n % 64 != 0) return hipErrorInvalidValue;
+  const int nblk = n / 64;
   // launch i updates the blocks after i and solves block i + 1 (forward);
   // the last block is solved by the launch before it
   const int nfwd = nblk > 1 ? nblk - 1 : 1;
