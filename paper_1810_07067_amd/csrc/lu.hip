@@ -375,8 +375,26 @@ __global__ __launch_bounds__(256) void laswp(Mats<T> B, int k1, int k2, int cb, 
   const int32_t* piv = mz.piv;
   int c = cb + blockIdx.x * 256 + threadIdx.x;
   if (c >= ce) return;
-  for (int k = k1; k < k2; ++k) {
-    int p = piv[k];
+  // groups of 8 interchanges: the group's pivots are read together, so only
+  // the interchanges actually made (p != k; most pivots lie on the diagonal)
+  // wait on memory, not every pivot read; a shorter rest goes one at a time
+  int k0 = k1;
+  for (; k0 + 8 <= k2; k0 += 8) {
+    int p[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) p[j] = piv[k0 + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (p[j] != k0 + j) {
+        const size_t rk = (size_t)(k0 + j) * n + c, rp = (size_t)p[j] * n + c;
+        const T a = M[rk], bb = M[rp];
+        M[rk] = bb;
+        M[rp] = a;
+      }
+    }
+  }
+  for (int k = k0; k < k2; ++k) {
+    const int p = piv[k];
     if (p != k) {
       T a = M[(size_t)k * n + c];
       M[(size_t)k * n + c] = M[(size_t)p * n + c];
