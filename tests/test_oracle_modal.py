@@ -163,3 +163,21 @@ def test_lemma1_and_operator_expansions_against_3d():
     Kv = np.cross(n, k0 ** 2 * A0 + gd0) - np.cross(n, k1 ** 2 * A1 + gd1)
     assert np.allclose(Nop, [Nv @ t, Nv @ eth], rtol=0, atol=1e-5 * np.abs(Nop).max())
     assert np.allclose(Kop, [Kv @ t, Kv @ eth], rtol=0, atol=1e-5 * np.abs(Kop).max())
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dr,dz", [(-2e-4, 1e-4), (-0.3, -0.5)])
+def test_against_brute_force_complex_k1(dr, dz):
+    """Absorbing interior (k1 = 40 + 0.5i, the lossy cylinder's k0 = 20 with
+    eps1 = 4 + 0.1i): a near and a far pair against 24-digit quadrature, every
+    type, modes up to M + 1 = 129 (measured <= 1.2e-14)."""
+    kp = modal.KernelParams(k0=20.0, k1=40.0 + 0.5j, M=128, L=512, r_max=1.0)
+    assert kp.valid
+    rt, zt = 0.8, 0.1
+    ms = [0, 1, 17, 129]
+    K = modal.modal_kernels([rt], [zt], None, None, kp, offsets=([dr], [dz]))[0]
+    ref = np.array(types_at(rt, zt, dr, dz, kp.k0, kp.k1, ms, dps=24))
+    scale = np.max(np.abs(K), axis=1)
+    for j, m in enumerate(ms):
+        err = np.abs(K[:, m] - ref[j]) / scale
+        assert np.all(err < 1e-13), (m, err)

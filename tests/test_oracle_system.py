@@ -1,5 +1,19 @@
 """Whole-chain pins for the oracle: mode parity, the trivial medium, the Mie
-series (P8), and energy balance for a lossless sphere (P10)."""
+series for dielectric, magnetic and absorbing spheres, reciprocity of the far
+field, energy balance for a lossless sphere, and absorption with the optical
+theorem for lossy bodies.
+
+Why 1e-10 is not the bound against Mie: the oracle's far field moves by about
+as much as its Mie error (1.1-1.3e-9 on the 8-panel sphere) when every kernel
+of the table is perturbed by 1e-14 relative noise, the accuracy of the kernels
+themselves (they agree with 24-digit quadrature to ~1e-14).  The rows next to
+the axis carry 1/r_t and 1/r_t^2 factors of the mode operators (Lemma 1 and
+the N, K expansions of Section 3) whose terms cancel, so kernel rounding is
+amplified there; more panels (12: 8.0e-10, 16: 2.2e-9) or dyadic refinement at
+the poles (3 levels: 1.4e-9, 6: 1.4e-9) do not lower the error, so it is not
+discretization error.  The tests below therefore bound the Mie error by the
+measured value with a small margin and check that it stays within a few times
+the oracle's own rounding sensitivity."""
 import numpy as np
 import pytest
 
@@ -8,7 +22,9 @@ from oracle import assemble, discretize, farfield, modal, solve
 from workloads import geometry, incident, rules
 
 
-def build(curve, k0, eps1, M, L, mu1=1.0):
+def build(curve, k0, eps1, M, L, mu1=1.0, noise=0.0):
+    """Oracle table and matrices; noise > 0 perturbs every table entry by that
+    relative amount (seeded complex Gaussian) to measure rounding sensitivity."""
     (ys, ws), (ya, wa) = rules.load_rules()
     sup = discretize.support_points(curve, (ys, ws), (ya, wa))
     omega = k0
@@ -16,21 +32,42 @@ def build(curve, k0, eps1, M, L, mu1=1.0):
     kp = modal.KernelParams(k0, k1, M, L, float(curve.r.max()))
     assert kp.valid
     tab = modal.tabulate(curve, sup, kp)
+    if noise:
+        rng = np.random.default_rng(7)
+        tab = tab * (1 + noise * (rng.standard_normal(tab.shape) + 1j * rng.standard_normal(tab.shape)))
     w = geometry.gl_weights(curve)
     mats = [assemble.assemble_mode(curve, sup, tab, m, k0, k1, omega, 1.0, 1.0, eps1, mu1, w)
             for m in range(M + 1)]
     return sup, tab, w, mats
 
 
-@pytest.fixture(scope="module")
-def sphere_case():
+def sphere_solution(eps1, mu1=1.0, k0=1.0, M=16, L=64, noise=0.0, deg=30.0):
     curve = geometry.sphere(8)
-    M, L, k0, eps1 = 16, 64, 1.0, 2.25
-    sup, tab, w, mats = build(curve, k0, eps1, M, L)
-    d, p = incident.tilted_direction(30.0)
+    sup, tab, w, mats = build(curve, k0, eps1, M, L, mu1, noise)
+    d, p = incident.tilted_direction(deg)
     rhs = incident.rhs_modes(curve, [(d, p)], k0, -M, M)
     x = solve.solve_modes(mats, w, rhs, -M, M)
-    return dict(curve=curve, M=M, k0=k0, eps1=eps1, w=w, mats=mats, x=x, d=d, p=p)
+    return dict(curve=curve, M=M, k0=k0, eps1=eps1, mu1=mu1, w=w, mats=mats, x=x, d=d, p=p)
+
+
+def random_dirs(n, seed=0):
+    rng = np.random.default_rng(seed)
+    dirs = rng.standard_normal((n, 3))
+    return dirs / np.linalg.norm(dirs, axis=1)[:, None]
+
+
+def mie_error(c, dirs):
+    E = farfield.far_field(c["curve"], c["w"], c["x"][:, 0], -c["M"], c["k0"], c["k0"], 1.0, dirs)
+    e = np.cross(np.cross(c["d"], c["p"]), c["d"])
+    n_rel = np.sqrt(complex(c["eps1"] * c["mu1"]))
+    Em = mie.far_field(c["k0"], 1.0, n_rel, c["d"], e, dirs, mu=1.0, mu1=c["mu1"])
+    scale = np.max(np.linalg.norm(Em, axis=1))
+    return E, np.max(np.linalg.norm(E - Em, axis=1)) / scale, scale
+
+
+@pytest.fixture(scope="module")
+def sphere_case():
+    return sphere_solution(2.25)
 
 
 def test_mode_parity():
@@ -73,18 +110,126 @@ def test_trivial_medium_scatters_nothing():
 
 @pytest.mark.slow
 def test_mie_far_field(sphere_case):
+    """Dielectric sphere (eps1 = 2.25, k0 = 1) against the Mie series; measured
+    1.74e-9, and the oracle's own change under 1e-14 kernel noise is 1.1e-9."""
     c = sphere_case
-    rng = np.random.default_rng(0)
-    dirs = rng.standard_normal((24, 3))
-    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
-    E = farfield.far_field(c["curve"], c["w"], c["x"][:, 0], -c["M"], c["k0"], c["k0"], 1.0, dirs)
+    dirs = random_dirs(24)
+    E, err, scale = mie_error(c, dirs)
+    assert err < 2.5e-9, err
+    noisy = sphere_solution(c["eps1"], noise=1e-14)
+    En = farfield.far_field(noisy["curve"], noisy["w"], noisy["x"][:, 0], -c["M"], c["k0"], c["k0"], 1.0, dirs)
+    sens = np.max(np.linalg.norm(En - E, axis=1)) / scale
+    assert 1e-10 < sens and err < 3 * sens, (err, sens)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("eps1,mu1,bound", [
+    (3.0, 2.0, 5e-9),                 # magnetic contrast: the (mu0 - mu1) N^{k0} term
+    (2.25 + 0.3j, 1.0, 3e-9),         # absorbing: complex k1
+    (3.0 + 0.2j, 2.0 + 0.1j, 5e-9),   # absorbing and magnetic
+])
+def test_mie_far_field_magnetic_and_lossy(eps1, mu1, bound):
+    """Spheres with mu1 != mu0 and complex eps1, mu1 against the Mie series
+    with the permeability ratio (Bohren & Huffman's a_n, b_n): pins the mu
+    weights of eq. mullerrep and the complex-k1 kernels end to end.  Measured
+    3.2e-9, 1.9e-9 and 3.5e-9; the oracle's change under 1e-14 kernel noise is
+    1.5e-9, 1.1e-9 and 1.4e-9 (a wrong weight or sign gives errors of percent)."""
+    c = sphere_solution(eps1, mu1)
+    _, err, _ = mie_error(c, random_dirs(24))
+    assert err < bound, err
+
+
+def test_mie_series_self_consistency():
+    """The reference itself: the forward amplitude gives the extinction sum
+    (optical theorem), lossless spheres have sigma_ext = sigma_sca, absorbing
+    ones sigma_ext > sigma_sca, and an impedance-matched sphere (eps1 = mu1)
+    does not scatter backwards."""
+    d, e = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0])
+    for n_rel, mu1, lossy in ((1.5, 1.0, False), (np.sqrt(6.0), 2.0, False),
+                             (np.sqrt((3 + 0.2j) * (2 + 0.1j)), 2 + 0.1j, True)):
+        ext, sca = mie.cross_sections(1.0, 1.0, n_rel, mu1=mu1)
+        a, b = mie.mie_coefficients(1.0, n_rel, 30, 1.0, mu1)
+        S0, _ = mie.amplitudes(a, b, 1.0)
+        # E_inf(d) = (i/k) S(0) e, sigma_ext = (4 pi / k) Im(e . E_inf(d))
+        assert abs(4 * np.pi * np.real(S0) - ext) < 1e-13 * ext
+        if lossy:
+            assert ext - sca > 1e-3 * ext
+        else:
+            assert abs(ext - sca) < 1e-13 * ext
+    back = mie.far_field(1.3, 1.0, 2.0, d, e, [[1e-12, 0.0, -1.0]], mu=1.0, mu1=2.0)
+    fwd = mie.far_field(1.3, 1.0, 2.0, d, e, [[0.6, 0.0, 0.8]], mu=1.0, mu1=2.0)
+    assert np.abs(back).max() < 1e-14 * np.abs(fwd).max()
+
+
+def _absorbed_power(c):
+    """P_abs = -pi sum_m int Re(M2 conj(J1) - M1 conj(J2)) r ds (net power into
+    the body; n . (t x e_theta) = -1) for a unit-amplitude plane wave."""
+    X = c["x"][:, 0].reshape(2 * c["M"] + 1, c["curve"].n, 4)
+    J1, J2, M1, M2 = (X[:, :, i] for i in range(4))
+    rw = c["curve"].r * c["w"]
+    return -np.pi * np.sum(np.real(M2 * np.conj(J1) - M1 * np.conj(J2)) * rw[None, :])
+
+
+def _sphere_grid(n_th=40, n_ph=80):
+    """Gauss-Legendre in cos(theta) x trapezoid in phi on the unit sphere."""
+    ct, wt = np.polynomial.legendre.leggauss(n_th)
+    ph = 2 * np.pi * np.arange(n_ph) / n_ph
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([np.outer(st, np.cos(ph)), np.outer(st, np.sin(ph)),
+                     np.outer(ct, np.ones(n_ph))], axis=-1).reshape(-1, 3)
+    return dirs, np.repeat(wt, n_ph) * (2 * np.pi / n_ph)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("body", ["sphere", "spheroid"])
+def test_absorption_and_optical_theorem(body):
+    """A lossy body (eps1 = 2.25 + 0.3i) absorbs (P_abs > 0), and
+    sigma_ext = sigma_sca + sigma_abs with sigma_ext = (4 pi / k0) Im(e . E_inf(d)),
+    sigma_sca = int |E_inf|^2 dOmega, sigma_abs = P_abs / (1/2)."""
+    k0, eps1, M = 1.0, 2.25 + 0.3j, 16
+    if body == "sphere":
+        c = sphere_solution(eps1, M=M)
+    else:
+        curve = geometry.spheroid(8, 1.5)
+        _, _, w, mats = build(curve, k0, eps1, M, 64)
+        d, p = incident.tilted_direction(40.0)
+        x = solve.solve_modes(mats, w, incident.rhs_modes(curve, [(d, p)], k0, -M, M), -M, M)
+        c = dict(curve=curve, M=M, k0=k0, w=w, x=x, d=d, p=p)
     e = np.cross(np.cross(c["d"], c["p"]), c["d"])
-    Em = mie.far_field(c["k0"], 1.0, np.sqrt(c["eps1"]), c["d"], e, dirs)
-    err = np.max(np.linalg.norm(E - Em, axis=1)) / np.max(np.linalg.norm(Em, axis=1))
-    # 8 equal panels on the semicircle: ~1.7e-9, limited by the rows next to the
-    # axis, where the 1/r_t and 1/r_t^2 factors of the mode operators amplify
-    # rounding of the kernels
-    assert err < 5e-9, err
+    ff = lambda dirs: farfield.far_field(c["curve"], c["w"], c["x"][:, 0], -M, k0, k0, 1.0, dirs)
+    ext = 4 * np.pi / k0 * np.imag(np.dot(e, ff(c["d"][None, :])[0]))
+    dirs, wq = _sphere_grid()
+    sca = float(np.sum(wq * np.sum(np.abs(ff(dirs)) ** 2, axis=1)))
+    absorbed = 2 * _absorbed_power(c)
+    assert absorbed > 1e-2 * ext
+    assert abs(ext - sca - absorbed) < 1e-8 * ext, (ext, sca, absorbed)
+    if body == "sphere":
+        mext, msca = mie.cross_sections(k0, 1.0, np.sqrt(eps1))
+        assert abs(ext - mext) < 1e-8 * mext and abs(sca - msca) < 1e-8 * msca
+
+
+@pytest.mark.slow
+def test_reciprocity():
+    """e_j . E_inf(-d_j; d_i, e_i) = e_i . E_inf(-d_i; d_j, e_j) for plane waves
+    E = e exp(i k0 d.x), e perpendicular to d (Colton & Kress), on a lossy 1:1.5
+    spheroid with four seeded directions: every ordered pair."""
+    k0, eps1, M = 1.5, 2.5 + 0.2j, 16
+    curve = geometry.spheroid(8, 1.5)
+    _, _, w, mats = build(curve, k0, eps1, M, 64)
+    waves = incident.random_directions(11, 4)
+    waves = [(d, np.cross(np.cross(d, p), d) / np.linalg.norm(np.cross(d, p))) for d, p in waves]
+    rhs = incident.rhs_modes(curve, waves, k0, -M, M)
+    x = solve.solve_modes(mats, w, rhs, -M, M)
+    amp = {}
+    for i, (di, ei) in enumerate(waves):
+        E = farfield.far_field(curve, w, x[:, i], -M, k0, k0, 1.0, np.array([-dj for dj, _ in waves]))
+        for j, (dj, ej) in enumerate(waves):
+            amp[i, j] = np.dot(ej, E[j])
+    scale = max(abs(v) for v in amp.values())
+    for i in range(4):
+        for j in range(i + 1, 4):
+            # measured up to 1.3e-9 of the largest amplitude: the rounding floor above
+            assert abs(amp[i, j] - amp[j, i]) < 3e-9 * scale, (i, j, amp[i, j], amp[j, i])
 
 
 @pytest.mark.slow
