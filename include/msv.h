@@ -100,13 +100,33 @@ int32_t msv_num_support(const msv_plan *plan);
 size_t msv_table_entries(const msv_plan *plan);
 int32_t msv_matrix_order(const msv_plan *plan);
 
+/* Device memory owned by a plan (not the caller's table, matrices, right-hand
+ * sides or solutions).  msv_workspace_bytes is an upper bound, computable
+ * before any plan exists, on what a plan of n_nodes nodes and n_support support
+ * slots holds once n_modes modes are factored (msv_factor) and a solve of
+ * n_solve_vectors (mode, right-hand side) vectors at once has run: geometry,
+ * pivots, LU workspace, complex64 factors (precision 1), diagonal-block
+ * inverses and the solve workspace.  It counts the near-pair list at its
+ * largest (every pair), so it exceeds the real footprint by at most
+ * 8 N (N + S) bytes plus one batch record per factored mode.  Returns 0 for
+ * invalid arguments.  msv_plan_device_bytes is what the plan holds now.
+ * Neither touches the device. */
+size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t n_modes, int32_t n_solve_vectors,
+                           int32_t precision);
+size_t msv_plan_device_bytes(const msv_plan *plan);
+
 /* Modal Green's functions (Section 4): for every target node t, every source
  * point s (the N nodes, then the S support nodes of t) and every mode
  * m = 0..M+1, the nine quantities
- *   0 g^{k0}  1 d_r g^{k0}  2 d_z g^{k0}  3 g^{k1}  4 d_r g^{k1}  5 d_z g^{k1}
+ *   0 g^{k0}            1 d_r g^{k0}              2 d_z g^{k0}
+ *   3 g^{k0}-g^{k1}     4 d_r (g^{k0}-g^{k1})     5 d_z (g^{k0}-g^{k1})
  *   6 d_rr(g^{k0}-g^{k1})  7 d_rz(g^{k0}-g^{k1})  8 d_zz(g^{k0}-g^{k1})
  * with g^k_m = int_0^{2pi} e^{ik rho}/(4 pi rho) e^{-i m phi} dphi (eq. green11)
- * and derivatives with respect to the target coordinates.
+ * and derivatives with respect to the target coordinates.  The interior
+ * kernels enter the Mueller system only through differences with the exterior
+ * ones (eq. mullerrep: K^{k0} - K^{k1}, mu0 N^{k0} - mu1 N^{k1}); types 3-5 are
+ * those differences, evaluated from analytic differences of the integrands so
+ * that nothing cancels when the two kernels are close (g^{k1} = type 0 - type 3).
  * d_kern: device, [M+2][9][N][N+S] complex128, written in full (coincident
  * pairs t = s and unused support slots are 0).  kern_elems must equal
  * msv_table_entries(plan). */
@@ -123,21 +143,38 @@ msv_status msv_tabulate(msv_plan *plan, msv_c128 *d_kern, size_t kern_elems, voi
 msv_status msv_assemble(msv_plan *plan, const msv_c128 *d_kern, int32_t m_lo, int32_t m_hi,
                         msv_c128 *d_A, void *stream);
 
-/* LU with partial pivoting of each matrix of d_A (as written by msv_assemble
- * for the same m_lo..m_hi).  precision 0: in place in d_A; precision 1: the plan
- * keeps complex64 factors and d_A is left intact for the refinement residual.
- * The plan keeps the pivots (and remembers d_A, which must stay valid and
- * unchanged until the last msv_solve).  Returns MSV_ESINGULAR after the stream
- * completes if a zero pivot was met (checked lazily by msv_solve). */
+/* The per-mode direct solve of Section 6: the discretized Mueller system of
+ * each azimuthal mode (eq. mullerrep after the separation of variables of
+ * Section 3) is a dense 4N x 4N system, factored once by LU with partial
+ * pivoting so that further right-hand sides cost only triangular solves.
+ * msv_factor factors each matrix of d_A (as written by msv_assemble for the
+ * same m_lo..m_hi).  precision 0: complex128, in place in d_A; precision 1: the
+ * plan keeps complex64 factors and d_A is left intact for the refinement
+ * residual of msv_solve.  The plan keeps the pivots (and remembers d_A, which
+ * must stay valid and unchanged until the last msv_solve).  A zero pivot is
+ * recorded on the device and reported as MSV_ESINGULAR by the next msv_solve
+ * (the first solve after a factorization reads the flags, which waits for the
+ * factorization).  The plan allocates its factor storage on the first call
+ * and whenever the mode count grows; while a batch holds the plan (see below)
+ * it refuses, with MSV_EINVAL, a mode count larger than the batch's. */
 msv_status msv_factor(msv_plan *plan, msv_c128 *d_A, int32_t m_lo, int32_t m_hi, void *stream);
 
-/* Solve A_m x = b for modes m in [m_lo, m_hi] with -M <= m, |m| factored.
+/* Solve A_m x = b for modes m in [m_lo, m_hi] with -M <= m, |m| factored:
+ * the surface currents J, M of each mode (Section 2.1, eq. mullerrep; the
+ * further right-hand sides of Section 6 reuse the factors).
  * Negative modes use A_{-m} = D A_m D, D = diag(1, -1, -1, 1) per node.
  * d_rhs, d_x: device, [m_hi-m_lo+1][n_rhs][4N] complex128 in physical
  * (unweighted) form; rows as above: i w mu0 (n x H_inc)_{t,theta} then
  * i w eps0 (n x E_inc)_{t,theta}, Fourier modes (1/2pi) int f e^{-i m theta}.
- * d_x may not alias d_rhs.  Synchronizes `stream` when precision is 1 (the
- * refinement loop checks convergence on the host). */
+ * d_x may not alias d_rhs.  precision 0: triangular solves with the complex128
+ * factors, stream-ordered.  precision 1: x <- x + LU32^{-1}(b - A x) with the
+ * residual in complex128 from the caller's matrices, until
+ * max_v ||b - A x||_inf / ||b||_inf <= ir_tol; the steps the plan's previous
+ * converged solve needed are queued without waiting, after which each step's
+ * residual is read on the host, so the call returns once the stream reaches
+ * the converged step.  MSV_ENOCONV if ir_max_iter steps do not converge (x
+ * then holds the last iterate).  The solve workspace is allocated on the
+ * first call and whenever the vector count grows. */
 msv_status msv_solve(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_rhs,
                      const msv_c128 *d_rhs, msv_c128 *d_x, void *stream);
 
@@ -165,6 +202,12 @@ int32_t msv_last_ir_iterations(const msv_plan *plan);
  * ordered on `stream` (the graph runs on the batch's own stream, joined by
  * events).  Afterwards msv_solve works on each plan.  Factorizations of the
  * same plan outside the batch overwrite its factors.
+ *
+ * The captured launches hold the plans' factor storage by address, so a batch
+ * pins its plans: msv_factor on a pinned plan may not grow that storage
+ * (MSV_EINVAL), and msv_plan_destroy of a pinned plan only marks it; the last
+ * msv_batch_destroy that holds it frees it.  msv_batch_destroy waits for the
+ * batch's stream.
  * ------------------------------------------------------------------------- */
 typedef struct msv_batch msv_batch;
 msv_status msv_batch_create(msv_batch **out, msv_plan *const *plans, msv_c128 *const *d_A, int32_t n_plans,

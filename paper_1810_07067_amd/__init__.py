@@ -22,7 +22,7 @@ EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nod
            "msv_num_support", "msv_table_entries", "msv_matrix_order", "msv_tabulate",
            "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations",
            "msv_batch_create", "msv_batch_factor", "msv_batch_destroy", "msv_batch_last_error",
-           "msv_batch_panel", "msv_batch_tuned_ms"]
+           "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes"]
 
 
 class MsvError(RuntimeError):
@@ -97,6 +97,10 @@ def load_library(path: str = LIB_PATH):
     lib.msv_batch_panel.restype = ctypes.c_int32
     lib.msv_batch_tuned_ms.argtypes = [P, ctypes.c_int32]
     lib.msv_batch_tuned_ms.restype = ctypes.c_float
+    lib.msv_workspace_bytes.argtypes = [ctypes.c_int32] * 5
+    lib.msv_workspace_bytes.restype = ctypes.c_size_t
+    lib.msv_plan_device_bytes.argtypes = [P]
+    lib.msv_plan_device_bytes.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -162,6 +166,10 @@ class Plan:
     @property
     def table_shape(self):
         return (self.M + 2, 9, self.N, self.N + self.S)
+
+    @property
+    def device_bytes(self) -> int:
+        return int(self.lib.msv_plan_device_bytes(self._h))
 
     def last_ir_iterations(self) -> int:
         return int(self.lib.msv_last_ir_iterations(self._h))
@@ -247,6 +255,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def workspace_bytes(n_nodes, n_support, n_modes, n_solve_vectors, precision, lib=None):
+    """Upper bound on a plan's own device memory (msv_workspace_bytes)."""
+    lib = lib or load_library()
+    return int(lib.msv_workspace_bytes(int(n_nodes), int(n_support), int(n_modes), int(n_solve_vectors),
+                                       int(precision)))
 
 
 def plan_from_curve(curve, rules, k0, eps1, mu1=1.0, m_max=16, fft_len=64, precision=0, **kw):

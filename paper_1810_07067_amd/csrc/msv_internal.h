@@ -156,6 +156,12 @@ struct VecBatch {
   int nv;
   int off[kVB];
 };
+// The batches of a solve over modes m_lo .. m_lo+nm-1 with n_rhs vectors each,
+// against factors of modes fac_lo .. fac_lo+nfac-1 (|m| selects the factor):
+// their number, and the table itself, written on the device in stream order.
+int count_vec_batches(int m_lo, int nm, int n_rhs, int fac_lo, int nfac);
+hipError_t build_vec_batches(VecBatch* vb, int nvb, int m_lo, int nm, int n_rhs, int fac_lo, int nfac,
+                             hipStream_t s);
 // perm[f][i] = source row of row i under the interchanges ipiv[f]
 hipError_t lu_perm(const int32_t* ipiv, int32_t* perm, int n, int nfac, hipStream_t s);
 // out = P in for every vector of the batches (complex128 or rounded to complex64)

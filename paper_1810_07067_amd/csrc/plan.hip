@@ -25,6 +25,7 @@ struct msv_plan {
   double ir_tol = 1e-13;
   int ir_max_iter = 10;
   int last_ir_iters = 0;
+  int ir_pred = 0;  // refinement steps of the last converged solve
   std::vector<double> h_r, h_w;
   // device
   double *d_r = nullptr, *d_z = nullptr, *d_tr = nullptr, *d_tz = nullptr, *d_w = nullptr, *d_sqw = nullptr;
@@ -57,6 +58,12 @@ struct msv_plan {
   msv::VecBatch* d_vb = nullptr;
   size_t work_elems = 0;
   size_t vb_cap = 0;
+  // batches that hold raw pointers to this plan's factor storage: while any
+  // does, that storage is never reallocated, and a destroy is deferred until
+  // the last such batch is destroyed
+  size_t geom_bytes = 0;  // device bytes of the geometry uploaded at creation
+  int batch_refs = 0;
+  bool destroy_pending = false;
   std::string err;
 };
 
@@ -119,6 +126,7 @@ template <typename T>
 msv_status upload(msv_plan* p, T** dst, const T* src, size_t count) {
   if (count == 0) return MSV_OK;
   if (hipMalloc(dst, sizeof(T) * count) != hipSuccess) return fail(p, MSV_ENOMEM, "hipMalloc failed");
+  p->geom_bytes += sizeof(T) * count;
   if (hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice) != hipSuccess)
     return fail(p, MSV_EHIP, "hipMemcpy failed");
   return MSV_OK;
@@ -160,14 +168,66 @@ size_t msv_table_entries(const msv_plan* p) {
   return p ? (size_t)(p->M + 2) * msv::kTypes * p->N * p->NS : 0;
 }
 
-void msv_plan_destroy(msv_plan* p) {
-  if (!p) return;
+static void plan_free(msv_plan* p) {
   void* bufs[] = {p->d_r, p->d_z, p->d_tr, p->d_tz, p->d_w, p->d_sqw, p->d_sup, p->d_lag_self,
                   p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
                   p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm, p->d_vb};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
+}
+
+// Device bytes of the factor storage for nb modes of order n, and of the
+// solve workspace for `vectors` (mode, right-hand side) vectors in nvb batches.
+static size_t factor_bytes(int n, int nb, int precision) {
+  const size_t nn = (size_t)n * n;
+  return (size_t)nb * n * 2 * sizeof(int32_t) + (size_t)nb * sizeof(int32_t) +
+         msv::lu_work_bytes(n, nb, precision == 0) + (precision == 1 ? (size_t)nb * nn * sizeof(float2) : 0) +
+         (size_t)nb * ((n + 63) / 64) * 2 * 64 * 64 * (precision == 0 ? 16 : 8);
+}
+static size_t solve_bytes(int n, size_t vectors, size_t nvb, int precision) {
+  const size_t elems = vectors * n;
+  return elems * (3 * sizeof(double2) + (precision == 1 ? 2 * sizeof(float2) : 0)) + vectors * sizeof(double) +
+         nvb * sizeof(msv::VecBatch);
+}
+
+size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t n_modes, int32_t n_solve_vectors,
+                           int32_t precision) {
+  if (n_nodes < 1 || n_support < 0 || n_modes < 1 || n_solve_vectors < 0 || (precision != 0 && precision != 1))
+    return 0;
+  const size_t N = n_nodes, S = n_support, NS = N + S, n = 4 * N;
+  // geometry: 6 node arrays, support records, Lagrange rows (bounded by the
+  // slot count), neighbour lists, pair classes, near-pair list (at most every
+  // pair)
+  size_t b = 6 * N * sizeof(double) + N * S * msv::kSupFields * sizeof(double) +
+             (size_t)kOrder * kOrder * S * sizeof(double) + kOrder * S * sizeof(double) +
+             2 * (N / kOrder) * sizeof(int) + N * NS + N * NS * sizeof(int2);
+  b += factor_bytes((int)n, n_modes, precision);
+  if (n_solve_vectors > 0)
+    b += solve_bytes((int)n, n_solve_vectors, (size_t)n_modes + (n_solve_vectors + msv::kVB - 1) / msv::kVB,
+                     precision);
+  return b;
+}
+
+size_t msv_plan_device_bytes(const msv_plan* p) {
+  if (!p) return 0;
+  const size_t n = 4 * (size_t)p->N;
+  size_t b = p->geom_bytes;
+  const size_t nbf = p->ipiv_elems / n;  // modes of the pivot storage
+  b += p->ipiv_elems * 2 * sizeof(int32_t) + nbf * sizeof(int32_t) + p->luw_bytes + p->fac32_elems * sizeof(float2) +
+       p->inv_bytes;
+  if (p->work_elems) b += solve_bytes((int)n, p->work_elems / n, 0, p->precision);
+  b += p->vb_cap * sizeof(msv::VecBatch);
+  return b;
+}
+
+void msv_plan_destroy(msv_plan* p) {
+  if (!p) return;
+  if (p->batch_refs > 0) {
+    p->destroy_pending = true;  // freed by the last msv_batch_destroy that holds it
+    return;
+  }
+  plan_free(p);
 }
 
 msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* ru, const msv_desc* d,
@@ -514,6 +574,14 @@ static hipError_t factor_groups(msv_plan* p, msv_c128* A64, float2* A32, int n, 
 // flags, LU workspace, complex64 factors (precision 1), block inverses.
 static msv_status factor_buffers(msv_plan* p, int n, int nb) {
   const size_t nn = (size_t)n * n;
+  if (p->batch_refs > 0) {
+    // a batch's captured launches and matrix list point into this storage
+    const size_t inv_need = (size_t)nb * ((n + 63) / 64) * 2 * 64 * 64 * (p->precision == 0 ? 16 : 8);
+    if ((size_t)nb * n > p->ipiv_elems || msv::lu_work_bytes(n, nb, p->precision == 0) > p->luw_bytes ||
+        (p->precision == 1 && (size_t)nb * nn > p->fac32_elems) || inv_need > p->inv_bytes)
+      return fail(p, MSV_EINVAL, "the plan is held by a batch: factor at most the batch's mode count");
+    return MSV_OK;
+  }
   if ((size_t)nb * n > p->ipiv_elems) {
     if (p->d_ipiv) (void)hipFree(p->d_ipiv);
     if (p->d_info) (void)hipFree(p->d_info);
@@ -606,6 +674,7 @@ struct msv_batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool pinned = false;  // holds a reference on every plan
   int panel = 128;
   float tuned_ms[4] = {-1.f, -1.f, -1.f, -1.f};  // panel 64, 128, 256, 512
   std::string err;
@@ -650,6 +719,11 @@ static hipError_t batch_capture(msv_batch* b, int panel, hipGraph_t* g, hipGraph
 
 void msv_batch_destroy(msv_batch* b) {
   if (!b) return;
+  if (b->pinned) {
+    (void)hipStreamSynchronize(b->st);  // a replay may still read the plans' storage
+    for (msv_plan* p : b->plans)
+      if (--p->batch_refs == 0 && p->destroy_pending) plan_free(p);
+  }
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_list) (void)hipFree(b->d_list);
@@ -758,7 +832,9 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
     plans[i]->fac_hi = m_hi;
     plans[i]->fac_A = d_A[i];
     plans[i]->info_checked = false;
+    plans[i]->batch_refs++;
   }
+  b->pinned = true;
   *out = b;
   return MSV_OK;
 }
@@ -828,24 +904,10 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
       return fail(p, MSV_ENOMEM, "solve workspace allocation failed");
     p->work_elems = elems;
   }
-  // vector batches: every (mode, rhs) vector grouped by the factor it uses
-  std::vector<msv::VecBatch> vb;
-  for (int f = 0; f < nfac; ++f) {
-    msv::VecBatch cur{};
-    cur.fac = f;
-    for (int i = 0; i < nm; ++i) {
-      if (std::abs(m_lo + i) - p->fac_lo != f) continue;
-      for (int q = 0; q < n_rhs; ++q) {
-        cur.off[cur.nv++] = i * n_rhs + q;
-        if (cur.nv == msv::kVB) {
-          vb.push_back(cur);
-          cur.nv = 0;
-        }
-      }
-    }
-    if (cur.nv) vb.push_back(cur);
-  }
-  const int nvb = (int)vb.size();
+  // vector batches: every (mode, rhs) vector grouped by the factor it uses;
+  // the table is written on the device, in stream order behind any earlier
+  // solve on this plan that still reads it
+  const int nvb = msv::count_vec_batches(m_lo, nm, n_rhs, p->fac_lo, nfac);
   if ((size_t)nvb > p->vb_cap) {
     if (p->d_vb) (void)hipFree(p->d_vb);
     p->d_vb = nullptr;
@@ -854,7 +916,7 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
       return fail(p, MSV_ENOMEM, "batch table allocation failed");
     p->vb_cap = nvb;
   }
-  MSV_HIP(p, hipMemcpy(p->d_vb, vb.data(), sizeof(msv::VecBatch) * nvb, hipMemcpyHostToDevice));
+  MSV_HIP(p, msv::build_vec_batches(p->d_vb, nvb, m_lo, nm, n_rhs, p->fac_lo, nfac, s));
   const long long nn = (long long)n * n;
   const double2* rhs = reinterpret_cast<const double2*>(d_rhs);
   double2* x = reinterpret_cast<double2*>(d_x);
@@ -871,12 +933,17 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
     std::vector<double> rat((size_t)nm * n_rhs);
     bool conv = false;
     int it = 0;
+    // The steps that the plan's previous converged solve needed are queued
+    // without waiting; the residual is checked on the host only from the
+    // last of them on, so a repeated solve waits on the device once.
+    const int unchecked = std::min(p->ir_max_iter, std::max(p->ir_pred, 1)) - 1;
     for (it = 1; it <= p->ir_max_iter; ++it) {
       MSV_HIP(p, msv::gather_c(p->d_rw, p->d_r32, p->d_perm, p->d_vb, nvb, n, s));
       MSV_HIP(p, msv::trsv_c(p->d_fac32, static_cast<const float2*>(p->d_inv), nn, n, p->d_vb, nvb, p->d_r32,
                              p->d_y32, s));
       MSV_HIP(p, msv::accum_c64(p->d_xw, p->d_r32, elems, s));
       MSV_HIP(p, msv::residual_batches(Aref, nn, n, p->d_vb, nvb, p->d_bw, p->d_xw, p->d_rw, s));
+      if (it <= unchecked) continue;
       MSV_HIP(p, msv::ratios(p->d_rw, p->d_bw, p->d_nrm, n, nm * n_rhs, s));
       MSV_HIP(p, hipMemcpyAsync(rat.data(), p->d_nrm, sizeof(double) * rat.size(), hipMemcpyDeviceToHost, s));
       MSV_HIP(p, hipStreamSynchronize(s));
@@ -888,6 +955,7 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
       }
     }
     p->last_ir_iters = conv ? it : p->ir_max_iter;
+    p->ir_pred = conv ? it : 0;
     MSV_HIP(p, msv::solve_finish(p->d_xw, x, p->d_sqw, n, n_rhs, nm, m_lo, s));
     if (!conv) return fail(p, MSV_ENOCONV, "iterative refinement did not reach ir_tol");
     return MSV_OK;

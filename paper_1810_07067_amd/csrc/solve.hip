@@ -96,9 +96,61 @@ __global__ __launch_bounds__(256) void ratio_inf(const double2* r, const double2
   if (threadIdx.x == 0) out[v] = sb[0] > 0 ? sr[0] / sb[0] : 0.0;
 }
 
+// The vectors of a solve over modes m_lo .. m_lo+nm-1 (n_rhs each), grouped
+// by the factor f = |m| - fac_lo they use: for each f the vectors of mode -a,
+// then of +a (a = fac_lo + f), right-hand sides in order, kVB to a batch.
+// Record b is built by thread b; entries past a batch's count are 0, a valid
+// offset.
+__device__ __forceinline__ int modes_of(int a, int m_lo, int nm, int* idx) {
+  int k = 0;
+  const int i0 = -a - m_lo, i1 = a - m_lo;
+  if (i0 >= 0 && i0 < nm) idx[k++] = i0;
+  if (a != 0 && i1 >= 0 && i1 < nm) idx[k++] = i1;
+  return k;
+}
+
+__global__ void vec_batches(VecBatch* vb, int nvb, int m_lo, int nm, int n_rhs, int fac_lo, int nfac) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nvb) return;
+  int first = 0;
+  for (int f = 0; f < nfac; ++f) {
+    int idx[2];
+    const int cnt = modes_of(fac_lo + f, m_lo, nm, idx) * n_rhs;
+    const int nbf = (cnt + kVB - 1) / kVB;
+    if (b < first + nbf) {
+      const int j = b - first;
+      VecBatch r;
+      r.fac = f;
+      r.nv = min(kVB, cnt - j * kVB);
+      for (int v = 0; v < kVB; ++v) {
+        const int g = j * kVB + v;
+        r.off[v] = v < r.nv ? idx[g / n_rhs] * n_rhs + g % n_rhs : 0;
+      }
+      vb[b] = r;
+      return;
+    }
+    first += nbf;
+  }
+}
+
 inline dim3 grid1(size_t count) { return dim3((unsigned)((count + 255) / 256)); }
 
 }  // namespace
+
+int count_vec_batches(int m_lo, int nm, int n_rhs, int fac_lo, int nfac) {
+  int nvb = 0;
+  for (int f = 0; f < nfac; ++f) {
+    const int a = fac_lo + f, i0 = -a - m_lo, i1 = a - m_lo;
+    const int k = (i0 >= 0 && i0 < nm) + (a != 0 && i1 >= 0 && i1 < nm);
+    nvb += (k * n_rhs + kVB - 1) / kVB;
+  }
+  return nvb;
+}
+hipError_t build_vec_batches(VecBatch* vb, int nvb, int m_lo, int nm, int n_rhs, int fac_lo, int nfac,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(vec_batches, dim3((nvb + 63) / 64), dim3(64), 0, s, vb, nvb, m_lo, nm, n_rhs, fac_lo, nfac);
+  return hipGetLastError();
+}
 
 hipError_t solve_prep(const double2* rhs, double2* xw, const double* sqw, int n, int nrhs, int nm, int m_lo,
                       hipStream_t s) {

@@ -54,17 +54,28 @@ class Result:
     mode_solves: int          # (2M+1) x n_waves
 
 
-def entry_bytes(curve, m_max, fft_len, precision, n_support=228):
-    """HBM held by a cache entry (matrices + factors + block inverses), and the
-    transient peak while it is built (plus the modal-kernel table)."""
+MAX_WAVES = 32  # plane waves per request
+
+
+def entry_bytes(curve, m_max, precision, n_support):
+    """HBM held by a cache entry, and the transient extra while it is built.
+
+    Held: the caller-owned complex128 matrices of modes 0..M plus everything
+    the plan owns once factored and after its largest solve (2M+1 modes x
+    MAX_WAVES vectors), as bounded by the library (msv_workspace_bytes:
+    geometry, pivots, LU workspace, complex64 factors, block inverses, solve
+    workspace), plus the request's right-hand sides and solutions.
+    Transient: the modal-kernel table, freed once the matrices are assembled."""
+    import paper_1810_07067_amd as msv
     N = curve.n
     n = 4 * N
     nm = m_max + 1
+    vectors = (2 * m_max + 1) * MAX_WAVES
     mats = nm * n * n * 16
-    fac = nm * n * n * 8 if precision == 1 else 0
-    inv = nm * n * 64 * 2 * (8 if precision == 1 else 16)
+    plan = msv.workspace_bytes(N, n_support, nm, vectors, precision)
+    io = 2 * vectors * n * 16
     table = (m_max + 2) * 9 * N * (N + n_support) * 16
-    return mats + fac + inv, table
+    return mats + plan + io, table
 
 
 @dataclass
@@ -108,7 +119,8 @@ class Server:
         """Bytes a request needs admitted: 0 for a cached (or in-build) body."""
         if self.key(req) in self.cache:
             return 0, 0
-        keep, table = entry_bytes(req.curve, req.m_max, req.fft_len, self.precision)
+        (ys, _), (ya, _) = self.rules
+        keep, table = entry_bytes(req.curve, req.m_max, self.precision, ys.shape[1] + 2 * ya.size)
         return keep, table
 
     def _try_admit(self, req):
@@ -124,6 +136,8 @@ class Server:
             victim = min(idle, key=lambda e: e.last_used)
             del self.cache[victim.key]
             self.used -= victim.bytes
+            if victim.plan is not None:
+                victim.plan.close()
             victim.plan = None
             victim.A = None
             self.evictions += 1
@@ -149,12 +163,20 @@ class Server:
             plan = msv.plan_from_curve(req.curve, self.rules, req.k0, req.eps1, req.mu1, m_max=req.m_max,
                                        fft_len=req.fft_len, precision=self.precision, ir_tol=self.ir_tol,
                                        ir_max_iter=self.ir_max_iter)
+            torch.cuda.empty_cache()  # matrices of evicted entries go back to the device
             with torch.cuda.stream(stream):
                 kern = plan.tabulate(stream=stream)
                 A = plan.assemble(kern, 0, req.m_max, stream=stream)
+                stream.synchronize()
+                # hand the table back to the device before the factor storage
+                # is allocated (at the largest bodies the two do not fit together)
+                del kern
+                torch.cuda.empty_cache()
+                with self._mu:
+                    self.used -= table_bytes
+                    table_bytes = 0
                 plan.factor(A, 0, req.m_max, stream=stream)
                 stream.synchronize()
-                del kern
             e.plan, e.A = plan, A
         except BaseException as exc:  # reported to every user of the entry
             e.error = exc

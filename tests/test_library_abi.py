@@ -75,3 +75,21 @@ def test_bad_normals_and_panel_ratio_rejected(lib):
     with pytest.raises(msv.MsvError) as ei:
         msv.Plan(**_args(c2, dsdu=d), lib=lib)
     assert "adjacent panels" in str(ei.value)
+
+
+def test_workspace_bytes_without_a_device(lib):
+    """msv_workspace_bytes is a host computation: zero for invalid arguments,
+    and for the benchmark spheroid (N = 1024, S = 228, 65 modes, precision 1)
+    at least the complex64 factors, pivots and block inverses it must hold."""
+    assert lib.msv_workspace_bytes(0, 228, 65, 0, 1) == 0
+    assert lib.msv_workspace_bytes(1024, 228, 0, 0, 1) == 0
+    assert lib.msv_workspace_bytes(1024, 228, 65, 0, 2) == 0
+    n, nb = 4096, 65
+    b1 = msv.workspace_bytes(1024, 228, nb, 0, 1, lib=lib)
+    b0 = msv.workspace_bytes(1024, 228, nb, 0, 0, lib=lib)
+    floor1 = nb * n * n * 8 + nb * n * 8 + nb * (n // 64) * 2 * 64 * 64 * 8
+    assert floor1 < b1 < floor1 + 2.5e9         # + LU planes (33.5 MB per mode) and geometry
+    assert b0 < b1                              # precision 0 factors in the caller's matrices
+    vec = 129 * 8
+    bs = msv.workspace_bytes(1024, 228, nb, vec, 1, lib=lib)
+    assert bs - b1 >= vec * n * (3 * 16 + 2 * 8)  # solve workspace
