@@ -132,6 +132,16 @@ size_t msv_plan_device_bytes(const msv_plan *plan);
  * msv_table_entries(plan). */
 msv_status msv_tabulate(msv_plan *plan, msv_c128 *d_kern, size_t kern_elems, void *stream);
 
+/* The same table for the target rows t0 .. t0+nt-1 only (0 <= t0, 1 <= nt,
+ * t0 + nt <= N): d_kern is [M+2][9][nt][N+S] complex128 and kern_elems must be
+ * (M+2) * 9 * nt * (N+S).  Every pair is tabulated exactly as by
+ * msv_tabulate, so row blocks of any size reproduce its table bit for bit.
+ * A row block is all the assembly of those targets' equations reads (see
+ * msv_assemble_rows), so a caller can stream a body whose whole table does not
+ * fit beside its matrices (Section 5: the table is 9 (M+2) N (N+S) entries). */
+msv_status msv_tabulate_rows(msv_plan *plan, int32_t t0, int32_t nt, msv_c128 *d_kern, size_t kern_elems,
+                             void *stream);
+
 /* Per-mode Mueller-Nystrom matrices (eq. mullerrep with Lemma 1 and the N, K
  * expansions of Section 3; quadrature of Section 5) for 0 <= m_lo <= m <= m_hi
  * <= M, from a table written by msv_tabulate on this plan.
@@ -142,6 +152,13 @@ msv_status msv_tabulate(msv_plan *plan, msv_c128 *d_kern, size_t kern_elems, voi
  * The stored matrix is the L^2-weighted one, sqrt(w_i/w_j) A_ij (Section 6). */
 msv_status msv_assemble(msv_plan *plan, const msv_c128 *d_kern, int32_t m_lo, int32_t m_hi,
                         msv_c128 *d_A, void *stream);
+
+/* The equations (rows 4 t0 .. 4(t0+nt)-1 of every matrix) of targets
+ * t0 .. t0+nt-1 only, from the row block d_kern written by msv_tabulate_rows
+ * with the same t0, nt.  d_A is the full [m_hi-m_lo+1][4N][4N] array; the
+ * other rows are not touched.  Bitwise the same rows as msv_assemble. */
+msv_status msv_assemble_rows(msv_plan *plan, const msv_c128 *d_kern, int32_t t0, int32_t nt, int32_t m_lo,
+                             int32_t m_hi, msv_c128 *d_A, void *stream);
 
 /* The per-mode direct solve of Section 6: the discretized Mueller system of
  * each azimuthal mode (eq. mullerrep after the separation of variables of

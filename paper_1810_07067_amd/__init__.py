@@ -22,7 +22,8 @@ EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nod
            "msv_num_support", "msv_table_entries", "msv_matrix_order", "msv_tabulate",
            "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations",
            "msv_batch_create", "msv_batch_factor", "msv_batch_destroy", "msv_batch_last_error",
-           "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes"]
+           "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes",
+           "msv_tabulate_rows", "msv_assemble_rows"]
 
 
 class MsvError(RuntimeError):
@@ -97,6 +98,10 @@ def load_library(path: str = LIB_PATH):
     lib.msv_batch_panel.restype = ctypes.c_int32
     lib.msv_batch_tuned_ms.argtypes = [P, ctypes.c_int32]
     lib.msv_batch_tuned_ms.restype = ctypes.c_float
+    lib.msv_tabulate_rows.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_size_t, P]
+    lib.msv_tabulate_rows.restype = ctypes.c_int
+    lib.msv_assemble_rows.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
+    lib.msv_assemble_rows.restype = ctypes.c_int
     lib.msv_workspace_bytes.argtypes = [ctypes.c_int32] * 5
     lib.msv_workspace_bytes.restype = ctypes.c_size_t
     lib.msv_plan_device_bytes.argtypes = [P]
@@ -181,6 +186,45 @@ class Plan:
         assert out.dtype == torch.complex128 and out.is_cuda and out.is_contiguous()
         self._check(self.lib.msv_tabulate(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(),
                                           _stream_handle(stream)))
+        return out
+
+    def table_rows_shape(self, nt):
+        return (self.M + 2, 9, int(nt), self.N + self.S)
+
+    def tabulate_rows(self, t0, nt, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.table_rows_shape(nt), dtype=torch.complex128, device="cuda")
+        assert out.dtype == torch.complex128 and out.is_cuda and out.is_contiguous()
+        self._check(self.lib.msv_tabulate_rows(self._h, int(t0), int(nt), ctypes.c_void_p(out.data_ptr()),
+                                               out.numel(), _stream_handle(stream)))
+        return out
+
+    def assemble_rows(self, kern, t0, nt, m_lo, m_hi, out, stream=None):
+        import torch
+        nm = m_hi - m_lo + 1
+        assert out.dtype == torch.complex128 and out.is_contiguous() and out.shape == (nm, self.n, self.n)
+        assert kern.is_contiguous() and tuple(kern.shape) == self.table_rows_shape(nt)
+        self._check(self.lib.msv_assemble_rows(self._h, ctypes.c_void_p(kern.data_ptr()), int(t0), int(nt),
+                                               int(m_lo), int(m_hi), ctypes.c_void_p(out.data_ptr()),
+                                               _stream_handle(stream)))
+        return out
+
+    def assemble_streamed(self, m_lo, m_hi, out=None, rows_per_block=None, block=None, stream=None):
+        """Tabulate and assemble in target-row blocks through one reused table
+        block, so the whole table is never resident."""
+        import torch
+        nm = m_hi - m_lo + 1
+        if out is None:
+            out = torch.empty((nm, self.n, self.n), dtype=torch.complex128, device="cuda")
+        nb = int(rows_per_block or self.N)
+        if block is None:
+            block = torch.empty(self.table_rows_shape(nb), dtype=torch.complex128, device="cuda")
+        for t0 in range(0, self.N, nb):
+            nt = min(nb, self.N - t0)
+            kb = block.view(-1)[: (self.M + 2) * 9 * nt * (self.N + self.S)].view(self.table_rows_shape(nt))
+            self.tabulate_rows(t0, nt, out=kb, stream=stream)
+            self.assemble_rows(kb, t0, nt, m_lo, m_hi, out, stream=stream)
         return out
 
     def assemble(self, kern, m_lo, m_hi, out=None, stream=None):

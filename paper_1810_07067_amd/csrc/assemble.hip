@@ -156,7 +156,7 @@ __device__ __forceinline__ void load_T(const AsmParams& P, int m, int t, int col
   for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int ty = 0; ty < kTypes; ++ty)
-      T[j][ty] = ld(P.kern + (((size_t)ms[j] * kTypes + ty) * P.N + t) * P.NS + col);
+      T[j][ty] = ld(P.kern + (((size_t)ms[j] * kTypes + ty) * P.nt + (t - P.t0)) * P.NS + col);
 }
 
 __device__ __forceinline__ bool near_panel(const AsmParams& P, int pt, int ps) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kFarThreads, 3) void assemble_far(AsmParams P, int 
   const int njb = (P.N + kFarThreads - 1) / kFarThreads;
   const int mi = item % nm;
   const int jb = (item / nm) % njb;
-  const int t = item / nm / njb;
+  const int t = P.t0 + item / nm / njb;
   const int j0 = jb * kFarThreads, j = j0 + threadIdx.x;
   const int m = P.m_lo + mi;
   const int pt = t / kOrder;
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P, int n
   if (item >= n_items) return;
   const int nm = P.m_hi - P.m_lo + 1;
   const int mi = item % nm;
-  const int t = item / nm;
+  const int t = P.t0 + item / nm;
   const int m = P.m_lo + mi;
   const int S = P.S;
   double2* Bw = reinterpret_cast<double2*>(smem);  // [S][16]
@@ -298,8 +298,10 @@ __global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P, int n
 
 hipError_t launch_assemble(const AsmParams& P, hipStream_t s) {
   const int nm = P.m_hi - P.m_lo + 1;
-  const long long items = (long long)nm * ((P.N + kFarThreads - 1) / kFarThreads) * P.N;
-  if (items > (1LL << 30)) return hipErrorInvalidValue;
+  if (P.nt <= 0) return hipSuccess;
+  const long long items = (long long)nm * ((P.N + kFarThreads - 1) / kFarThreads) * P.nt;
+  // a dispatch counts work-items in 32 bits
+  if (items * kFarThreads >= (1LL << 32)) return hipErrorInvalidValue;
   const int n_items = (int)items;
   hipLaunchKernelGGL(assemble_far, dim3(8 * ((n_items + 7) / 8)), dim3(kFarThreads), 0, s, P, n_items);
   hipError_t e = hipGetLastError();
@@ -309,7 +311,7 @@ hipError_t launch_assemble(const AsmParams& P, hipStream_t s) {
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&assemble_near), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds);
   if (e != hipSuccess) return e;
-  const int n_near = nm * P.N;
+  const int n_near = nm * P.nt;
   hipLaunchKernelGGL(assemble_near, dim3(8 * ((n_near + 7) / 8)), dim3(kNearThreads), lds, s, P, n_near);
   return hipGetLastError();
 }

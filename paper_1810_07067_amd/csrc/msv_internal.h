@@ -36,7 +36,9 @@ struct TabParams {
   const uint8_t* cls;   // [N][NS]
   const int2* near;     // near pairs (t, source column), sorted by t
   int n_near;
-  double2* out;         // [M2][9][N][NS]
+  // row block: targets t0 .. t0+nt-1, their near pairs near[near_lo .. near_hi)
+  int t0, nt, near_lo, near_hi;
+  double2* out;         // [M2][9][nt][NS]
 };
 
 // Support-slot record (doubles): offset from the target, the source geometry
@@ -45,6 +47,7 @@ enum { kSupDr = 0, kSupDz, kSupR, kSupTr, kSupTz, kSupW, kSupFields };
 
 struct AsmParams {
   int N, S, NS, M2, npan, n_self, n_adj, m_lo, m_hi;
+  int t0, nt;           // equations of targets t0 .. t0+nt-1; kern holds their rows
   double k0, k1r, k1i, omega;
   double eps0r, eps0i, mu0r, mu0i, eps1r, eps1i, mu1r, mu1i;
   const double* r;      // [N]
@@ -57,7 +60,7 @@ struct AsmParams {
   const int* right;     // [npan]
   const double* lag_self;  // [16][n_self][16]
   const double* lag_adj;   // [n_adj][16]
-  const double2* kern;  // table
+  const double2* kern;  // table rows of the block: [M2][9][nt][NS]
   double2* A;           // [m_hi-m_lo+1][4N][4N]
 };
 

@@ -34,6 +34,7 @@ struct msv_plan {
   uint8_t* d_cls = nullptr;
   int2* d_near = nullptr;
   int n_near = 0;
+  std::vector<int> near_start;  // [N+1]: near pairs of target t are near[near_start[t] ..]
   // factors
   int fac_lo = -1, fac_hi = -1;
   msv_c128* fac_A = nullptr;   // caller's matrices (FP64 factors or FP64 originals)
@@ -466,6 +467,9 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
     }
   }
   p->n_near = (int)nearv.size();
+  p->near_start.assign(N + 1, 0);
+  for (const int2& pr : nearv) p->near_start[pr.x + 1]++;
+  for (int t = 0; t < N; ++t) p->near_start[t + 1] += p->near_start[t];
   p->h_r.assign(c->h_r, c->h_r + N);
   p->h_w = w;
 
@@ -492,10 +496,13 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   return MSV_OK;
 }
 
-msv_status msv_tabulate(msv_plan* p, msv_c128* d_kern, size_t kern_elems, void* stream) {
+msv_status msv_tabulate_rows(msv_plan* p, int32_t t0, int32_t nt, msv_c128* d_kern, size_t kern_elems,
+                             void* stream) {
   if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
   if (!d_kern) return fail(p, MSV_EINVAL, "null table");
-  if (kern_elems != msv_table_entries(p)) return fail(p, MSV_EINVAL, "table size mismatch");
+  if (t0 < 0 || nt < 1 || t0 + nt > p->N) return fail(p, MSV_EINVAL, "need 0 <= t0, 1 <= nt, t0 + nt <= N");
+  if (kern_elems != (size_t)(p->M + 2) * msv::kTypes * nt * p->NS)
+    return fail(p, MSV_EINVAL, "table size mismatch");
   msv::TabParams T{};
   T.N = p->N;
   T.S = p->S;
@@ -515,17 +522,29 @@ msv_status msv_tabulate(msv_plan* p, msv_c128* d_kern, size_t kern_elems, void* 
   T.cls = p->d_cls;
   T.near = p->d_near;
   T.n_near = p->n_near;
+  T.t0 = t0;
+  T.nt = nt;
+  T.near_lo = p->near_start[t0];
+  T.near_hi = p->near_start[t0 + nt];
   T.out = reinterpret_cast<double2*>(d_kern);
   MSV_HIP(p, msv::launch_tabulate(T, (hipStream_t)stream));
   return MSV_OK;
 }
 
-msv_status msv_assemble(msv_plan* p, const msv_c128* d_kern, int32_t m_lo, int32_t m_hi, msv_c128* d_A,
-                        void* stream) {
+msv_status msv_tabulate(msv_plan* p, msv_c128* d_kern, size_t kern_elems, void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  return msv_tabulate_rows(p, 0, p->N, d_kern, kern_elems, stream);
+}
+
+msv_status msv_assemble_rows(msv_plan* p, const msv_c128* d_kern, int32_t t0, int32_t nt, int32_t m_lo,
+                             int32_t m_hi, msv_c128* d_A, void* stream) {
   if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
   if (!d_kern || !d_A) return fail(p, MSV_EINVAL, "null buffer");
   if (m_lo < 0 || m_hi < m_lo || m_hi > p->M) return fail(p, MSV_EINVAL, "need 0 <= m_lo <= m_hi <= M");
+  if (t0 < 0 || nt < 1 || t0 + nt > p->N) return fail(p, MSV_EINVAL, "need 0 <= t0, 1 <= nt, t0 + nt <= N");
   msv::AsmParams A{};
+  A.t0 = t0;
+  A.nt = nt;
   A.N = p->N;
   A.S = p->S;
   A.NS = p->NS;
@@ -561,6 +580,12 @@ msv_status msv_assemble(msv_plan* p, const msv_c128* d_kern, int32_t m_lo, int32
   A.A = reinterpret_cast<double2*>(d_A);
   MSV_HIP(p, msv::launch_assemble(A, (hipStream_t)stream));
   return MSV_OK;
+}
+
+msv_status msv_assemble(msv_plan* p, const msv_c128* d_kern, int32_t m_lo, int32_t m_hi, msv_c128* d_A,
+                        void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  return msv_assemble_rows(p, d_kern, 0, p->N, m_lo, m_hi, d_A, stream);
 }
 
 // Factor nb matrices (complex128 at A64 or complex64 at A32) on s.

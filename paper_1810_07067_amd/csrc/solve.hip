@@ -51,17 +51,20 @@ __global__ void finish_x(const double2* xw, double2* x, const double* sqw, int n
   x[(size_t)i * nrhs * n + e] = make_double2(s * v.x, s * v.y);
 }
 
+// Elementwise kernels walk their range in strides of the whole grid: a
+// dispatch counts its work-items in 32 bits, so one work-item per element
+// would wrap for the 8.7e9 elements of 129 matrices of order 8192.
 __global__ void to_c64(const double2* a, float2* b, size_t count) {
-  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < count) {
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += step) {
     double2 v = a[e];
     b[e] = make_float2((float)v.x, (float)v.y);
   }
 }
 
 __global__ void add_c64(double2* x, const float2* d, size_t count) {
-  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < count) {
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += step) {
     double2 v = x[e];
     float2 u = d[e];
     x[e] = make_double2(v.x + (double)u.x, v.y + (double)u.y);
@@ -69,8 +72,9 @@ __global__ void add_c64(double2* x, const float2* d, size_t count) {
 }
 
 __global__ void fill_zero(double2* x, size_t count) {
-  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < count) x[e] = make_double2(0.0, 0.0);
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += step)
+    x[e] = make_double2(0.0, 0.0);
 }
 
 // ratio[i*nrhs+q] = max|r| / max|b| over the vector
@@ -133,7 +137,9 @@ __global__ void vec_batches(VecBatch* vb, int nvb, int m_lo, int nm, int n_rhs, 
   }
 }
 
-inline dim3 grid1(size_t count) { return dim3((unsigned)((count + 255) / 256)); }
+// 256-thread workgroups, at most 2^20 of them (2^28 work-items; the kernels
+// loop over the rest)
+inline dim3 grid1(size_t count) { return dim3((unsigned)std::min<size_t>((count + 255) / 256, (size_t)1 << 20)); }
 
 }  // namespace
 

@@ -354,13 +354,13 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
     int t, src;
     bool ok;
     if (NEAR) {
-      long long idx = (long long)blockIdx.x * TP + tid;
-      ok = idx < P.n_near;
-      int2 pr = ok ? P.near[idx] : make_int2(0, 0);
+      long long idx = (long long)P.near_lo + (long long)blockIdx.x * TP + tid;
+      ok = idx < P.near_hi;
+      int2 pr = ok ? P.near[idx] : make_int2(P.t0, 0);
       t = pr.x;
       src = pr.y;
     } else {
-      t = blockIdx.y;
+      t = P.t0 + blockIdx.y;
       src = blockIdx.x * TP + tid;
       ok = src < P.NS;
     }
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
     if (m >= P.M2) continue;
 #pragma unroll
     for (int ty = 0; ty < kTypes; ++ty) {
-      size_t off = (((size_t)m * kTypes + ty) * P.N + t) * P.NS + src;
+      size_t off = (((size_t)m * kTypes + ty) * P.nt + (t - P.t0)) * P.NS + src;
       P.out[off] = make_double2(acc[2 * ty][i] * scale, acc[2 * ty + 1][i] * scale);
     }
   }
@@ -539,10 +539,11 @@ hipError_t launch_one(const TabParams& P, hipStream_t s) {
   if (lds > 112 * 1024) return hipErrorInvalidValue;
   dim3 grid;
   if (NEAR) {
-    if (P.n_near == 0) return hipSuccess;
-    grid = dim3((P.n_near + TP - 1) / TP, 1, 1);
+    const int cnt = P.near_hi - P.near_lo;
+    if (cnt <= 0) return hipSuccess;
+    grid = dim3((cnt + TP - 1) / TP, 1, 1);
   } else {
-    grid = dim3((P.NS + TP - 1) / TP, P.N, 1);
+    grid = dim3((P.NS + TP - 1) / TP, P.nt, 1);
   }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tabulate_kernel<NEAR, K1C, MB>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -5,18 +5,13 @@
               triangular solves take 8 per workgroup), a factored mode range
               that starts above 0 and single-mode solves.
   degenerate  a single azimuthal mode (m_max = 0).
-  maximum     4N = 8192, the largest order the LU panel kernel accepts.
-  full size   the benchmark workload (prolate spheroid 1:3, 1024 nodes,
-              |m| <= 64, L = 256, k0 = 10) in the launch configuration the
-              benchmark times: sampled table rows against the oracle; the
-              complex64-LU + complex128-refinement solution against the FP64
-              LU solution; power balance of the lossless body.
+  (4N = 8192, the largest order the LU accepts, and the full-size workloads
+  are in test_gpu_fullsize.py.)
   errors      invalid calls return EINVAL and leave the plan usable.
 """
 import numpy as np
 import pytest
 
-import bench
 from gpu_cases import RULES, normwise_table_error, oracle_matrix, oracle_setup, oracle_table
 from oracle import farfield
 from oracle import solve as osolve
@@ -89,70 +84,6 @@ def test_single_mode():
     E = farfield.far_field(curve, w, x[:, 0], 0, k0, k0, 1.0, DIRS)
     Er = farfield.far_field(curve, w, xr[:, 0], 0, k0, k0, 1.0, DIRS)
     assert np.max(np.abs(E - Er)) < 1e-10 * np.max(np.abs(Er))
-
-
-def test_maximum_order():
-    """4N = 8192: sampled table rows against the oracle; mixed-precision
-    refinement reaches the FP64 LU solution."""
-    curve, k0, eps1, M, L = geometry.cylinder(), 1.0, 2.25, 0, 32
-    assert 4 * curve.n == 8192
-    rows = np.array([0, 1000, curve.n - 1])
-    sup, kp = oracle_setup(curve, k0, eps1, M, L)
-    tab = oracle_table(curve, sup, kp, rows=rows)
-    rhs = torch.from_numpy(incident.rhs_modes(curve, [incident.tilted_direction(20.0)], k0, 0, 0)).cuda()
-    xs = []
-    for precision in (0, 1):
-        plan = make_plan(curve, k0, eps1, 1.0, M, L, precision=precision, ir_tol=1e-13, ir_max_iter=20)
-        kern = plan.tabulate()
-        if precision == 0:
-            err, zero_bad = normwise_table_error(kern[:, :, rows, :].cpu().numpy(), tab)
-            assert zero_bad == 0.0 and err < 1e-12, err
-        A = plan.assemble(kern, 0, 0)
-        del kern
-        plan.factor(A, 0, 0)
-        xs.append(plan.solve(0, 0, rhs).cpu().numpy())
-        del A, plan
-        torch.cuda.empty_cache()
-    sw = l2w(curve)
-    d = np.linalg.norm(sw * (xs[1] - xs[0])) / np.linalg.norm(sw * xs[0])
-    print(f"[max] complex64+IR vs FP64 LU: {d:.3e}", flush=True)
-    assert d < 1e-10, d
-
-
-def test_benchmark_workload():
-    curve, rls, waves, cfg = bench.workload()
-    k0, eps1, mu1, M, L = cfg["k0"], cfg["eps1"], cfg["mu1"], cfg["M"], cfg["L"]
-    rows = np.array([0, 7, 300, 512, curve.n - 1])
-    sup, kp = oracle_setup(curve, k0, eps1, M, L, mu1=mu1)
-    tab = oracle_table(curve, sup, kp, rows=rows)
-    rhs = torch.from_numpy(incident.rhs_modes(curve, waves, k0, -M, M)).cuda()
-    sols = {}
-    for precision in (1, 0):
-        plan = make_plan(curve, k0, eps1, mu1, M, L, precision=precision, ir_tol=1e-12, ir_max_iter=20)
-        kern = plan.tabulate()
-        if precision == 1:
-            err, zero_bad = normwise_table_error(kern[:, :, rows, :].cpu().numpy(), tab)
-            print(f"[bench-size] sampled table rows err {err:.3e}", flush=True)
-            assert zero_bad == 0.0 and err < 1e-12, err
-        A = plan.assemble(kern, 0, M)
-        del kern
-        plan.factor(A, 0, M)
-        sols[precision] = plan.solve(-M, M, rhs).cpu().numpy()
-        if precision == 1:
-            assert 1 <= plan.last_ir_iterations() <= 10
-        del A, plan
-        torch.cuda.empty_cache()
-    sw = l2w(curve)
-    d = np.linalg.norm(sw * (sols[1] - sols[0])) / np.linalg.norm(sw * sols[0])
-    w = geometry.gl_weights(curve)
-    E1 = farfield.far_field(curve, w, sols[1][:, 0], -M, k0, k0, 1.0, DIRS)
-    E0 = farfield.far_field(curve, w, sols[0][:, 0], -M, k0, k0, 1.0, DIRS)
-    fe = np.max(np.abs(E1 - E0)) / np.max(np.abs(E0))
-    pb = max(power_balance(curve, sols[1][:, i]) for i in range(len(waves)))
-    print(f"[bench-size] complex64+IR vs FP64 LU: currents {d:.3e}, far field {fe:.3e}; "
-          f"power balance {pb:.3e}", flush=True)
-    assert d < 1e-10 and fe < 1e-10
-    assert pb < 1e-6, pb
 
 
 def test_invalid_calls_raise_einval():

@@ -1,0 +1,223 @@
+"""Full-size checks through the C-ABI, in the launch configurations bench.py
+times.
+
+  spheroid   the 1:3 prolate spheroid (N = 1024, |m| <= 64, L = 256, k0 = 10,
+             eps1 = 4): sampled table rows and, for every mode, the same rows
+             of the assembled matrices against the oracle; the refined
+             complex64 solution against the complex128 LU on the same
+             matrices (currents and far field); power balance of the lossless
+             body.
+  cylinder   the dyadic cylinder (N = 2048, 128 panels, |m| <= 128, L = 512,
+             k0 = 20, eps1 = 4 + 0.1i), tabulated and assembled in 512-row
+             blocks as the benchmark does: table rows and assembled rows of
+             targets next to the axis and on the 7.45e-9 panels at a corner
+             against the oracle; all 129 modes factored (complex64 LU +
+             refinement) against the complex128 LU; absorption > 0.
+  seeded LU  seeded matrices of the full sizes (65 modes of order 4096, 129
+             of order 8192: 8.7e9 complex64 elements, more than a dispatch's
+             32-bit work-item count) through msv_factor/msv_solve against the
+             oracle's dense solve of the same matrices; their dominant entries
+             sit on a random permutation of the diagonal, so every column
+             needs an interchange.
+
+Assembly rows are checked on the oracle's table rows (as in test_gpu_parity),
+each to max(1e-12 rowmax, 16 sens_tab, sens_geo): the oracle's own change of
+the row when every table entry is scaled by an independent 1 + u 2^-53
+(sens_tab), or when the nodal data r, z, n, ds/du are scaled by 1 + 16 u 2^-53
+before the support nodes are interpolated from them (sens_geo, largest of three
+seeds).  Each support-node quantity is a 16-term interpolation sum, so its
+rounding in either implementation is at most 16 ulps of the sum of the
+absolute terms, which the random 16-ulp scaling of the terms reaches.  This
+matters where a support quantity is far smaller than the terms it is
+interpolated from: next to the poles dz/du at a support node is ~1e-4 of the
+nodal values, and on the 1:3 spheroid a one-ulp change of the nodal data
+flips rows of the E-equation by up to 8e-12 of their size (measured; the GPU
+and the oracle differ there by 4e-12 .. 1e-11, within sens_geo = 1.6e-11 ..
+2.9e-11).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import bench
+from gpu_cases import RULES, normwise_table_error, oracle_matrix, oracle_setup, oracle_table
+from oracle import discretize as odisc
+from oracle import farfield
+from oracle import solve as osolve
+from workloads import geometry
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1810_07067_amd as msv  # noqa: E402
+
+DIRS = np.array([[0.3, 0.4, np.sqrt(0.75)], [-0.6, 0.0, 0.8], [0.0, -1.0, 0.0]])
+
+
+@pytest.fixture(autouse=True)
+def _release():
+    torch.cuda.empty_cache()
+    yield
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def make_plan(name, precision):
+    curve, rls, waves, cfg = bench.workload(name)
+    print(f"[case] {name} N={curve.n} M={cfg['M']} L={cfg['L']} prec={precision}", flush=True)
+    plan = msv.plan_from_curve(curve, rls, cfg["k0"], cfg["eps1"], cfg["mu1"], m_max=cfg["M"], fft_len=cfg["L"],
+                               precision=precision, ir_tol=1e-12, ir_max_iter=20)
+    return plan, curve, waves, cfg
+
+
+def l2w(curve):
+    return np.sqrt(np.repeat(geometry.gl_weights(curve), 4))
+
+
+def check_rows(plan, curve, cfg, t0, nt, modes):
+    """GPU table rows t0..t0+nt-1 against the oracle's, then the GPU assembly
+    of those rows (from the oracle's table rows) against the oracle's rows."""
+    rows = np.arange(t0, t0 + nt)
+    sup, kp = oracle_setup(curve, cfg["k0"], cfg["eps1"], cfg["M"], cfg["L"], mu1=cfg["mu1"])
+    tab = oracle_table(curve, sup, kp, rows=rows)
+    got = plan.tabulate_rows(t0, nt).cpu().numpy()
+    err, zero_bad = normwise_table_error(got, tab)
+    print(f"[rows {t0}..{t0 + nt - 1}] table err {err:.3e}", flush=True)
+    assert zero_bad == 0.0 and err < 1e-12, err
+    rng = np.random.default_rng(11)
+    tabp = tab * (1.0 + 2.0 ** -53 * rng.uniform(-1.0, 1.0, tab.shape))
+    sups = []
+    for seed in (1, 2, 3):
+        rg = np.random.default_rng(seed)
+        pert = lambda a: a * (1.0 + 16 * 2.0 ** -53 * rg.uniform(-1.0, 1.0, a.shape))
+        c2 = dataclasses.replace(curve, r=pert(curve.r), z=pert(curve.z), nr=pert(curve.nr), nz=pert(curve.nz),
+                                 dsdu=pert(curve.dsdu))
+        sups.append(odisc.support_points(c2, *RULES))
+    ktab = torch.from_numpy(tab).cuda()
+    worst = 0.0
+    for m in modes:
+        A = torch.empty((1, plan.n, plan.n), dtype=torch.complex128, device="cuda")
+        plan.assemble_rows(ktab, t0, nt, m, m, A)
+        g = A[0, 4 * t0:4 * (t0 + nt)].cpu().numpy()
+        del A
+        ref = oracle_matrix(curve, sup, tab, m, cfg["k0"], kp.k1, cfg["eps1"], cfg["mu1"], rows=rows)
+        refp = oracle_matrix(curve, sup, tabp, m, cfg["k0"], kp.k1, cfg["eps1"], cfg["mu1"], rows=rows)
+        diff = np.max(np.abs(g - ref), axis=1)
+        rowmax = np.max(np.abs(ref), axis=1)
+        sens_tab = np.max(np.abs(refp - ref), axis=1)
+        sens_geo = np.zeros_like(sens_tab)
+        for sp in sups:
+            refg = oracle_matrix(curve, sp, tab, m, cfg["k0"], kp.k1, cfg["eps1"], cfg["mu1"], rows=rows)
+            sens_geo = np.maximum(sens_geo, np.max(np.abs(refg - ref), axis=1))
+        bound = np.maximum(np.maximum(1e-12 * rowmax, 16.0 * sens_tab), sens_geo)
+        worst = max(worst, float(np.max(diff / rowmax)))
+        assert np.all(diff <= bound), (m, diff / rowmax, sens_tab / rowmax, sens_geo / rowmax)
+    print(f"[rows {t0}..{t0 + nt - 1}] assembly worst row err/rowmax {worst:.3e} over modes {modes}", flush=True)
+
+
+def absorbed_power(curve, x):
+    """Net power into the body, relative to pi sum_m int |J||M| r ds."""
+    X = x.reshape(x.shape[0], curve.n, 4)
+    J1, J2, M1, M2 = (X[:, :, i] for i in range(4))
+    rw = curve.r * geometry.gl_weights(curve)
+    P = -np.pi * np.sum(np.real(M2 * np.conj(J1) - M1 * np.conj(J2)) * rw[None, :])
+    scale = np.pi * np.sum((np.abs(J1) + np.abs(J2)) * (np.abs(M1) + np.abs(M2)) * rw[None, :])
+    return P / scale
+
+
+def full_step(plan, cfg, curve, waves, A, block_rows):
+    """Streamed tabulate + assemble of modes 0..M, factor, solve (as bench.py)."""
+    from workloads import incident
+    M = cfg["M"]
+    plan.assemble_streamed(0, M, out=A, rows_per_block=block_rows)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    plan.factor(A, 0, M)
+    rhs = torch.from_numpy(incident.rhs_modes(curve, waves, cfg["k0"], -M, M)).cuda()
+    return plan.solve(-M, M, rhs).cpu().numpy(), rhs
+
+
+def compare_precisions(name, block_rows):
+    p1, curve, waves, cfg = make_plan(name, 1)
+    M = cfg["M"]
+    A = torch.empty((M + 1, p1.n, p1.n), dtype=torch.complex128, device="cuda")
+    x1, rhs = full_step(p1, cfg, curve, waves, A, block_rows)
+    it = p1.last_ir_iterations()
+    p1.close()
+    torch.cuda.empty_cache()
+    p0, _, _, _ = make_plan(name, 0)
+    p0.factor(A, 0, M)  # A was left intact by the precision-1 factorization
+    x0 = p0.solve(-M, M, rhs).cpu().numpy()
+    p0.close()
+    del A, rhs
+    sw = l2w(curve)
+    d = np.linalg.norm(sw * (x1 - x0)) / np.linalg.norm(sw * x0)
+    w = geometry.gl_weights(curve)
+    E1 = farfield.far_field(curve, w, x1[:, 0], -M, cfg["k0"], cfg["k0"], 1.0, DIRS)
+    E0 = farfield.far_field(curve, w, x0[:, 0], -M, cfg["k0"], cfg["k0"], 1.0, DIRS)
+    fe = np.max(np.abs(E1 - E0)) / np.max(np.abs(E0))
+    print(f"[{name}] complex64+IR ({it} steps) vs complex128 LU: currents {d:.3e}, far field {fe:.3e}", flush=True)
+    assert 1 <= it <= 10
+    assert d < 1e-10 and fe < 1e-10, (d, fe)
+    return curve, x1
+
+
+def test_spheroid_rows_against_oracle():
+    plan, curve, _, cfg = make_plan("spheroid", 1)
+    for t0, nt in ((0, 2), (300, 2), (1022, 2)):
+        check_rows(plan, curve, cfg, t0, nt, list(range(0, cfg["M"] + 1, 8)) + [cfg["M"]])
+
+
+def test_spheroid_full_size():
+    curve, x = compare_precisions("spheroid", None)
+    pb = max(abs(absorbed_power(curve, x[:, i])) for i in range(x.shape[1]))
+    print(f"[spheroid] power balance {pb:.3e}", flush=True)
+    assert pb < 1e-6, pb
+
+
+def test_cylinder_corner_and_axis_rows_against_oracle():
+    """Rows next to the axis (r_t = 6.6e-4) and on both sides of a corner,
+    where the 7.45e-9 panels put sources at eta ~ 1e-17 of the target."""
+    plan, curve, _, cfg = make_plan("cylinder", 1)
+    assert curve.panel_len[31] < 1e-8 and curve.panel_len[32] < 1e-8
+    for t0, nt in ((0, 2), (510, 4), (2046, 2)):
+        check_rows(plan, curve, cfg, t0, nt, [0, 1, 64, 128])
+
+
+def test_cylinder_full_size():
+    curve, x = compare_precisions("cylinder", 512)
+    pa = absorbed_power(curve, x[:, 0])
+    print(f"[cylinder] absorbed power (relative) {pa:.3e}", flush=True)
+    assert pa > 1e-4  # eps1 = 4 + 0.1i absorbs
+
+
+@pytest.mark.parametrize("name,modes", [("spheroid", (0, 64)), ("cylinder", (128,))])
+def test_seeded_matrices_through_the_full_size_lu(name, modes):
+    """All modes of the workload's order, seeded: complex Gaussian entries
+    scaled by 1/sqrt(n), plus 1.5 at a random permutation of the diagonal
+    positions (condition number ~5, and partial pivoting must move every
+    dominant row into place).  Refined complex64 solves against the oracle's
+    dense solve."""
+    plan, curve, _, cfg = make_plan(name, 1)
+    M, n = cfg["M"], plan.n
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    A = torch.randn((M + 1, n, n), dtype=torch.complex128, device="cuda", generator=g)
+    A.mul_(1.0 / np.sqrt(n))
+    cols = torch.arange(n, device="cuda")
+    for z in range(M + 1):
+        perm = torch.randperm(n, device="cuda", generator=g)
+        A[z, perm, cols] += 1.5
+    b = torch.randn((M + 1, 2, n), dtype=torch.complex128, device="cuda", generator=g)
+    plan.factor(A, 0, M)
+    x = plan.solve(0, M, b).cpu().numpy()
+    print(f"[seeded {name}] n={n} modes={M + 1}, refinement steps {plan.last_ir_iterations()}", flush=True)
+    w = geometry.gl_weights(curve)
+    for m in modes:
+        Am = A[m].cpu().numpy()
+        ref = osolve.solve_modes({m: Am}, w, b[m:m + 1].cpu().numpy(), m, m)[0]
+        err = np.max(np.abs(x[m] - ref)) / np.max(np.abs(ref))
+        print(f"[seeded {name}] mode {m}: {err:.3e}", flush=True)
+        assert err < 1e-10, (m, err)
+    plan.close()
