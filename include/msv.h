@@ -108,7 +108,8 @@ int32_t msv_matrix_order(const msv_plan *plan);
  * pivots, LU workspace, complex64 factors (precision 1), diagonal-block
  * inverses and the solve workspace.  It counts the near-pair list at its
  * largest (every pair), so it exceeds the real footprint by at most
- * 8 N (N + S) bytes plus one batch record per factored mode.  Returns 0 for
+ * 8 N (N + S) bytes plus one 72-byte batch record per factored mode and 256
+ * bytes of alignment.  Returns 0 for
  * invalid arguments.  msv_plan_device_bytes is what the plan holds now.
  * Neither touches the device. */
 size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t n_modes, int32_t n_solve_vectors,

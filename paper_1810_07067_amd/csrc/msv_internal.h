@@ -192,6 +192,7 @@ hipError_t solve_finish(const double2* xw, double2* x, const double* sqw, int n,
 hipError_t conv_c64(const double2* a, float2* b, size_t count, hipStream_t s);
 hipError_t accum_c64(double2* x, const float2* d, size_t count, hipStream_t s);
 hipError_t zero_c128(double2* x, size_t count, hipStream_t s);
+// out[v] = ||r_v||_inf / ||b_v||_inf for v < nvec, and out[nvec] = their maximum
 hipError_t ratios(const double2* r, const double2* b, double* out, int n, int nvec, hipStream_t s);
 
 }  // namespace msv

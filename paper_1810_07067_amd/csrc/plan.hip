@@ -49,16 +49,9 @@ struct msv_plan {
   size_t luw_bytes = 0;
   size_t ipiv_elems = 0;
   bool info_checked = false;
-  // solve workspace
-  double2* d_bw = nullptr;  // weighted right-hand sides
-  double2* d_xw = nullptr;  // weighted solution
-  double2* d_rw = nullptr;  // residual
-  float2* d_r32 = nullptr;  // complex64 residual / correction
-  float2* d_y32 = nullptr;  // complex64 sweep scratch
-  double* d_nrm = nullptr;
-  msv::VecBatch* d_vb = nullptr;
-  size_t work_elems = 0;
-  size_t vb_cap = 0;
+  // solve workspace (SolveWork, carved from one allocation)
+  void* d_work = nullptr;
+  size_t work_bytes = 0;
   // batches that hold raw pointers to this plan's factor storage: while any
   // does, that storage is never reallocated, and a destroy is deferred until
   // the last such batch is destroyed
@@ -69,6 +62,7 @@ struct msv_plan {
 };
 
 static thread_local std::string g_create_err;
+
 
 namespace {
 
@@ -172,24 +166,26 @@ size_t msv_table_entries(const msv_plan* p) {
 static void plan_free(msv_plan* p) {
   void* bufs[] = {p->d_r, p->d_z, p->d_tr, p->d_tz, p->d_w, p->d_sqw, p->d_sup, p->d_lag_self,
                   p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
-                  p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm, p->d_vb};
+                  p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_work};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
 }
 
-// Device bytes of the factor storage for nb modes of order n, and of the
-// solve workspace for `vectors` (mode, right-hand side) vectors in nvb batches.
+// Device bytes of the factor storage for nb modes of order n.
 static size_t factor_bytes(int n, int nb, int precision) {
   const size_t nn = (size_t)n * n;
   return (size_t)nb * n * 2 * sizeof(int32_t) + (size_t)nb * sizeof(int32_t) +
          msv::lu_work_bytes(n, nb, precision == 0) + (precision == 1 ? (size_t)nb * nn * sizeof(float2) : 0) +
          (size_t)nb * ((n + 63) / 64) * 2 * 64 * 64 * (precision == 0 ? 16 : 8);
 }
-static size_t solve_bytes(int n, size_t vectors, size_t nvb, int precision) {
+// Device bytes of the solve workspace for `vectors` vectors of order n in nvb
+// batches, laid out as SolveWork, each part 256-byte aligned.
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+static size_t solve_work_bytes(size_t n, size_t vectors, size_t nvb, int precision) {
   const size_t elems = vectors * n;
-  return elems * (3 * sizeof(double2) + (precision == 1 ? 2 * sizeof(float2) : 0)) + vectors * sizeof(double) +
-         nvb * sizeof(msv::VecBatch);
+  return 3 * align256(sizeof(double2) * elems) + (precision == 1 ? 2 * align256(sizeof(float2) * elems) : 0) +
+         align256(sizeof(double) * (vectors + 1)) + align256(sizeof(msv::VecBatch) * nvb);
 }
 
 size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t n_modes, int32_t n_solve_vectors,
@@ -205,8 +201,8 @@ size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t n_modes, 
              2 * (N / kOrder) * sizeof(int) + N * NS + N * NS * sizeof(int2);
   b += factor_bytes((int)n, n_modes, precision);
   if (n_solve_vectors > 0)
-    b += solve_bytes((int)n, n_solve_vectors, (size_t)n_modes + (n_solve_vectors + msv::kVB - 1) / msv::kVB,
-                     precision);
+    b += solve_work_bytes(n, n_solve_vectors, (size_t)n_modes + (n_solve_vectors + msv::kVB - 1) / msv::kVB,
+                          precision);
   return b;
 }
 
@@ -217,8 +213,7 @@ size_t msv_plan_device_bytes(const msv_plan* p) {
   const size_t nbf = p->ipiv_elems / n;  // modes of the pivot storage
   b += p->ipiv_elems * 2 * sizeof(int32_t) + nbf * sizeof(int32_t) + p->luw_bytes + p->fac32_elems * sizeof(float2) +
        p->inv_bytes;
-  if (p->work_elems) b += solve_bytes((int)n, p->work_elems / n, 0, p->precision);
-  b += p->vb_cap * sizeof(msv::VecBatch);
+  b += p->work_bytes;
   return b;
 }
 
@@ -886,8 +881,19 @@ msv_status msv_batch_factor(msv_batch* b, void* stream) {
   return MSV_OK;
 }
 
-msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, const msv_c128* d_rhs,
-                     msv_c128* d_x, void* stream) {
+// Device workspace of one solve: weighted right-hand sides, solution and
+// residual (complex128), complex64 correction and sweep scratch (precision 1),
+// per-vector residual ratios and their maximum, the vector-batch table.
+struct SolveWork {
+  double2 *bw, *xw, *rw;
+  float2 *r32, *y32;
+  double* nrm;
+  msv::VecBatch* vb;
+};
+
+// Checks shared by both solve entry points; on success sets nvb.
+static msv_status solve_check(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, const msv_c128* d_rhs,
+                              msv_c128* d_x, int* nvb) {
   if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
   if (!d_rhs || !d_x || d_rhs == d_x) return fail(p, MSV_EINVAL, "need distinct rhs and x buffers");
   if (n_rhs < 1 || m_hi < m_lo) return fail(p, MSV_EINVAL, "empty solve");
@@ -896,97 +902,115 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
     int a = m < 0 ? -m : m;
     if (a < p->fac_lo || a > p->fac_hi) return fail(p, MSV_EINVAL, "mode outside the factored range");
   }
-  hipStream_t s = (hipStream_t)stream;
+  *nvb = msv::count_vec_batches(m_lo, m_hi - m_lo + 1, n_rhs, p->fac_lo, p->fac_hi - p->fac_lo + 1);
+  return MSV_OK;
+}
+
+static SolveWork carve_solve_work(char* base, size_t n, size_t vectors, size_t nvb, int precision) {
+  const size_t elems = vectors * n;
+  SolveWork w{};
+  w.bw = reinterpret_cast<double2*>(base);
+  base += align256(sizeof(double2) * elems);
+  w.xw = reinterpret_cast<double2*>(base);
+  base += align256(sizeof(double2) * elems);
+  w.rw = reinterpret_cast<double2*>(base);
+  base += align256(sizeof(double2) * elems);
+  if (precision == 1) {
+    w.r32 = reinterpret_cast<float2*>(base);
+    base += align256(sizeof(float2) * elems);
+    w.y32 = reinterpret_cast<float2*>(base);
+    base += align256(sizeof(float2) * elems);
+  }
+  w.nrm = reinterpret_cast<double*>(base);
+  base += align256(sizeof(double) * (vectors + 1));
+  w.vb = reinterpret_cast<msv::VecBatch*>(base);
+  return w;
+}
+
+// The solve itself, on a workspace the caller provides; allocates nothing.
+static msv_status solve_run(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, const msv_c128* d_rhs,
+                            msv_c128* d_x, int nvb, const SolveWork& w, hipStream_t s) {
   const int n = 4 * p->N, nm = m_hi - m_lo + 1;
   const int nfac = p->fac_hi - p->fac_lo + 1;
   if (!p->info_checked) {
-    std::vector<int32_t> info(nfac);
-    MSV_HIP(p, hipMemcpyAsync(info.data(), p->d_info, sizeof(int32_t) * nfac, hipMemcpyDeviceToHost, s));
-    MSV_HIP(p, hipStreamSynchronize(s));
-    for (int i = 0; i < nfac; ++i)
-      if (info[i] != 0) {
-        char buf[120];
-        snprintf(buf, sizeof buf, "zero pivot in mode %d at column %d", p->fac_lo + i, info[i] - 1);
-        return fail(p, MSV_ESINGULAR, buf);
-      }
+    // zero-pivot flags of the factorization, read in chunks into a fixed buffer
+    int32_t info[64];
+    for (int f0 = 0; f0 < nfac; f0 += 64) {
+      const int cnt = std::min(64, nfac - f0);
+      MSV_HIP(p, hipMemcpyAsync(info, p->d_info + f0, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+      MSV_HIP(p, hipStreamSynchronize(s));
+      for (int i = 0; i < cnt; ++i)
+        if (info[i] != 0) {
+          char buf[120];
+          snprintf(buf, sizeof buf, "zero pivot in mode %d at column %d", p->fac_lo + f0 + i, info[i] - 1);
+          return fail(p, MSV_ESINGULAR, buf);
+        }
+    }
     p->info_checked = true;
   }
   const size_t elems = (size_t)nm * n_rhs * n;
-  if (elems > p->work_elems) {
-    void* bufs[] = {p->d_bw, p->d_xw, p->d_rw, p->d_r32, p->d_y32, p->d_nrm};
-    for (void* bf : bufs)
-      if (bf) (void)hipFree(bf);
-    p->d_bw = p->d_xw = p->d_rw = nullptr;
-    p->d_r32 = p->d_y32 = nullptr;
-    p->d_nrm = nullptr;
-    p->work_elems = 0;
-    if (hipMalloc(&p->d_bw, sizeof(double2) * elems) != hipSuccess ||
-        hipMalloc(&p->d_xw, sizeof(double2) * elems) != hipSuccess ||
-        hipMalloc(&p->d_rw, sizeof(double2) * elems) != hipSuccess ||
-        (p->precision == 1 && (hipMalloc(&p->d_r32, sizeof(float2) * elems) != hipSuccess ||
-                               hipMalloc(&p->d_y32, sizeof(float2) * elems) != hipSuccess)) ||
-        hipMalloc(&p->d_nrm, sizeof(double) * (size_t)nm * n_rhs) != hipSuccess)
-      return fail(p, MSV_ENOMEM, "solve workspace allocation failed");
-    p->work_elems = elems;
-  }
-  // vector batches: every (mode, rhs) vector grouped by the factor it uses;
-  // the table is written on the device, in stream order behind any earlier
-  // solve on this plan that still reads it
-  const int nvb = msv::count_vec_batches(m_lo, nm, n_rhs, p->fac_lo, nfac);
-  if ((size_t)nvb > p->vb_cap) {
-    if (p->d_vb) (void)hipFree(p->d_vb);
-    p->d_vb = nullptr;
-    p->vb_cap = 0;
-    if (hipMalloc(&p->d_vb, sizeof(msv::VecBatch) * nvb) != hipSuccess)
-      return fail(p, MSV_ENOMEM, "batch table allocation failed");
-    p->vb_cap = nvb;
-  }
-  MSV_HIP(p, msv::build_vec_batches(p->d_vb, nvb, m_lo, nm, n_rhs, p->fac_lo, nfac, s));
+  // the batch table is written on the device, in stream order behind any
+  // earlier solve that still reads the same workspace
+  MSV_HIP(p, msv::build_vec_batches(w.vb, nvb, m_lo, nm, n_rhs, p->fac_lo, nfac, s));
   const long long nn = (long long)n * n;
   const double2* rhs = reinterpret_cast<const double2*>(d_rhs);
   double2* x = reinterpret_cast<double2*>(d_x);
-  MSV_HIP(p, msv::solve_prep(rhs, p->d_bw, p->d_sqw, n, n_rhs, nm, m_lo, s));
+  MSV_HIP(p, msv::solve_prep(rhs, w.bw, p->d_sqw, n, n_rhs, nm, m_lo, s));
   if (p->precision == 0) {
-    MSV_HIP(p, msv::gather_z(p->d_bw, p->d_xw, p->d_perm, p->d_vb, nvb, n, s));
+    MSV_HIP(p, msv::gather_z(w.bw, w.xw, p->d_perm, w.vb, nvb, n, s));
     MSV_HIP(p, msv::trsv_z(reinterpret_cast<const double2*>(p->fac_A), static_cast<const double2*>(p->d_inv), nn, n,
-                           p->d_vb, nvb, p->d_xw, p->d_rw, s));
+                           w.vb, nvb, w.xw, w.rw, s));
     p->last_ir_iters = 0;
-  } else {
-    const double2* Aref = reinterpret_cast<const double2*>(p->fac_A);
-    MSV_HIP(p, msv::zero_c128(p->d_xw, elems, s));
-    MSV_HIP(p, hipMemcpyAsync(p->d_rw, p->d_bw, sizeof(double2) * elems, hipMemcpyDeviceToDevice, s));
-    std::vector<double> rat((size_t)nm * n_rhs);
-    bool conv = false;
-    int it = 0;
-    // The steps that the plan's previous converged solve needed are queued
-    // without waiting; the residual is checked on the host only from the
-    // last of them on, so a repeated solve waits on the device once.
-    const int unchecked = std::min(p->ir_max_iter, std::max(p->ir_pred, 1)) - 1;
-    for (it = 1; it <= p->ir_max_iter; ++it) {
-      MSV_HIP(p, msv::gather_c(p->d_rw, p->d_r32, p->d_perm, p->d_vb, nvb, n, s));
-      MSV_HIP(p, msv::trsv_c(p->d_fac32, static_cast<const float2*>(p->d_inv), nn, n, p->d_vb, nvb, p->d_r32,
-                             p->d_y32, s));
-      MSV_HIP(p, msv::accum_c64(p->d_xw, p->d_r32, elems, s));
-      MSV_HIP(p, msv::residual_batches(Aref, nn, n, p->d_vb, nvb, p->d_bw, p->d_xw, p->d_rw, s));
-      if (it <= unchecked) continue;
-      MSV_HIP(p, msv::ratios(p->d_rw, p->d_bw, p->d_nrm, n, nm * n_rhs, s));
-      MSV_HIP(p, hipMemcpyAsync(rat.data(), p->d_nrm, sizeof(double) * rat.size(), hipMemcpyDeviceToHost, s));
-      MSV_HIP(p, hipStreamSynchronize(s));
-      double mx = 0.0;
-      for (double v : rat) mx = std::max(mx, v);
-      if (mx <= p->ir_tol) {
-        conv = true;
-        break;
-      }
-    }
-    p->last_ir_iters = conv ? it : p->ir_max_iter;
-    p->ir_pred = conv ? it : 0;
-    MSV_HIP(p, msv::solve_finish(p->d_xw, x, p->d_sqw, n, n_rhs, nm, m_lo, s));
-    if (!conv) return fail(p, MSV_ENOCONV, "iterative refinement did not reach ir_tol");
+    MSV_HIP(p, msv::solve_finish(w.xw, x, p->d_sqw, n, n_rhs, nm, m_lo, s));
     return MSV_OK;
   }
-  MSV_HIP(p, msv::solve_finish(p->d_xw, x, p->d_sqw, n, n_rhs, nm, m_lo, s));
+  const double2* Aref = reinterpret_cast<const double2*>(p->fac_A);
+  MSV_HIP(p, msv::zero_c128(w.xw, elems, s));
+  MSV_HIP(p, hipMemcpyAsync(w.rw, w.bw, sizeof(double2) * elems, hipMemcpyDeviceToDevice, s));
+  const int nvec = nm * n_rhs;
+  bool conv = false;
+  int it = 0;
+  // The steps that the plan's previous converged solve needed are queued
+  // without waiting; the largest residual ratio is read on the host only from
+  // the last of them on, so a repeated solve waits on the device once.
+  const int unchecked = std::min(p->ir_max_iter, std::max(p->ir_pred, 1)) - 1;
+  for (it = 1; it <= p->ir_max_iter; ++it) {
+    MSV_HIP(p, msv::gather_c(w.rw, w.r32, p->d_perm, w.vb, nvb, n, s));
+    MSV_HIP(p, msv::trsv_c(p->d_fac32, static_cast<const float2*>(p->d_inv), nn, n, w.vb, nvb, w.r32, w.y32, s));
+    MSV_HIP(p, msv::accum_c64(w.xw, w.r32, elems, s));
+    MSV_HIP(p, msv::residual_batches(Aref, nn, n, w.vb, nvb, w.bw, w.xw, w.rw, s));
+    if (it <= unchecked) continue;
+    MSV_HIP(p, msv::ratios(w.rw, w.bw, w.nrm, n, nvec, s));
+    double mx = 0.0;
+    MSV_HIP(p, hipMemcpyAsync(&mx, w.nrm + nvec, sizeof(double), hipMemcpyDeviceToHost, s));
+    MSV_HIP(p, hipStreamSynchronize(s));
+    if (mx <= p->ir_tol) {
+      conv = true;
+      break;
+    }
+  }
+  p->last_ir_iters = conv ? it : p->ir_max_iter;
+  p->ir_pred = conv ? it : 0;
+  MSV_HIP(p, msv::solve_finish(w.xw, x, p->d_sqw, n, n_rhs, nm, m_lo, s));
+  if (!conv) return fail(p, MSV_ENOCONV, "iterative refinement did not reach ir_tol");
   return MSV_OK;
+}
+
+msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, const msv_c128* d_rhs,
+                     msv_c128* d_x, void* stream) {
+  int nvb = 0;
+  MSV_CHECK(solve_check(p, m_lo, m_hi, n_rhs, d_rhs, d_x, &nvb));
+  const size_t n = 4 * (size_t)p->N, vectors = (size_t)(m_hi - m_lo + 1) * n_rhs;
+  const size_t need = solve_work_bytes(n, vectors, (size_t)nvb, p->precision);
+  if (need > p->work_bytes) {
+    if (p->d_work) (void)hipFree(p->d_work);
+    p->d_work = nullptr;
+    p->work_bytes = 0;
+    if (hipMalloc(&p->d_work, need) != hipSuccess) return fail(p, MSV_ENOMEM, "solve workspace allocation failed");
+    p->work_bytes = need;
+  }
+  const SolveWork w = carve_solve_work(static_cast<char*>(p->d_work), n, vectors, (size_t)nvb, p->precision);
+  return solve_run(p, m_lo, m_hi, n_rhs, d_rhs, d_x, nvb, w, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -100,6 +100,20 @@ __global__ __launch_bounds__(256) void ratio_inf(const double2* r, const double2
   if (threadIdx.x == 0) out[v] = sb[0] > 0 ? sr[0] / sb[0] : 0.0;
 }
 
+// out[0] = max of r[0 .. count)
+__global__ __launch_bounds__(256) void max_reduce(const double* r, int count, double* out) {
+  __shared__ double sm[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) v = fmax(v, r[i]);
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
 // The vectors of a solve over modes m_lo .. m_lo+nm-1 (n_rhs each), grouped
 // by the factor f = |m| - fac_lo they use: for each f the vectors of mode -a,
 // then of +a (a = fac_lo + f), right-hand sides in order, kVB to a batch.
@@ -184,6 +198,8 @@ hipError_t zero_c128(double2* x, size_t count, hipStream_t s) {
 }
 hipError_t ratios(const double2* r, const double2* b, double* out, int n, int nvec, hipStream_t s) {
   hipLaunchKernelGGL(ratio_inf, dim3(nvec), dim3(256), 0, s, r, b, out, n);
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  hipLaunchKernelGGL(max_reduce, dim3(1), dim3(256), 0, s, out, nvec, out + nvec);
   return hipGetLastError();
 }
 
