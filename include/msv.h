@@ -196,6 +196,24 @@ msv_status msv_factor(msv_plan *plan, msv_c128 *d_A, int32_t m_lo, int32_t m_hi,
 msv_status msv_solve(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_rhs,
                      const msv_c128 *d_rhs, msv_c128 *d_x, void *stream);
 
+/* msv_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, bit for bit, but its workspace is a static device array of the
+ * library, msv_solve_noalloc_max_bytes() = 192 MiB, of which each device the
+ * library runs on holds one copy until the process ends.  It calls no
+ * hipMalloc or hipFree (the plan's factors must already exist: msv_factor
+ * allocates).  A solve whose workspace would exceed the array -- 48 bytes
+ * per element of the (mode, right-hand side) vectors, 64 with precision 1:
+ * 257 modes of order 8192 with one right-hand side (135 MB) fit, with two
+ * they do not -- returns MSV_EINVAL; solve fewer modes or right-hand sides
+ * per call.  Every call on one device shares that
+ * device's array and leaves its contents behind (nothing in it is assumed to
+ * start at zero): calls that overlap on one device, on any streams or plans,
+ * race and must be serialized by the caller. */
+msv_status msv_solve_noalloc(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_rhs,
+                             const msv_c128 *d_rhs, msv_c128 *d_x, void *stream);
+size_t msv_solve_noalloc_max_bytes(void);
+
 /* Iterations used by the last precision-1 msv_solve (max over modes). */
 int32_t msv_last_ir_iterations(const msv_plan *plan);
 

@@ -23,7 +23,7 @@ EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nod
            "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations",
            "msv_batch_create", "msv_batch_factor", "msv_batch_destroy", "msv_batch_last_error",
            "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes",
-           "msv_tabulate_rows", "msv_assemble_rows"]
+           "msv_tabulate_rows", "msv_assemble_rows", "msv_solve_noalloc", "msv_solve_noalloc_max_bytes"]
 
 
 class MsvError(RuntimeError):
@@ -85,6 +85,10 @@ def load_library(path: str = LIB_PATH):
     lib.msv_factor.restype = ctypes.c_int
     lib.msv_solve.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.msv_solve.restype = ctypes.c_int
+    lib.msv_solve_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    lib.msv_solve_noalloc.restype = ctypes.c_int
+    lib.msv_solve_noalloc_max_bytes.argtypes = []
+    lib.msv_solve_noalloc_max_bytes.restype = ctypes.c_size_t
     lib.msv_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, P]
     lib.msv_batch_create.restype = ctypes.c_int
@@ -255,6 +259,19 @@ class Plan:
         self._check(self.lib.msv_solve(self._h, int(m_lo), int(m_hi), int(rhs.shape[1]),
                                        ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                        _stream_handle(stream)))
+        return out
+
+
+    def solve_noalloc(self, m_lo, m_hi, rhs, out, stream=None):
+        """msv_solve with the library's static workspace (no device allocation;
+        `out` must be preallocated)."""
+        import torch
+        nm = m_hi - m_lo + 1
+        assert rhs.dtype == torch.complex128 and rhs.is_contiguous() and rhs.shape[0] == nm
+        assert rhs.shape[2] == self.n and out.shape == rhs.shape and out.is_contiguous()
+        self._check(self.lib.msv_solve_noalloc(self._h, int(m_lo), int(m_hi), int(rhs.shape[1]),
+                                               ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                               _stream_handle(stream)))
         return out
 
 

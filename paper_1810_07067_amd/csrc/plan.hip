@@ -7,10 +7,18 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "msv_internal.h"
+
+// Workspace of msv_solve_noalloc: one array per device, held by the process
+// for its whole life.  In host code `scratch` names a host-side stand-in, not
+// the device memory: host code uses only the per-device address that
+// hipGetSymbolAddress returns for it (g_scratch below).
+constexpr size_t kScratchBytes = (size_t)192 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 using msv::kOrder;
 using cplx = std::complex<double>;
@@ -58,11 +66,42 @@ struct msv_plan {
   size_t geom_bytes = 0;  // device bytes of the geometry uploaded at creation
   int batch_refs = 0;
   bool destroy_pending = false;
+  // device address of `scratch` on the plan's device (null if it could not be
+  // resolved; scratch_err says why)
+  void* scratch = nullptr;
+  std::string scratch_err;
   std::string err;
 };
 
 static thread_local std::string g_create_err;
 
+// Per-device address of `scratch`, resolved once per device with that device
+// current.
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+void* scratch_address(std::string& err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
+}  // namespace
 
 namespace {
 
@@ -486,6 +525,8 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   UP(p->d_cls, cls);
   UP(p->d_near, nearv);
 #undef UP
+  // set-up of the allocation-free solve's workspace on this device
+  p->scratch = scratch_address(p->scratch_err);
   (void)stream;
   *out = p;
   return MSV_OK;
@@ -1012,5 +1053,24 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
   const SolveWork w = carve_solve_work(static_cast<char*>(p->d_work), n, vectors, (size_t)nvb, p->precision);
   return solve_run(p, m_lo, m_hi, n_rhs, d_rhs, d_x, nvb, w, (hipStream_t)stream);
 }
+
+msv_status msv_solve_noalloc(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, const msv_c128* d_rhs,
+                             msv_c128* d_x, void* stream) {
+  int nvb = 0;
+  MSV_CHECK(solve_check(p, m_lo, m_hi, n_rhs, d_rhs, d_x, &nvb));
+  if (!p->scratch) return fail(p, MSV_EHIP, "no device address for the static workspace: " + p->scratch_err);
+  const size_t n = 4 * (size_t)p->N, vectors = (size_t)(m_hi - m_lo + 1) * n_rhs;
+  const size_t need = solve_work_bytes(n, vectors, (size_t)nvb, p->precision);
+  if (need > kScratchBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "solve needs %zu bytes of workspace; msv_solve_noalloc has %zu: solve fewer modes "
+             "or right-hand sides per call", need, kScratchBytes);
+    return fail(p, MSV_EINVAL, buf);
+  }
+  const SolveWork w = carve_solve_work(static_cast<char*>(p->scratch), n, vectors, (size_t)nvb, p->precision);
+  return solve_run(p, m_lo, m_hi, n_rhs, d_rhs, d_x, nvb, w, (hipStream_t)stream);
+}
+
+size_t msv_solve_noalloc_max_bytes(void) { return kScratchBytes; }
 
 }  // extern "C"
