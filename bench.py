@@ -343,6 +343,8 @@ def main():
                     help="skip the complex128-path comparison and the secondary workload")
     ap.add_argument("--form", choices=["batching", "serving"],
                     help="measure one AI-systems form instead of the step (separate JSON line)")
+    ap.add_argument("--modes", type=int, default=None,
+                    help="with --profile-target lu: factor modes 0..modes-1 only")
     ap.add_argument("--profile-target", choices=["lu", "tabulate", "copy"],
                     help="run one piece once for hardware counters and exit: the LU of the workload, "
                          "its tabulation, or a 1 GiB device copy (counter calibration)")
@@ -353,7 +355,7 @@ def main():
         sys.exit(2)
     if args.profile_target:
         from bench_forms import profile_target
-        profile_target(args.profile_target, args.config)
+        profile_target(args.profile_target, args.config, args.modes)
         return
     if args.form:
         from bench_forms import run_form

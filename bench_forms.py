@@ -115,8 +115,10 @@ def run_form(form):
     return {"form": "serving", "complex64_lu_refined": bench_serving(rls, 1), "complex128_lu": bench_serving(rls, 0)}
 
 
-def profile_target(what, config):
-    """One piece of the step, once, for rocprofv3 counter runs."""
+def profile_target(what, config, modes=None):
+    """One piece of the step, once, for rocprofv3 counter runs.  `modes`
+    limits the LU to modes 0..modes-1 (each matrix's factorization is
+    independent of the others in the batch)."""
     import torch
     import paper_1810_07067_amd as msv
     if what == "copy":
@@ -141,10 +143,12 @@ def profile_target(what, config):
             plan.tabulate_rows(t0, nt, out=kb)
             print(f"tabulated rows {t0}..{t0 + nt - 1}", file=sys.stderr, flush=True)
     else:
-        A = plan.assemble_streamed(0, M, rows_per_block=nb, block=block)
+        mh = M if modes is None else min(M, int(modes) - 1)
+        A = plan.assemble_streamed(0, mh, rows_per_block=nb, block=block)
         del block
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        plan.factor(A, 0, M)
+        print(f"assembled modes 0..{mh}", file=sys.stderr, flush=True)
+        plan.factor(A, 0, mh)
     torch.cuda.synchronize()
     print(f"{what} done", flush=True)
