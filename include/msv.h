@@ -76,7 +76,8 @@ typedef struct {
   msv_c128 eps0, mu0;        /* exterior: real and positive */
   msv_c128 eps1, mu1;        /* interior: Re > 0, Im >= 0 (eq. materials) */
   int32_t m_max;             /* M: modes |m| <= M are assembled and solved */
-  int32_t fft_len;           /* L: azimuthal FFT length, a power of two; the
+  int32_t fft_len;           /* L: azimuthal FFT length, a power of two in
+                                [8, 1024]; the
                                 plan refuses L too short for M and k (the
                                 discrete convolution of eq. discA needs
                                 M + 1 + N_f <= L/2 - 1) */
@@ -102,18 +103,19 @@ int32_t msv_matrix_order(const msv_plan *plan);
 
 /* Device memory owned by a plan (not the caller's table, matrices, right-hand
  * sides or solutions).  msv_workspace_bytes is an upper bound, computable
- * before any plan exists, on what a plan of n_nodes nodes and n_support support
- * slots holds once n_modes modes are factored (msv_factor) and a solve of
- * n_solve_vectors (mode, right-hand side) vectors at once has run: geometry,
- * pivots, LU workspace, complex64 factors (precision 1), diagonal-block
- * inverses and the solve workspace.  It counts the near-pair list at its
- * largest (every pair), so it exceeds the real footprint by at most
- * 8 N (N + S) bytes plus one 72-byte batch record per factored mode and 256
- * bytes of alignment.  Returns 0 for
- * invalid arguments.  msv_plan_device_bytes is what the plan holds now.
- * Neither touches the device. */
-size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t n_modes, int32_t n_solve_vectors,
-                           int32_t precision);
+ * before any plan exists, on what a plan of n_nodes nodes, n_support support
+ * slots and FFT length fft_len holds once n_modes modes are factored
+ * (msv_factor) and a solve of n_solve_vectors (mode, right-hand side) vectors
+ * at once has run: geometry, the near pairs' spectra scratch (at most 65536
+ * pairs x (fft_len/2 + 1) x 16 bytes), pivots, LU workspace, complex64 factors
+ * (precision 1), diagonal-block inverses and the solve workspace.  It counts
+ * the near-pair list and the spectra scratch as if every pair were near, so it
+ * exceeds the real footprint by at most 8 N (N + S) bytes plus that scratch's
+ * unused part, one 72-byte batch record per factored mode and 256 bytes of
+ * alignment.  Returns 0 for invalid arguments.  msv_plan_device_bytes is what
+ * the plan holds now.  Neither touches the device. */
+size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t fft_len, int32_t n_modes,
+                           int32_t n_solve_vectors, int32_t precision);
 size_t msv_plan_device_bytes(const msv_plan *plan);
 
 /* Modal Green's functions (Section 4): for every target node t, every source

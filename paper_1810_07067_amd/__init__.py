@@ -106,7 +106,7 @@ def load_library(path: str = LIB_PATH):
     lib.msv_tabulate_rows.restype = ctypes.c_int
     lib.msv_assemble_rows.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
     lib.msv_assemble_rows.restype = ctypes.c_int
-    lib.msv_workspace_bytes.argtypes = [ctypes.c_int32] * 5
+    lib.msv_workspace_bytes.argtypes = [ctypes.c_int32] * 6
     lib.msv_workspace_bytes.restype = ctypes.c_size_t
     lib.msv_plan_device_bytes.argtypes = [P]
     lib.msv_plan_device_bytes.restype = ctypes.c_size_t
@@ -318,11 +318,11 @@ class Batch:
             pass
 
 
-def workspace_bytes(n_nodes, n_support, n_modes, n_solve_vectors, precision, lib=None):
+def workspace_bytes(n_nodes, n_support, fft_len, n_modes, n_solve_vectors, precision, lib=None):
     """Upper bound on a plan's own device memory (msv_workspace_bytes)."""
     lib = lib or load_library()
-    return int(lib.msv_workspace_bytes(int(n_nodes), int(n_support), int(n_modes), int(n_solve_vectors),
-                                       int(precision)))
+    return int(lib.msv_workspace_bytes(int(n_nodes), int(n_support), int(fft_len), int(n_modes),
+                                       int(n_solve_vectors), int(precision)))
 
 
 def plan_from_curve(curve, rules, k0, eps1, mu1=1.0, m_max=16, fft_len=64, precision=0, **kw):

@@ -39,7 +39,25 @@ struct TabParams {
   // row block: targets t0 .. t0+nt-1, their near pairs near[near_lo .. near_hi)
   int t0, nt, near_lo, near_hi;
   double2* out;         // [M2][9][nt][NS]
+  // scratch for the Legendre-Q spectra of up to spec_cap near pairs at a
+  // time: [spec_cap][L/2 + 1] complex (X1_n, X3_n)
+  double2* spec;
+  int spec_cap;
+  // azimuth tables of the transforms, N = L/2: [N] e^{-2 pi i k / 2N}, then
+  // [N/2 + 1] (cos, sin)(pi j / N), then [N + 2] sin^2(pi j / 2N) (doubles)
+  const double2* tabs;
 };
+// doubles in the azimuth tables for FFT length L
+inline size_t tab_doubles(int L) {
+  const size_t N = L / 2;
+  return 2 * N + 2 * (N / 2 + 1) + (N + 2);
+}
+// near pairs whose spectra the scratch holds at once, and its size in bytes
+constexpr int kSpecCap = 65536;
+inline size_t spec_bytes(int L, int n_near) {
+  const size_t cap = (size_t)(n_near < kSpecCap ? n_near : kSpecCap);
+  return cap * (size_t)(L / 2 + 1) * sizeof(double2);
+}
 
 // Support-slot record (doubles): offset from the target, the source geometry
 // needed by the assembly, and the quadrature weight (0 = unused slot).

@@ -42,6 +42,9 @@ struct msv_plan {
   uint8_t* d_cls = nullptr;
   int2* d_near = nullptr;
   int n_near = 0;
+  double2* d_spec = nullptr;  // Legendre-Q spectra of up to spec_cap near pairs
+  int spec_cap = 0;
+  double* d_tabs = nullptr;   // azimuth tables of the transforms
   std::vector<int> near_start;  // [N+1]: near pairs of target t are near[near_start[t] ..]
   // factors
   int fac_lo = -1, fac_hi = -1;
@@ -205,7 +208,7 @@ size_t msv_table_entries(const msv_plan* p) {
 static void plan_free(msv_plan* p) {
   void* bufs[] = {p->d_r, p->d_z, p->d_tr, p->d_tz, p->d_w, p->d_sqw, p->d_sup, p->d_lag_self,
                   p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
-                  p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_work};
+                  p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_work, p->d_spec, p->d_tabs};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -227,17 +230,20 @@ static size_t solve_work_bytes(size_t n, size_t vectors, size_t nvb, int precisi
          align256(sizeof(double) * (vectors + 1)) + align256(sizeof(msv::VecBatch) * nvb);
 }
 
-size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t n_modes, int32_t n_solve_vectors,
-                           int32_t precision) {
-  if (n_nodes < 1 || n_support < 0 || n_modes < 1 || n_solve_vectors < 0 || (precision != 0 && precision != 1))
+size_t msv_workspace_bytes(int32_t n_nodes, int32_t n_support, int32_t fft_len, int32_t n_modes,
+                           int32_t n_solve_vectors, int32_t precision) {
+  if (n_nodes < 1 || n_support < 0 || fft_len < 8 || fft_len > 1024 || n_modes < 1 || n_solve_vectors < 0 ||
+      (precision != 0 && precision != 1))
     return 0;
   const size_t N = n_nodes, S = n_support, NS = N + S, n = 4 * N;
   // geometry: 6 node arrays, support records, Lagrange rows (bounded by the
-  // slot count), neighbour lists, pair classes, near-pair list (at most every
-  // pair)
+  // slot count), neighbour lists, pair classes, near-pair list and the
+  // near pairs' spectra scratch (at most every pair near)
+  const int near_max = (int)std::min<size_t>(N * NS, (size_t)1 << 30);
   size_t b = 6 * N * sizeof(double) + N * S * msv::kSupFields * sizeof(double) +
              (size_t)kOrder * kOrder * S * sizeof(double) + kOrder * S * sizeof(double) +
-             2 * (N / kOrder) * sizeof(int) + N * NS + N * NS * sizeof(int2);
+             2 * (N / kOrder) * sizeof(int) + N * NS + N * NS * sizeof(int2) + msv::spec_bytes(fft_len, near_max) +
+             msv::tab_doubles(fft_len) * sizeof(double);
   b += factor_bytes((int)n, n_modes, precision);
   if (n_solve_vectors > 0)
     b += solve_work_bytes(n, n_solve_vectors, (size_t)n_modes + (n_solve_vectors + msv::kVB - 1) / msv::kVB,
@@ -283,8 +289,8 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   if (!(d->eps1.re > 0 && d->eps1.im >= 0 && d->mu1.re > 0 && d->mu1.im >= 0))
     return fail(nullptr, MSV_EINVAL, "need Re eps1, Re mu1 > 0 and Im eps1, Im mu1 >= 0");
   if (d->m_max < 0) return fail(nullptr, MSV_EINVAL, "m_max must be >= 0");
-  if (d->fft_len < 8 || (d->fft_len & (d->fft_len - 1)))
-    return fail(nullptr, MSV_EINVAL, "fft_len must be a power of two >= 8");
+  if (d->fft_len < 8 || d->fft_len > 1024 || (d->fft_len & (d->fft_len - 1)))
+    return fail(nullptr, MSV_EINVAL, "fft_len must be a power of two in [8, 1024]");
   if (d->precision != 0 && d->precision != 1) return fail(nullptr, MSV_EINVAL, "precision must be 0 or 1");
   const int N = c->n_panels * kOrder;
   if (4 * N > 8192) return fail(nullptr, MSV_EINVAL, "4N > 8192 exceeds the LU panel kernel");
@@ -525,6 +531,41 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   UP(p->d_cls, cls);
   UP(p->d_near, nearv);
 #undef UP
+  {
+    // azimuth tables (long double, rounded once): e^{-2 pi i k / L},
+    // (cos, sin)(2 pi j / L), sin^2(pi j / L)
+    const int Nh = p->L / 2;
+    std::vector<double> tabs(msv::tab_doubles(p->L), 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < Nh; ++k) {
+      tabs[2 * k] = (double)std::cos(pi * k / Nh);
+      tabs[2 * k + 1] = (double)-std::sin(pi * k / Nh);
+    }
+    double* cs = tabs.data() + 2 * Nh;
+    for (int j = 0; j <= Nh / 2; ++j) {
+      cs[2 * j] = (double)std::cos(pi * j / Nh);
+      cs[2 * j + 1] = (double)std::sin(pi * j / Nh);
+    }
+    double* s2 = cs + 2 * (Nh / 2 + 1);
+    for (int j = 0; j <= Nh; ++j) {
+      const long double sn = std::sin(pi * j / (2 * Nh));
+      s2[j] = (double)(sn * sn);
+    }
+    msv_status st2 = upload(p, &p->d_tabs, tabs.data(), tabs.size());
+    if (st2 != MSV_OK) {
+      msv_plan_destroy(p);
+      return st2;
+    }
+  }
+  p->spec_cap = std::min(p->n_near, msv::kSpecCap);
+  if (p->spec_cap > 0) {
+    const size_t sb = msv::spec_bytes(p->L, p->n_near);
+    if (hipMalloc(&p->d_spec, sb) != hipSuccess) {
+      msv_plan_destroy(p);
+      return fail(nullptr, MSV_ENOMEM, "spectra scratch allocation failed");
+    }
+    p->geom_bytes += sb;
+  }
   // set-up of the allocation-free solve's workspace on this device
   p->scratch = scratch_address(p->scratch_err);
   (void)stream;
@@ -562,6 +603,9 @@ msv_status msv_tabulate_rows(msv_plan* p, int32_t t0, int32_t nt, msv_c128* d_ke
   T.nt = nt;
   T.near_lo = p->near_start[t0];
   T.near_hi = p->near_start[t0 + nt];
+  T.spec = p->d_spec;
+  T.spec_cap = p->spec_cap;
+  T.tabs = reinterpret_cast<const double2*>(p->d_tabs);
   T.out = reinterpret_cast<double2*>(d_kern);
   MSV_HIP(p, msv::launch_tabulate(T, (hipStream_t)stream));
   return MSV_OK;

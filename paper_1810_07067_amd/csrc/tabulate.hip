@@ -11,12 +11,12 @@
 // Lemma A.2), which turns the L-point sum into the discrete convolution of
 // eq. discA.
 //
-// Work decomposition: a 256-thread workgroup owns TP pairs.  The folded sample
-// index j in [0, L/4] pairs phi_j with pi - phi_j, so even modes need
-// f(phi_j) + f(pi - phi_j) and odd modes f(phi_j) - f(pi - phi_j).  Samples are
-// produced chunk by chunk into LDS (one thread per (pair, folded j)), then each
-// thread accumulates 18 real sequences x MB modes of one parity for one pair
-// in registers.  Outputs go to HBM once, coalesced along the source index.
+// Work decomposition: a 256-thread workgroup owns TP = max(1, 256 / (L/2))
+// pairs and keeps all L/2 + 1 azimuth samples of their nine integrands in LDS.
+// Near pairs first synthesize their band-limited 1/rho, 1/rho^3 from the
+// spectra with one real-even FFT; then every pair's samples are transformed
+// with nine real-even FFTs (see the transform section below) and modes
+// m = 0..M+1 go to HBM, consecutive threads writing consecutive sources.
 #include <hip/hip_runtime.h>
 
 #include "msv_internal.h"
@@ -24,11 +24,7 @@
 namespace msv {
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kSeq = 2 * kTypes;  // 18 real sequences
-// LDS stride of one pair's folded samples: one double of padding puts the
-// pairs a wave reads at distinct banks
-constexpr int kEO = 2 * kSeq + 1;
 constexpr int kNSer = 13;  // |x| <= 2: the 13th term is below 1e-17 of the first
 
 struct SeriesCoef {
@@ -275,9 +271,16 @@ __device__ void elliptic_ke(double kp2, double& K, double& E) {
   E = K * (1.0 - s);
 }
 
-// Spectra X1_n, X3_n (n = 0..Mq) of 1/rho and 1/rho^3 for one near pair.
-// Written to x1[n], x3[n] (LDS).
-__device__ void near_spectra(const Pair& g, const TabParams& P, double* x1, double* x3) {
+// LDS position of element i of a transform sequence: one element of padding
+// per 16 spreads the bit-reversed stores of the transforms (indices that
+// differ only in their high bits) over distinct banks.
+__device__ __forceinline__ int lpos(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int seq_stride(int N) { return N + 1 + ((N + 1) >> 4) + 1; }
+
+// Spectra X1_n, X3_n (n = 0..Mq) of 1/rho and 1/rho^3 for one near pair:
+// xs(n) = (X1_n, X3_n) for n <= Mq, xs(Mq + 1) = 0 (xs(n) returns a reference).
+template <class At>
+__device__ void near_spectra(const Pair& g, const TabParams& P, At xs) {
   const int Mq = P.Mq;
   double eta = g.d2 / (2.0 * g.rt * g.rs);
   double chi = 1.0 + eta;
@@ -293,17 +296,16 @@ __device__ void near_spectra(const Pair& g, const TabParams& P, double* x1, doub
     //   (n + 1/2) D_{n+1} = (n - 1/2) D_n + 2 n eta Q_{n-1/2}
     double Q = q0;
     double D = eta * q0 - tail;
-    x1[0] = c1 * Q;
-    x3[0] = c3 * tail;
+    xs(0) = make_double2(c1 * Q, c3 * tail);
     for (int n = 1; n <= Mq; ++n) {
       Q = Q + D;
       double num = D + eta * Q;
-      x1[n] = c1 * Q;
-      x3[n] = c3 * (1.0 - 2.0 * n) * num;
+      xs(n) = make_double2(c1 * Q, c3 * (1.0 - 2.0 * n) * num);
       D = ((n - 0.5) * D + 2.0 * n * eta * Q) / (n + 0.5);
     }
   } else {
-    // Miller's backward recurrence from n_start, normalized by Q_{-1/2}.
+    // Miller's backward recurrence from n_start, normalized by Q_{-1/2}; the
+    // raw values are kept in the .x slots until the normalization is known.
     int ns = P.fwd_n + (int)ceil(P.miller_extra / acs);
     if (ns < Mq + 2) ns = Mq + 2;
     double fhi = 0.0, f = 1.0;
@@ -311,61 +313,295 @@ __device__ void near_spectra(const Pair& g, const TabParams& P, double* x1, doub
       double flo = (2.0 * n * chi * f - (n + 0.5) * fhi) / (n - 0.5);
       fhi = f;
       f = flo;
-      if (n - 1 <= Mq) x1[n - 1] = f;
+      if (n - 1 <= Mq) xs(n - 1).x = f;
       if (fabs(f) > 1e250) {
         fhi *= 1e-250;
         f *= 1e-250;
-        for (int i = n - 1; i <= Mq; ++i) x1[i] *= 1e-250;
+        for (int i = n - 1; i <= Mq; ++i) xs(i).x *= 1e-250;
       }
     }
-    double sc = q0 / x1[0];
+    double sc = q0 / xs(0).x;
     // num_n = chi Q_n - Q_{n-1}; go downward so Q_{n-1} is still raw
     for (int n = Mq; n >= 1; --n) {
-      double Qn = x1[n] * sc, Qm = x1[n - 1] * sc;
-      x3[n] = c3 * (1.0 - 2.0 * n) * (chi * Qn - Qm);
+      double Qn = xs(n).x * sc, Qm = xs(n - 1).x * sc;
+      xs(n).y = c3 * (1.0 - 2.0 * n) * (chi * Qn - Qm);
     }
-    x3[0] = c3 * tail;
-    for (int n = 0; n <= Mq; ++n) x1[n] = c1 * (x1[n] * sc);
+    xs(0).y = c3 * tail;
+    for (int n = 0; n <= Mq; ++n) xs(n).x = c1 * (xs(n).x * sc);
+  }
+  xs(Mq + 1) = make_double2(0.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Real-even transforms (the discrete convolution of eq. discA).
+//
+// Every sequence here is even with period L = 2N, so only x_0 .. x_N are held,
+// and its length-L DFT is the type-I cosine transform
+//   F_m = x_0 + (-1)^m x_N + 2 sum_{j=1}^{N-1} x_j cos(pi m j / N),  m = 0..N.
+// With u_j = x_j + x_{N-j}, v_j = x_j - x_{N-j} and y_j = u_j - 2 sin(pi j/N) v_j
+// (j = 0..N-1, x_{N-0} = x_N) and Y = FFT_N(y):
+//   F_{2k}   = (Y_k + Y_{N-k}) / 2,
+//   F_{2k+1} = F_{2k-1} + i (Y_k - Y_{N-k}) / 2,   F_1 = sum_j cos(pi j/N) v_j,
+// for complex x as well (the real and imaginary parts are two real even
+// sequences and every step is linear with real coefficients), so one complex
+// FFT of length N transforms the real and imaginary parts of one kernel type.
+// The odd outputs come from a running sum started at F_1, so each carries an
+// absolute error of a few ulps of |F_1|: harmless for the modal coefficients,
+// but the band-limited 1/rho, 1/rho^3 of a near-singular pair fall by many
+// orders of magnitude from phi = 0 to pi.  Those are therefore synthesized
+// from their spectra with a complex FFT of the full length 2N of the even
+// extension, which needs no running sum (the two real spectra share it).
+// All of it runs on the workgroup's LDS; the FFT is an in-place radix-2
+// decimation in time on bit-reversed input, two stages per pass through LDS.
+// ---------------------------------------------------------------------------
+struct Seqs {
+  double2* base;  // sequence s at base + s * stride, element i at lpos(i)
+  int stride;
+  int nseq;
+};
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+
+// pre-pass: y in bit-reversed order, F_1 per sequence into f1[s].  One wave
+// per sequence; every lane loads before any lane stores.
+constexpr int kMaxR = 5;  // (N/2 + 1) / 64 rounded up, N <= 512
+__device__ void dct_pre(const Seqs& q, int logN, const double2* cs, double2* f1, int wave, int lane, int nwaves) {
+  const int N = 1 << logN, H = N / 2;
+  for (int s = wave; s < q.nseq; s += nwaves) {
+    double2* x = q.base + (size_t)s * q.stride;
+    double2 xa[kMaxR], xb[kMaxR];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+      const int j = lane + 64 * r;
+      const int jc = j <= H ? j : H;  // lanes past N/2 load a valid element and drop it
+      xa[r] = x[lpos(jc)];
+      xb[r] = x[lpos(N - jc)];
+      if (j > H) xa[r] = xb[r] = make_double2(0, 0);
+    }
+    double2 acc = make_double2(0, 0);
+    double2 ya[kMaxR], yb[kMaxR];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+      const int j = lane + 64 * r;
+      const double2 u = cadd(xa[r], xb[r]), v = csub(xa[r], xb[r]);
+      const double c = (j <= H) ? cs[j].x : 0.0, sn = (j <= H) ? cs[j].y : 0.0;
+      // F_1 = v_0 + 2 sum_{0<j<N/2} cos(pi j/N) v_j (the pairs j, N-j)
+      const double wgt = (j == 0) ? 1.0 : (j < H ? 2.0 * c : 0.0);
+      acc = make_double2(fma(wgt, v.x, acc.x), fma(wgt, v.y, acc.y));
+      ya[r] = make_double2(fma(-2.0 * sn, v.x, u.x), fma(-2.0 * sn, v.y, u.y));
+      yb[r] = make_double2(fma(2.0 * sn, v.x, u.x), fma(2.0 * sn, v.y, u.y));
+    }
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+      const int j = lane + 64 * r;
+      if (j > H) continue;
+      const unsigned rj = __brev((unsigned)j) >> (32 - logN);
+      x[lpos((int)rj)] = ya[r];
+      if (j != 0 && j != H) {
+        const unsigned rk = __brev((unsigned)(N - j)) >> (32 - logN);
+        x[lpos((int)rk)] = yb[r];
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, 64);
+      acc.y += __shfl_xor(acc.y, o, 64);
+    }
+    if (lane == 0) f1[s] = acc;
   }
 }
 
-template <bool NEAR, bool K1C, int MB>
-__global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP, int JC, int Q) {
-  extern __shared__ double smem[];
-  const int L = P.L;
-  const int Lq = L / 4;
-  const int Mq = P.Mq;
-  double* cos_tab = smem;                 // [L]
-  double* s2_tab = cos_tab + L;           // [L/2 + 1]
-  double* geo = s2_tab + (L / 2 + 2);     // [TP][4]: rt, dr, dz, valid flag
-  double* EO = geo + 4 * TP;              // [JC][TP][kEO]: 2 x 18 folded samples
-  double* Xh = EO + (size_t)JC * TP * kEO;  // NEAR: [TP][2][Mq+1]
-  int* tgt = reinterpret_cast<int*>(NEAR ? Xh + (size_t)TP * 2 * (Mq + 1) : Xh);  // [TP] t, [TP] src
+// in-place FFT of length N = 2^logN of every sequence (bit-reversed input,
+// natural output); tw[ts * k] = e^{-2 pi i k / N}, k < N/2.  Ends with a
+// barrier.
+__device__ void dct_fft(const Seqs& q, int logN, const double2* tw, int ts, int tid, int nthreads) {
+  const int N = 1 << logN;
+  int h = 1, lh = 0;
+  for (; 4 * h <= N; h *= 4, lh += 2) {
+    const int lG = logN - 2;  // N/4 butterfly groups per sequence
+    const int total = q.nseq << lG;
+    for (int g = tid; g < total; g += nthreads) {
+      const int s = g >> lG, r = g & ((1 << lG) - 1);
+      const int p = r & (h - 1), b = r >> lh;
+      double2* x = q.base + (size_t)s * q.stride;
+      const int i0 = b * 4 * h + p;
+      double2 a0 = x[lpos(i0)], a1 = x[lpos(i0 + h)], a2 = x[lpos(i0 + 2 * h)], a3 = x[lpos(i0 + 3 * h)];
+      const double2 w1 = tw[ts * p * (N / (2 * h))];
+      double2 t = cmul(w1, a1);
+      a1 = csub(a0, t);
+      a0 = cadd(a0, t);
+      t = cmul(w1, a3);
+      a3 = csub(a2, t);
+      a2 = cadd(a2, t);
+      const double2 w2 = tw[ts * p * (N / (4 * h))], w3 = tw[ts * (p + h) * (N / (4 * h))];
+      t = cmul(w2, a2);
+      a2 = csub(a0, t);
+      a0 = cadd(a0, t);
+      t = cmul(w3, a3);
+      a3 = csub(a1, t);
+      a1 = cadd(a1, t);
+      x[lpos(i0)] = a0;
+      x[lpos(i0 + h)] = a1;
+      x[lpos(i0 + 2 * h)] = a2;
+      x[lpos(i0 + 3 * h)] = a3;
+    }
+    __syncthreads();
+  }
+  if (h < N) {  // one radix-2 stage left: half size h = N/2
+    const int total = q.nseq << lh;
+    for (int g = tid; g < total; g += nthreads) {
+      const int s = g >> lh, p = g & (h - 1);
+      double2* x = q.base + (size_t)s * q.stride;
+      const double2 a0 = x[lpos(p)], t = cmul(tw[ts * p], x[lpos(p + h)]);
+      x[lpos(p + h)] = csub(a0, t);
+      x[lpos(p)] = cadd(a0, t);
+    }
+    __syncthreads();
+  }
+}
+
+// post-pass: outputs F_m * scale for m < mout, in place at lpos(m).  One wave
+// per sequence; each lane owns consecutive k and every lane loads before any
+// lane stores.
+__device__ void dct_post(const Seqs& q, int logN, int mout, double scale, const double2* f1, int wave, int lane,
+                         int nwaves) {
+  const int N = 1 << logN;
+  const int kmax = (mout - 1) / 2;  // F_{2k} or F_{2k+1} below mout for k <= kmax
+  const int R = (kmax + 64) / 64;   // <= kMaxR
+  for (int s = wave; s < q.nseq; s += nwaves) {
+    double2* x = q.base + (size_t)s * q.stride;
+    double2 yk[kMaxR], yn[kMaxR];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+      const int k = lane * R + r;
+      const bool ok = r < R && k <= kmax;
+      const int kc = ok ? k : 0;  // lanes without a k load element 0 and drop it
+      yk[r] = x[lpos(kc)];
+      yn[r] = x[lpos((N - kc) & (N - 1))];
+      if (!ok) yk[r] = yn[r] = make_double2(0, 0);
+    }
+    // odd outputs: prefix sums of D_k = i (Y_k - Y_{N-k}) / 2, D_0 = 0
+    double2 pre[kMaxR];
+    double2 run = make_double2(0, 0);
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+      const int k = lane * R + r;
+      if (r < R && k >= 1) {
+        run.x += -0.5 * (yk[r].y - yn[r].y);
+        run.y += 0.5 * (yk[r].x - yn[r].x);
+      }
+      pre[r] = run;
+    }
+    // exclusive scan of the lane totals across the wave
+    double2 inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double ux = __shfl_up(inc.x, o, 64), uy = __shfl_up(inc.y, o, 64);
+      if (lane >= o) {
+        inc.x += ux;
+        inc.y += uy;
+      }
+    }
+    const double2 base1 = cadd(f1[s], csub(inc, run));
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+      const int k = lane * R + r;
+      if (r >= R || k > kmax) continue;
+      if (2 * k < mout) x[lpos(2 * k)] = cscale(0.5 * scale, cadd(yk[r], yn[r]));
+      if (2 * k + 1 < mout) x[lpos(2 * k + 1)] = cscale(scale, cadd(base1, pre[r]));
+    }
+  }
+}
+
+constexpr int kThreads = 256;
+
+// The Legendre-Q spectra of near pairs near[near_lo .. near_hi), one thread
+// per pair, into spec[idx - near_lo][n], n = 0..N (N = L/2; the recurrences are
+// serial in n).  The exponent e that scales the 1/rho^3 spectrum to the size
+// of the 1/rho one (their transform is shared; see below) is stored in place
+// of the zero entry n = N.
+__global__ __launch_bounds__(kThreads) void near_spectra_kernel(TabParams P) {
+  const long long idx = (long long)P.near_lo + (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= P.near_hi) return;
+  const int N = P.L / 2;
+  const int2 pr = P.near[idx];
+  const int t = pr.x, src = pr.y;
+  const double rt = P.r[t];
+  double dr, dz;
+  if (src < P.N) {
+    dr = P.r[src] - rt;
+    dz = P.z[src] - P.z[t];
+  } else {
+    const double* sp = P.sup + ((size_t)t * P.S + (src - P.N)) * kSupFields;
+    dr = sp[kSupDr];
+    dz = sp[kSupDz];
+  }
+  const Pair g = make_pair(rt, dr, dz);
+  double2* xs = P.spec + (size_t)(idx - P.near_lo) * (N + 1);
+  near_spectra(g, P, [xs](int n) -> double2& { return xs[n]; });
+  double m1 = 0.0, m3 = 0.0;
+  for (int n = 0; n < N; ++n) {
+    const double2 v = xs[n];
+    m1 = fmax(m1, fabs(v.x));
+    m3 = fmax(m3, fabs(v.y));
+  }
+  int e = 0;
+  if (m1 > 0.0 && m3 > 0.0) e = ilogb(m1) - ilogb(m3);
+  xs[N] = make_double2((double)e, 0.0);
+}
+
+// One workgroup = TP pairs (TP = max(1, 256 / N)), all L/2 + 1 = N + 1
+// azimuth samples of their nine integrands resident in LDS.
+template <bool NEAR, bool K1C>
+__global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int logTP, int logN, int n_items, int ntile) {
+  const int TP = 1 << logTP;
+  extern __shared__ double2 smem2[];
+  const int N = 1 << logN, H = N / 2, L = 2 * N;
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD one
+  // contiguous range of tiles, so neighbouring sources are written from one L2
+  const int per = (n_items + 7) / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= n_items) return;
+  const int stride = seq_stride(N), stride2 = seq_stride(2 * N);
+  double2* tw = smem2;                 // [N]: e^{-2 pi i k / 2N}
+  double2* cs = tw + N;                // [N/2 + 1] (cos, sin)(pi j / N)
+  double* s2 = reinterpret_cast<double*>(cs + H + 1);  // [N + 1] sin^2(pi j / 2N)
+  double2* geo2 = reinterpret_cast<double2*>(s2 + N + 2);  // [TP][3]: (rt, dr), (dz, flag), (1/sigma, -)
+  double2* f1 = geo2 + 3 * TP;         // [9 TP]
+  double2* S = f1 + 10 * TP;           // [TP][9][stride]
+  double2* XS = S + (size_t)TP * kTypes * stride;  // NEAR: [TP][stride2]
+  int* tgt = reinterpret_cast<int*>(NEAR ? XS + (size_t)TP * stride2 : XS);  // [TP] t, [TP] src
   int* srcs = tgt + TP;
 
-  const int tid = threadIdx.x;
-  for (int i = tid; i < L; i += kThreads) cos_tab[i] = cospi(2.0 * i / L);
-  for (int i = tid; i <= L / 2; i += kThreads) {
-    double s = sinpi((double)i / L);
-    s2_tab[i] = s * s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kThreads / 64;
+  {
+    // the plan's azimuth tables: N + N/2 + 1 complex, then N + 2 doubles,
+    // laid out as in LDS
+    const int nt2 = N + H + 1 + (N + 2) / 2;
+    for (int i = tid; i < nt2; i += kThreads) tw[i] = P.tabs[i];
   }
-  // pairs of this tile
   if (tid < TP) {
     int t, src;
     bool ok;
     if (NEAR) {
-      long long idx = (long long)P.near_lo + (long long)blockIdx.x * TP + tid;
+      const long long idx = (long long)P.near_lo + (long long)item * TP + tid;
       ok = idx < P.near_hi;
-      int2 pr = ok ? P.near[idx] : make_int2(P.t0, 0);
+      const int2 pr = ok ? P.near[idx] : make_int2(P.t0, 0);
       t = pr.x;
       src = pr.y;
     } else {
-      t = P.t0 + blockIdx.y;
-      src = blockIdx.x * TP + tid;
+      t = P.t0 + item / ntile;
+      src = (item % ntile) * TP + tid;
       ok = src < P.NS;
     }
-    uint8_t cl = ok ? P.cls[(size_t)t * P.NS + src] : kZero;
-    double rt = P.r[t], dr = 0.0, dz = 0.0;
+    const uint8_t cl = ok ? P.cls[(size_t)t * P.NS + src] : kZero;
+    const double rt = P.r[t];
+    double dr = 0.0, dz = 0.0;
     if (ok) {
       if (src < P.N) {
         dr = P.r[src] - rt;
@@ -376,198 +612,159 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int TP,
         dz = sp[kSupDz];
       }
     }
-    geo[4 * tid + 0] = rt;
-    geo[4 * tid + 1] = dr;
-    geo[4 * tid + 2] = dz;
-    // valid (compute) flag: far kernel computes class kFar, near kernel kNear;
-    // 2 marks a kZero pair to be written as zeros by the far kernel.
+    // flag 1: this kernel computes the pair; 2: a zero pair the far kernel
+    // writes as zeros; 0: nothing to write here
     double flag = 0.0;
     if (ok) {
       if (NEAR) flag = (cl == kNear) ? 1.0 : 0.0;
       else flag = (cl == kFar) ? 1.0 : (cl == kZero ? 2.0 : 0.0);
     }
-    geo[4 * tid + 3] = flag;
+    geo2[3 * tid] = make_double2(rt, dr);
+    geo2[3 * tid + 1] = make_double2(dz, flag);
+    // near pairs: 1/(2 pi) for the synthesized 1/rho and 1/(2 pi sigma) for
+    // 1/rho^3, sigma = 2^e the scaling applied before the shared transform
+    double isig = 0.15915494309189535;
+    if (NEAR && flag == 1.0) {
+      const long long idx = (long long)P.near_lo + (long long)item * TP + tid;
+      isig = ldexp(isig, -(int)P.spec[(size_t)(idx - P.near_lo) * (N + 1) + N].x);
+    }
+    geo2[3 * tid + 2] = make_double2(isig, 0.0);
     tgt[tid] = t;
     srcs[tid] = src;
   }
   __syncthreads();
-  if (!NEAR) {
-    // skip tiles without work; write zeros for kZero pairs
-    bool any = false;
-    for (int p = 0; p < TP; ++p) any |= (geo[4 * p + 3] != 0.0);
-    if (!any) return;
-  }
-  if (NEAR && tid < TP && geo[4 * tid + 3] == 1.0) {
-    Pair g = make_pair(geo[4 * tid], geo[4 * tid + 1], geo[4 * tid + 2]);
-    near_spectra(g, P, Xh + (size_t)tid * 2 * (Mq + 1), Xh + (size_t)tid * 2 * (Mq + 1) + (Mq + 1));
-  }
-  __syncthreads();
+  bool any = false;
+  for (int p = 0; p < TP; ++p) any |= (geo2[3 * p + 1].y != 0.0);
+  if (!any) return;  // uniform: every thread read the same flags
 
-  // accumulator role
-  const int q = tid / TP;      // 0 .. Q-1 (tid >= Q*TP: idle in accumulation)
-  const int pp = tid % TP;
-  const int par = q & 1;
-  const int grp = q >> 1;
-  const bool acc_active = q < Q;
-  double acc[kSeq][MB];
-#pragma unroll
-  for (int k = 0; k < kSeq; ++k)
-#pragma unroll
-    for (int i = 0; i < MB; ++i) acc[k][i] = 0.0;
+  if (NEAR) {
+    // band-limited 1/rho, 1/rho^3 at every azimuth sample: the cosine series
+    // of their Legendre-Q spectra (scratch, written by near_spectra_kernel),
+    // one transform of the even extension of length 2N per pair.  The two
+    // spectra share it; next to a source the 1/rho^3 spectrum is 1e9 or more
+    // times the 1/rho one, and its rounding would swamp the latter, so it
+    // enters scaled to the same size by a power of two (exact).
+    for (int e = tid; e < (TP << (logN + 1)); e += kThreads) {
+      const int p = e >> (logN + 1), j = e & (2 * N - 1);
+      const int n = j <= N ? j : 2 * N - j;
+      const double2* xs = P.spec + ((size_t)item * TP + p) * (N + 1);
+      double2 v = make_double2(0.0, 0.0);
+      if (n < N && geo2[3 * p + 1].y == 1.0) {
+        v = xs[n];
+        v.y = ldexp(v.y, (int)xs[N].x);
+      }
+      const unsigned rj = __brev((unsigned)j) >> (31 - logN);
+      XS[(size_t)p * stride2 + lpos((int)rj)] = v;
+    }
+    __syncthreads();
+    dct_fft(Seqs{XS, stride2, TP}, logN + 1, tw, 1, tid, kThreads);
+  }
 
+  // samples: one thread per (pair, azimuth j = 0..N); phi_j and pi - phi_j
+  // share the tables (cos(pi - phi) = -cos phi)
   const double k0 = P.k0;
   const cd k1 = mk(P.k1r, P.k1i);
-  const int nchunks = (Lq + 1 + JC - 1) / JC;
-  for (int ch = 0; ch < nchunks; ++ch) {
-    // sampling: task = jj * TP + p
-    for (int task = tid; task < JC * TP; task += kThreads) {
-      int p = task % TP, jj = task / TP;
-      int j = ch * JC + jj;
-      double* eo = EO + ((size_t)jj * TP + p) * kEO;
-      bool live = (j <= Lq) && (geo[4 * p + 3] == 1.0);
-      if (!live) {
-        for (int k = 0; k < 2 * kSeq; ++k) eo[k] = 0.0;
-        continue;
-      }
-      Pair g = make_pair(geo[4 * p], geo[4 * p + 1], geo[4 * p + 2]);
-      int jb = L / 2 - j;  // mirror index: phi_jb = pi - phi_j
-      double X1a, X3a, X1b, X3b;
-      if (NEAR) {
-        const double* x1 = Xh + (size_t)p * 2 * (Mq + 1);
-        const double* x3 = x1 + (Mq + 1);
-        double e1 = x1[0], o1 = 0.0, e3 = x3[0], o3 = 0.0;
-        for (int n = 1; n <= Mq; ++n) {
-          double cs = 2.0 * cos_tab[(n * j) & (L - 1)];
-          if (n & 1) {
-            o1 = fma(x1[n], cs, o1);
-            o3 = fma(x3[n], cs, o3);
-          } else {
-            e1 = fma(x1[n], cs, e1);
-            e3 = fma(x3[n], cs, e3);
-          }
-        }
-        const double i2pi = 0.15915494309189535;  // 1/(2 pi)
-        X1a = (e1 + o1) * i2pi;
-        X1b = (e1 - o1) * i2pi;
-        X3a = (e3 + o3) * i2pi;
-        X3b = (e3 - o3) * i2pi;
-      } else {
-        double ra = sqrt(g.d2 + 4.0 * g.rt * g.rs * s2_tab[j]);
-        double rb = sqrt(g.d2 + 4.0 * g.rt * g.rs * s2_tab[jb]);
-        X1a = 1.0 / ra;
-        X3a = X1a * X1a * X1a;
-        X1b = 1.0 / rb;
-        X3b = X1b * X1b * X1b;
-      }
-      double fa[kSeq], fb[kSeq];
-      sample<NEAR, K1C>(g, s2_tab[j], cos_tab[j], X1a, X3a, k0, k1, fa);
-      if (j == Lq) {
-#pragma unroll
-        for (int k = 0; k < kSeq; ++k) {
-          eo[k] = 2.0 * fa[k];
-          eo[kSeq + k] = 0.0;
-        }
-      } else {
-        sample<NEAR, K1C>(g, s2_tab[jb], cos_tab[jb], X1b, X3b, k0, k1, fb);
-        double w = (j == 0) ? 1.0 : 2.0;
-#pragma unroll
-        for (int k = 0; k < kSeq; ++k) {
-          eo[k] = w * (fa[k] + fb[k]);
-          eo[kSeq + k] = w * (fa[k] - fb[k]);
-        }
-      }
+  const int ntask = TP * (N + 1);
+  for (int task = tid; task < ntask; task += kThreads) {
+    const int p = task / (N + 1), j = task - p * (N + 1);
+    if (geo2[3 * p + 1].y != 1.0) continue;
+    const Pair g = make_pair(geo2[3 * p].x, geo2[3 * p].y, geo2[3 * p + 1].x);
+    double X1, X3;
+    if (NEAR) {
+      const double2 xl = XS[(size_t)p * stride2 + lpos(j)];
+      X1 = xl.x * 0.15915494309189535;  // 1/(2 pi)
+      X3 = xl.y * geo2[3 * p + 2].x;
+    } else {
+      const double rho = sqrt(g.d2 + 4.0 * g.rt * g.rs * s2[j]);
+      X1 = 1.0 / rho;
+      X3 = X1 * X1 * X1;
     }
-    __syncthreads();
-    if (acc_active) {
-      int jmax = min(JC, Lq + 1 - ch * JC);
-      for (int jj = 0; jj < jmax; ++jj) {
-        int j = ch * JC + jj;
-        const double* v = EO + ((size_t)jj * TP + pp) * kEO + par * kSeq;
-        double cs[MB];
+    const double cphi = j <= H ? cs[j].x : -cs[N - j].x;
+    double f[kSeq];
+    sample<NEAR, K1C>(g, s2[j], cphi, X1, X3, k0, k1, f);
+    double2* seq = S + (size_t)p * kTypes * stride;
 #pragma unroll
-        for (int i = 0; i < MB; ++i) {
-          int m = par + 2 * (grp * MB + i);
-          cs[i] = cos_tab[(m * j) & (L - 1)];
-        }
-#pragma unroll
-        for (int k = 0; k < kSeq; ++k) {
-          double vk = v[k];
-#pragma unroll
-          for (int i = 0; i < MB; ++i) acc[k][i] = fma(vk, cs[i], acc[k][i]);
-        }
-      }
-    }
-    __syncthreads();
+    for (int ty = 0; ty < kTypes; ++ty) seq[ty * stride + lpos(j)] = make_double2(f[2 * ty], f[2 * ty + 1]);
   }
-
-  if (!acc_active) return;
-  double flag = geo[4 * pp + 3];
-  if (flag == 0.0) return;
-  const int t = tgt[pp], src = srcs[pp];
-  const double scale = (flag == 1.0) ? 1.0 / (2.0 * L) : 0.0;  // (2pi/L)/(4pi)
-#pragma unroll
-  for (int i = 0; i < MB; ++i) {
-    int m = par + 2 * (grp * MB + i);
-    if (m >= P.M2) continue;
-#pragma unroll
-    for (int ty = 0; ty < kTypes; ++ty) {
-      size_t off = (((size_t)m * kTypes + ty) * P.nt + (t - P.t0)) * P.NS + src;
-      P.out[off] = make_double2(acc[2 * ty][i] * scale, acc[2 * ty + 1][i] * scale);
-    }
+  __syncthreads();
+  const Seqs qs{S, stride, kTypes * TP};
+  dct_pre(qs, logN, cs, f1, wave, lane, nwaves);
+  __syncthreads();
+  dct_fft(qs, logN, tw, 2, tid, kThreads);
+  const double scale = 1.0 / (2.0 * L);  // (2 pi / L) / (4 pi)
+  dct_post(qs, logN, P.M2, scale, f1, wave, lane, nwaves);
+  __syncthreads();
+  // out[m][type][t][src]: consecutive threads take consecutive pairs
+  const int nout = P.M2 * kTypes * TP;
+  for (int e = tid; e < nout; e += kThreads) {
+    const int p = e & (TP - 1), rest = e >> logTP;
+    const int ty = rest % kTypes, m = rest / kTypes;
+    const double flag = geo2[3 * p + 1].y;
+    if (flag == 0.0) continue;
+    const double2 v = (flag == 1.0) ? S[((size_t)p * kTypes + ty) * stride + lpos(m)] : make_double2(0.0, 0.0);
+    P.out[(((size_t)m * kTypes + ty) * P.nt + (tgt[p] - P.t0)) * P.NS + srcs[p]] = v;
   }
 }
 
-template <bool NEAR, bool K1C, int MB>
+template <bool NEAR, bool K1C>
 hipError_t launch_one(const TabParams& P, hipStream_t s) {
-  const int NM = P.M2;
-  const int neven = (NM + 1) / 2;
-  const int G = (neven + MB - 1) / MB;
-  const int Q = 2 * G;
-  const int Mq = P.Mq;
-  auto lds_of = [&](int tp) {
-    const int jc = kThreads / tp;
-    return sizeof(double) * ((size_t)P.L + (P.L / 2 + 2) + 4 * tp + (size_t)jc * tp * kEO +
-                             (NEAR ? (size_t)tp * 2 * (Mq + 1) : 0)) +
-           sizeof(int) * 2 * tp;
-  };
-  // pairs per workgroup: all Q accumulator groups busy, LDS within 112 KB
-  // (threads beyond TP * Q only sample)
-  int TP = kThreads / Q;
-  while (TP > 8 && lds_of(TP) > 112 * 1024) TP /= 2;
-  const int JC = kThreads / TP;
-  const size_t lds = lds_of(TP);
-  if (lds > 112 * 1024) return hipErrorInvalidValue;
-  dim3 grid;
-  if (NEAR) {
-    const int cnt = P.near_hi - P.near_lo;
-    if (cnt <= 0) return hipSuccess;
-    grid = dim3((cnt + TP - 1) / TP, 1, 1);
-  } else {
-    grid = dim3((P.NS + TP - 1) / TP, P.nt, 1);
-  }
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tabulate_kernel<NEAR, K1C, MB>),
+  const int N = P.L / 2;
+  int logN = 0;
+  while ((1 << logN) < N) ++logN;
+  if ((1 << logN) != N || N < 4 || N > 512) return hipErrorInvalidValue;
+  if (P.M2 > N + 1) return hipErrorInvalidValue;
+  const int TP = N >= 256 ? 1 : 256 / N;
+  int logTP = 0;
+  while ((1 << logTP) < TP) ++logTP;
+  const int stride = seq_stride(N);
+  const size_t lds = sizeof(double2) * ((size_t)N + (N / 2 + 1) + 3 * TP + 10 * TP +
+                                        (size_t)TP * kTypes * stride + (NEAR ? (size_t)TP * seq_stride(2 * N) : 0)) +
+                     sizeof(double) * (N + 2) + sizeof(int) * 2 * TP;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tabulate_kernel<NEAR, K1C>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tabulate_kernel<NEAR, K1C, MB>), grid, dim3(kThreads), lds, s, P, TP, JC, Q);
-  return hipGetLastError();
+  if (!NEAR) {
+    const int ntile = (P.NS + TP - 1) / TP;
+    const long long items = (long long)ntile * P.nt;
+    // a dispatch counts work-items in 32 bits
+    if ((items + 7) / 8 * 8 * kThreads >= (1LL << 32)) return hipErrorInvalidValue;
+    const int n_items = (int)items;
+    hipLaunchKernelGGL((tabulate_kernel<NEAR, K1C>), dim3(8 * ((n_items + 7) / 8)), dim3(kThreads), lds, s, P,
+                       logTP, logN, n_items, ntile);
+    return hipGetLastError();
+  }
+  // near pairs in chunks that the spectra scratch holds (a multiple of TP)
+  if (P.near_hi <= P.near_lo) return hipSuccess;
+  if (!P.spec || P.spec_cap < TP) return hipErrorInvalidValue;
+  const int chunk = P.spec_cap / TP * TP;
+  for (int c0 = P.near_lo; c0 < P.near_hi; c0 += chunk) {
+    TabParams Q = P;
+    Q.near_lo = c0;
+    Q.near_hi = c0 + chunk < P.near_hi ? c0 + chunk : P.near_hi;
+    const int cnt = Q.near_hi - Q.near_lo;
+    hipLaunchKernelGGL(near_spectra_kernel, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, Q);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int n_items = (cnt + TP - 1) / TP;
+    hipLaunchKernelGGL((tabulate_kernel<NEAR, K1C>), dim3(8 * ((n_items + 7) / 8)), dim3(kThreads), lds, s, Q,
+                       logTP, logN, n_items, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-template <bool K1C, int MB>
+template <bool K1C>
 hipError_t launch_pair(const TabParams& P, hipStream_t s) {
-  hipError_t e = launch_one<false, K1C, MB>(P, s);
+  hipError_t e = launch_one<false, K1C>(P, s);
   if (e != hipSuccess) return e;
-  return launch_one<true, K1C, MB>(P, s);
+  return launch_one<true, K1C>(P, s);
 }
 
 }  // namespace
 
-// Three modes per accumulating thread: with the file compiled without
-// machine-level loop-invariant hoisting (which otherwise keeps the series and
-// sincos constants live in registers across the chunk loop) the real-k1
-// kernels fit 256 registers, two waves per SIMD.
 hipError_t launch_tabulate(const TabParams& P, hipStream_t s) {
-  if (P.k1i != 0.0) return launch_pair<true, 3>(P, s);
-  return launch_pair<false, 3>(P, s);
+  if (P.k1i != 0.0) return launch_pair<true>(P, s);
+  return launch_pair<false>(P, s);
 }
 
 }  // namespace msv

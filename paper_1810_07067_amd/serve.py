@@ -57,7 +57,7 @@ class Result:
 MAX_WAVES = 32  # plane waves per request
 
 
-def entry_bytes(curve, m_max, precision, n_support):
+def entry_bytes(curve, m_max, fft_len, precision, n_support):
     """HBM held by a cache entry, and the transient extra while it is built.
 
     Held: the caller-owned complex128 matrices of modes 0..M plus everything
@@ -72,7 +72,7 @@ def entry_bytes(curve, m_max, precision, n_support):
     nm = m_max + 1
     vectors = (2 * m_max + 1) * MAX_WAVES
     mats = nm * n * n * 16
-    plan = msv.workspace_bytes(N, n_support, nm, vectors, precision)
+    plan = msv.workspace_bytes(N, n_support, fft_len, nm, vectors, precision)
     io = 2 * vectors * n * 16
     table = (m_max + 2) * 9 * N * (N + n_support) * 16
     return mats + plan + io, table
@@ -120,7 +120,7 @@ class Server:
         if self.key(req) in self.cache:
             return 0, 0
         (ys, _), (ya, _) = self.rules
-        keep, table = entry_bytes(req.curve, req.m_max, self.precision, ys.shape[1] + 2 * ya.size)
+        keep, table = entry_bytes(req.curve, req.m_max, req.fft_len, self.precision, ys.shape[1] + 2 * ya.size)
         return keep, table
 
     def _try_admit(self, req):

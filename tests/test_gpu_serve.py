@@ -38,7 +38,7 @@ def make_requests(seed=11, count=12, qps=200.0):
 def one_body_budget():
     """Room for the largest body while it is built, and for no second one."""
     S = RULES[0][0].shape[1] + 2 * RULES[1][0].size
-    return max(sum(entry_bytes(c, M, 1, S)) for c, _, _, M, L in BODIES.values())
+    return max(sum(entry_bytes(c, M, L, 1, S)) for c, _, _, M, L in BODIES.values())
 
 
 def test_results_alone_equal_results_in_the_mix():

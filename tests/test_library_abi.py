@@ -43,6 +43,7 @@ def _args(curve, **over):
     (dict(eps1=-1.0), "eps1"),
     (dict(eps1=2.0 - 0.1j), "eps1"),
     (dict(fft_len=48), "power of two"),
+    (dict(fft_len=2048), "power of two"),
     (dict(fft_len=32), "too short"),
     (dict(m_max=-1), "m_max"),
 ])
@@ -81,15 +82,17 @@ def test_workspace_bytes_without_a_device(lib):
     """msv_workspace_bytes is a host computation: zero for invalid arguments,
     and for the benchmark spheroid (N = 1024, S = 228, 65 modes, precision 1)
     at least the complex64 factors, pivots and block inverses it must hold."""
-    assert lib.msv_workspace_bytes(0, 228, 65, 0, 1) == 0
-    assert lib.msv_workspace_bytes(1024, 228, 0, 0, 1) == 0
-    assert lib.msv_workspace_bytes(1024, 228, 65, 0, 2) == 0
+    assert lib.msv_workspace_bytes(0, 228, 256, 65, 0, 1) == 0
+    assert lib.msv_workspace_bytes(1024, 228, 256, 0, 0, 1) == 0
+    assert lib.msv_workspace_bytes(1024, 228, 256, 65, 0, 2) == 0
+    assert lib.msv_workspace_bytes(1024, 228, 2048, 65, 0, 1) == 0
     n, nb = 4096, 65
-    b1 = msv.workspace_bytes(1024, 228, nb, 0, 1, lib=lib)
-    b0 = msv.workspace_bytes(1024, 228, nb, 0, 0, lib=lib)
+    b1 = msv.workspace_bytes(1024, 228, 256, nb, 0, 1, lib=lib)
+    b0 = msv.workspace_bytes(1024, 228, 256, nb, 0, 0, lib=lib)
     floor1 = nb * n * n * 8 + nb * n * 8 + nb * (n // 64) * 2 * 64 * 64 * 8
-    assert floor1 < b1 < floor1 + 2.5e9         # + LU planes (33.5 MB per mode) and geometry
+    # + LU planes (33.5 MB per mode), the spectra scratch (65536 x 129 x 16 B) and geometry
+    assert floor1 < b1 < floor1 + 2.7e9
     assert b0 < b1                              # precision 0 factors in the caller's matrices
     vec = 129 * 8
-    bs = msv.workspace_bytes(1024, 228, nb, vec, 1, lib=lib)
+    bs = msv.workspace_bytes(1024, 228, 256, nb, vec, 1, lib=lib)
     assert bs - b1 >= vec * n * (3 * 16 + 2 * 8)  # solve workspace

@@ -23,18 +23,18 @@ def test_entry_bytes_counts_matrices_plan_workspace_and_table():
     c = geometry.sphere(4)
     N, n, M = c.n, 4 * c.n, 4
     vec = (2 * M + 1) * 32
-    keep, table = entry_bytes(c, M, 1, S)
-    plan = msv.workspace_bytes(N, S, M + 1, vec, 1)
+    keep, table = entry_bytes(c, M, 64, 1, S)
+    plan = msv.workspace_bytes(N, S, 64, M + 1, vec, 1)
     assert keep == 5 * n * n * 16 + plan + 2 * vec * n * 16
     assert plan > 5 * n * n * 8 + vec * n * 64  # complex64 factors + solve workspace
     assert table == 6 * 9 * N * (N + S) * 16
-    keep0, _ = entry_bytes(c, M, 0, S)
-    assert keep0 == 5 * n * n * 16 + msv.workspace_bytes(N, S, M + 1, vec, 0) + 2 * vec * n * 16 < keep
+    keep0, _ = entry_bytes(c, M, 64, 0, S)
+    assert keep0 == 5 * n * n * 16 + msv.workspace_bytes(N, S, 64, M + 1, vec, 0) + 2 * vec * n * 16 < keep
 
 
 def test_admission_hits_and_lru_eviction():
     a, b = geometry.sphere(4), geometry.spheroid(4, 2.0)
-    keep, table = entry_bytes(a, 4, 1, S)
+    keep, table = entry_bytes(a, 4, 64, 1, S)
     srv = Server(rules=RULES, hbm_budget=keep + table + keep // 2, slots=2)
     e1, built1, t1 = srv._try_admit(_req(0, a, "a"))
     assert built1 and srv.used == keep + table
