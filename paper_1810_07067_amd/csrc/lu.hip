@@ -1131,16 +1131,18 @@ __global__ __launch_bounds__(256) void split_planes(Mats<float2> B, int r0, int 
 // of the complex product (re = Ar Br - Ai Bi, im = Ar Bi + Ai Br; the minus
 // sign flips the sign bits of the Bi operands) and each as hi hi + hi lo +
 // lo hi: 12 bf16 MFMAs per complex product, into two accumulators instead of
-// the three of 3M.  Each wave computes 64 x 64 (4 x 4 MFMA blocks).  K chunks
-// of 32 go through two LDS buffers, each 4 planes of A and 4 of B as
-// [128][32] bf16 rows with the 16-byte quarters of a row permuted by bits 2-3
-// of the row (q ^ (r >> 2 & 3)): the 16-byte reads of 8 consecutive lanes
-// (8 rows, one quarter) and the writes of 8 (2 rows, 4 quarters) fall on
-// distinct banks without padding.  Chunk c + 1 is staged while chunk c's
-// products run, one barrier per chunk; the registers freed by the two
-// accumulators hold two more chunks in flight (8 16-byte pieces of A and 8 of
-// B per thread and chunk), so each chunk's loads have two chunks of products
-// to arrive.  128 KB of dynamic LDS; one workgroup per CU.
+// the three of 3M.  512 threads: wave w computes rows 64 (w / 4) .. + 64 and
+// columns 32 (w % 4) .. + 32 of the tile (4 x 2 MFMA blocks), so two waves
+// share each SIMD and one's MFMAs issue while the other waits on LDS.  K
+// chunks of 32 go through two LDS buffers, each 4 planes of A and 4 of B as
+// [128][32] bf16 rows with the 16-byte quarters of row r permuted as
+// q ^ (r >> 1 & 3).  The chunks move from memory straight into LDS
+// (global_load_lds_dwordx4, one 1 KB block of 16 rows per wave instruction,
+// each lane fetching the quarter that belongs at its slot), so no register
+// holds a chunk in flight: chunk c + 1 is issued before chunk c's products and
+// waited for after them, one barrier per chunk.  A wave reads its A rows and
+// B columns of a chunk from LDS once, every operand of the chunk's 96 MFMAs in
+// registers together.  128 KB of dynamic LDS; one workgroup per CU.
 constexpr int kBT = 128;
 constexpr int kChunkElems = 2 * kPlanes * kBT * 32;  // one LDS buffer: A then B
 constexpr size_t kBfLds = 2 * kChunkElems * sizeof(__bf16);
@@ -1173,9 +1175,9 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
-__global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0, int rend, int c0, int cend, int k0,
-                                                          int K, const __bf16* ws, size_t ws_stride, int RA,
-                                                          int RB) {
+__global__ __launch_bounds__(512) void gemm_update_planes(Mats<float2> B, int r0, int rend, int c0, int cend,
+                                                           int k0, int K, const __bf16* ws, size_t ws_stride,
+                                                           int RA, int RB) {
   using C4 = Mfma<float>::C4;
   extern __shared__ __attribute__((aligned(16))) __bf16 lds_bf[];
   int bx, by, bz;
@@ -1190,134 +1192,106 @@ __global__ __launch_bounds__(256) void gemm_update_planes(Mats<float2> B, int r0
   float2* M = mz.a;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
   const int li = lane & 15, lq = lane >> 4;
-  C4 tre[4][4], tim[4][4];
+  C4 tre[4][2], tim[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 2; ++b) {
       tre[a][b] = C4{0, 0, 0, 0};
       tim[a][b] = C4{0, 0, 0, 0};
     }
-  // piece v of a chunk: plane v / 2, row 64 (v % 2) + tid / 4, quarter tid % 4;
-  // global addresses a uniform base per piece plus one 32-bit lane offset
-  const int sr = tid >> 2, sq = tid & 3;
-  const unsigned lofs = (unsigned)(sr * 32 + 8 * sq);
   const __bf16* wa = global_ptr(ws + bz * ws_stride) + (size_t)by * kBT * 32;
   const __bf16* wb = global_ptr(ws + bz * ws_stride) + (size_t)kPlanes * RA * K + (size_t)bx * kBT * 32;
-  // LDS element offsets (within a buffer) of this thread's pieces and reads
-  const int st_ofs = sr * 32 + 8 * (sq ^ ((sr >> 2) & 3));
-  const int rd_ofs = li * 32 + 8 * (lq ^ ((li >> 2) & 3));
-  bf16x8 ra0[8], rb0[8], ra1[8], rb1[8];
-  auto fetch = [&](int c, bf16x8(&ra)[8], bf16x8(&rb)[8]) {
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const __bf16* pa = wa + ((size_t)(kPlanes * c + (v >> 1)) * RA + 64 * (v & 1)) * 32;
-      const __bf16* pb = wb + ((size_t)(kPlanes * c + (v >> 1)) * RB + 64 * (v & 1)) * 32;
-      ra[v] = *reinterpret_cast<const bf16x8*>(pa + lofs);
-      rb[v] = *reinterpret_cast<const bf16x8*>(pb + lofs);
-    }
-  };
-  auto stage = [&](const bf16x8(&ra)[8], const bf16x8(&rb)[8], int buf) {
-    __bf16* x = lds_bf + buf * kChunkElems + st_ofs;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const int o = ((v >> 1) * kBT + 64 * (v & 1)) * 32;
-      *reinterpret_cast<bf16x8*>(x + o) = ra[v];
-      *reinterpret_cast<bf16x8*>(x + kPlanes * kBT * 32 + o) = rb[v];
-    }
-  };
+  const int rd_ofs = li * 32 + 8 * (lq ^ ((li >> 1) & 3));
   auto products = [&](int buf) {
     const __bf16* xa = lds_bf + buf * kChunkElems + rd_ofs + wr * 32;
     const __bf16* xb = lds_bf + buf * kChunkElems + kPlanes * kBT * 32 + rd_ofs + wc * 32;
+    bf16x8 arh[4], arl[4], aih[4], ail[4];
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {
-      // part 0: A = Ar (re += Ar Br, im += Ar Bi); part 1: A = Ai (im += Ai Br,
-      // re += Ai (-Bi)).  The A operands stay in registers while the column
-      // blocks of B stream through; consecutive MFMAs rotate over 8
-      // accumulators, so none waits on the one before.
-      bf16x8 ah[4], al[4];
+    for (int a = 0; a < 4; ++a) {
+      arh[a] = *reinterpret_cast<const bf16x8*>(xa + (0 * kBT + 16 * a) * 32);
+      arl[a] = *reinterpret_cast<const bf16x8*>(xa + (1 * kBT + 16 * a) * 32);
+      aih[a] = *reinterpret_cast<const bf16x8*>(xa + (2 * kBT + 16 * a) * 32);
+      ail[a] = *reinterpret_cast<const bf16x8*>(xa + (3 * kBT + 16 * a) * 32);
+    }
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        ah[a] = *reinterpret_cast<const bf16x8*>(xa + ((2 * part) * kBT + 16 * a) * 32);
-        al[a] = *reinterpret_cast<const bf16x8*>(xa + ((2 * part + 1) * kBT + 16 * a) * 32);
-      }
+    for (int b = 0; b < 2; ++b) {
+      const bf16x8 brh = *reinterpret_cast<const bf16x8*>(xb + (0 * kBT + 16 * b) * 32);
+      const bf16x8 brl = *reinterpret_cast<const bf16x8*>(xb + (1 * kBT + 16 * b) * 32);
+      const bf16x8 bih = *reinterpret_cast<const bf16x8*>(xb + (2 * kBT + 16 * b) * 32);
+      const bf16x8 bil = *reinterpret_cast<const bf16x8*>(xb + (3 * kBT + 16 * b) * 32);
+      const bf16x8 nih = neg8(bih), nil = neg8(bil);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const bf16x8 brh = *reinterpret_cast<const bf16x8*>(xb + (0 * kBT + 16 * b) * 32);
-        const bf16x8 brl = *reinterpret_cast<const bf16x8*>(xb + (1 * kBT + 16 * b) * 32);
-        bf16x8 xh = *reinterpret_cast<const bf16x8*>(xb + (2 * kBT + 16 * b) * 32);
-        bf16x8 xl = *reinterpret_cast<const bf16x8*>(xb + (3 * kBT + 16 * b) * 32);
-        if (part == 1) {
-          xh = neg8(xh);
-          xl = neg8(xl);
-        }
-        C4(&tb)[4][4] = part == 0 ? tre : tim;  // the products with Br
-        C4(&tx)[4][4] = part == 0 ? tim : tre;  // the products with +-Bi
+      for (int a = 0; a < 4; ++a) tre[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], brh, tre[a][b], 0, 0, 0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) tb[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brh, tb[a][b], 0, 0, 0);
+      for (int a = 0; a < 4; ++a) tim[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], bih, tim[a][b], 0, 0, 0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) tx[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], xh, tx[a][b], 0, 0, 0);
+      for (int a = 0; a < 4; ++a) tre[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], brl, tre[a][b], 0, 0, 0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) tb[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], brl, tb[a][b], 0, 0, 0);
+      for (int a = 0; a < 4; ++a) tim[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], bil, tim[a][b], 0, 0, 0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) tx[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], xl, tx[a][b], 0, 0, 0);
+      for (int a = 0; a < 4; ++a) tre[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl[a], brh, tre[a][b], 0, 0, 0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) tb[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], brh, tb[a][b], 0, 0, 0);
+      for (int a = 0; a < 4; ++a) tim[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl[a], bih, tim[a][b], 0, 0, 0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) tx[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], xh, tx[a][b], 0, 0, 0);
-      }
+      for (int a = 0; a < 4; ++a) tim[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih[a], brh, tim[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) tre[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih[a], nih, tre[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) tim[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih[a], brl, tim[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) tre[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih[a], nil, tre[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) tim[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail[a], brh, tim[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) tre[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail[a], nih, tre[a][b], 0, 0, 0);
     }
   };
-  // chunk c is in LDS buffer c % 2; while its products run, chunk c + 1 is
-  // staged into the other buffer from the registers that then take chunk c + 3.
-  // The fetches are unconditional (past the end they repeat the last chunk):
-  // behind a branch, the wait before each staging would also have to cover
-  // the path without them and would wait for every load in flight.
-  const int nc = K / kBK, last = nc - 1;
-  fetch(0, ra0, rb0);
-  fetch(min(1, last), ra1, rb1);
-  stage(ra0, rb0, 0);
-  fetch(min(2, last), ra0, rb0);
+  // wave w moves rows 16 w .. 16 w + 15 of every plane of a chunk from memory
+  // straight into LDS: lane l writes the 16 bytes at row 16 w + l / 4, slot
+  // l % 4, which hold the row's quarter (l % 4) ^ swizzle
+  const int dr = 16 * wave + (lane >> 2), dsl = lane & 3;
+  const unsigned dofs = (unsigned)(dr * 32 + 8 * (dsl ^ ((dr >> 1) & 3)));
+  auto issue = [&](int c, int buf) {
+    __bf16* base = lds_bf + buf * kChunkElems + 16 * wave * 32;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const __bf16* pa = wa + (size_t)(kPlanes * c + v) * RA * 32 + dofs;
+      const __bf16* pb = wb + (size_t)(kPlanes * c + v) * RB * 32 + dofs;
+      __builtin_amdgcn_global_load_lds(pa, base + v * kBT * 32, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(pb, base + (kPlanes + v) * kBT * 32, 16, 0, 0);
+    }
+  };
+  const int nc = K / kBK;
+  float2 cv[4][2][4];
+  issue(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  int c = 0;
-  for (; c + 2 < nc; c += 2) {
-    stage(ra1, rb1, 1);
-    fetch(min(c + 3, last), ra1, rb1);
-    products(0);
-    __syncthreads();
-    stage(ra0, rb0, 0);
-    fetch(min(c + 4, last), ra0, rb0);
-    products(1);
-    __syncthreads();
-  }
-  // one or two chunks left, the first in buffer 0, a second in (ra1, rb1)
-  const bool two = nc - c == 2;
-  if (two) stage(ra1, rb1, 1);
-  // the wave's 64 x 64 block of C is loaded while the last products run, in
-  // one round trip to memory
-  float2 cv[4][4][4];
+  for (int c = 0; c < nc; ++c) {
+    if (c + 1 < nc) issue(c + 1, (c + 1) & 1);
+    if (c == nc - 1) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = tr + wr + 16 * a + 4 * lq + i;
-        const int gc = tc + wc + 16 * b + li;
-        const bool ok = gr < rend && gc < cend;
-        cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
-      }
-  products(0);
-  if (two) {
+          for (int i = 0; i < 4; ++i) {
+            const int gr = tr + wr + 16 * a + 4 * lq + i;
+            const int gc = tc + wc + 16 * b + li;
+            const bool ok = gr < rend && gc < cend;
+            cv[a][b][i] = M[ok ? (size_t)gr * n + gc : 0];
+          }
+    }
+    products(c & 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    products(1);
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gr = tr + wr + 16 * a + 4 * lq + i;
@@ -1376,7 +1350,7 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
       if (attr != hipSuccess) return attr;
       hipLaunchKernelGGL(split_planes, dim3((4 * (RA + RB) + 255) / 256, K / kBK, b.nb), dim3(256), 0, s, b.d, r0, rend, c0,
                          cend, k0, K, b.planes, b.planes_stride, RA, RB);
-      hipLaunchKernelGGL(gemm_update_planes, dim3((RB / kBT) * (RA / kBT) * b.nb), dim3(256), kBfLds, s, b.d, r0,
+      hipLaunchKernelGGL(gemm_update_planes, dim3((RB / kBT) * (RA / kBT) * b.nb), dim3(512), kBfLds, s, b.d, r0,
                          rend, c0, cend, k0, K, b.planes, b.planes_stride, RA, RB);
     } else if (K % kBK == 0)
       hipLaunchKernelGGL(gemm_update_bf, g, dim3(256), 0, s, b.d, r0, rend, c0, cend, k0, K);
