@@ -10,7 +10,16 @@ Equations per target node i (rows 4i..4i+3):
                                              - i w (eps0 N^{k0} - eps1 N^{k1}) M
 
 (eq. mullerrep; the magnetic equation is placed first so that the identity
-terms sit on the diagonal).  The tabulated kernels are g^{k0} and g^{k0} - g^{k1}
+terms sit on the diagonal).  The indirect system (eq. dualmullrep, Section
+2.2) uses the same operators with other weights:
+
+  rows 0,1  i w eps0 (n x H_inc) = -(i w/2)(eps0+eps1) J - i w (eps0 N^{k0} - eps1 N^{k1}) J
+                                    - (eps0/mu0) (K^{k0}-K^{k1}) M
+  rows 2,3  i w mu0 (n x E_inc)  = -(i w/2)(mu0+mu1) M - i w (mu0 N^{k0} - mu1 N^{k1}) M
+                                    + (mu0/eps0) (K^{k0}-K^{k1}) J
+
+(its N terms written with the printed i w (eps1 N^{k1} - eps0 N^{k0}) =
+-i w (eps0 N^{k0} - eps1 N^{k1}), its K terms with K^{k1}-K^{k0} = -(K^{k0}-K^{k1})).  The tabulated kernels are g^{k0} and g^{k0} - g^{k1}
 (with their derivatives), so mu0 N^{k0} - mu1 N^{k1} is formed as
 (mu0 - mu1) N^{k0} + mu1 (N^{k0} - N^{k1}).  N and K act on a tangential
 density a = (a^1, a^2)
@@ -49,7 +58,7 @@ import numpy as np
 from .discretize import neighbours
 
 
-def blocks(tab_m, m, rt, trt, tzt, rs, trs, tzs, k0, k1, omega, eps0, mu0, eps1, mu1):
+def blocks(tab_m, m, rt, trt, tzt, rs, trs, tzs, k0, k1, omega, eps0, mu0, eps1, mu1, formulation="direct"):
     """4x4 kernel blocks for one mode: [4, 4, ...] over the broadcast pair shape.
 
     tab_m: dict with arrays for modes m-1, m, m+1 (indices 0..2) of the nine
@@ -122,18 +131,28 @@ def blocks(tab_m, m, rt, trt, tzt, rs, trs, tzs, k0, k1, omega, eps0, mu0, eps1,
         K[1, b] = Kth
     iw = 1j * omega
     B = np.zeros((4, 4) + K.shape[2:], dtype=complex)
-    # mu0 N^{k0} - mu1 N^{k1} = (mu0 - mu1) N^{k0} + mu1 (N^{k0} - N^{k1})
-    B[0:2, 0:2] = -iw * ((mu0 - mu1) * N0 + mu1 * dN)
-    B[0:2, 2:4] = -K
-    B[2:4, 0:2] = K
-    B[2:4, 2:4] = -iw * ((eps0 - eps1) * N0 + eps1 * dN)
+    if formulation == "direct":
+        # mu0 N^{k0} - mu1 N^{k1} = (mu0 - mu1) N^{k0} + mu1 (N^{k0} - N^{k1})
+        B[0:2, 0:2] = -iw * ((mu0 - mu1) * N0 + mu1 * dN)
+        B[0:2, 2:4] = -K
+        B[2:4, 0:2] = K
+        B[2:4, 2:4] = -iw * ((eps0 - eps1) * N0 + eps1 * dN)
+    elif formulation == "indirect":
+        B[0:2, 0:2] = -iw * ((eps0 - eps1) * N0 + eps1 * dN)
+        B[0:2, 2:4] = -(eps0 / mu0) * K
+        B[2:4, 0:2] = (mu0 / eps0) * K
+        B[2:4, 2:4] = -iw * ((mu0 - mu1) * N0 + mu1 * dN)
+    else:
+        raise ValueError(formulation)
     return B
 
 
-def assemble_mode(curve, sup, table, m, k0, k1, omega, eps0, mu0, eps1, mu1, w, rows=None):
+def assemble_mode(curve, sup, table, m, k0, k1, omega, eps0, mu0, eps1, mu1, w, rows=None,
+                  formulation="direct"):
     """Weighted matrix rows for mode m >= 0: [len(rows)*4, 4N] complex.
 
-    table: [M+2, 9, len(rows), N+S] (rows as in oracle.modal.tabulate).
+    table: [M+2, 9, len(rows), N+S] (rows as in oracle.modal.tabulate);
+    formulation "direct" (eq. mullerrep) or "indirect" (eq. dualmullrep).
     """
     N = curve.n
     order = curve.order
@@ -151,7 +170,7 @@ def assemble_mode(curve, sup, table, m, k0, k1, omega, eps0, mu0, eps1, mu1, w, 
         trs = np.concatenate([tr_nodes, sup.tr[t]])
         tzs = np.concatenate([tz_nodes, sup.tz[t]])
         B = blocks(tab, m, curve.r[t], tr_nodes[t], tz_nodes[t], rs, trs, tzs,
-                   k0, k1, omega, eps0, mu0, eps1, mu1)  # [4, 4, N+S]
+                   k0, k1, omega, eps0, mu0, eps1, mu1, formulation)  # [4, 4, N+S]
         p = t // order
         nearp = [p] + [q for q in (left[p], right[p]) if q >= 0]
         wts = w.copy()
@@ -167,10 +186,14 @@ def assemble_mode(curve, sup, table, m, k0, k1, omega, eps0, mu0, eps1, mu1, w, 
                 continue
             row[:, :, pq * order:(pq + 1) * order] += contrib[:, :, s, None] * sup.lag[t, s][None, None, :]
         # jump terms
-        row[0, 0, t] += 0.5j * omega * (mu0 + mu1)
-        row[1, 1, t] += 0.5j * omega * (mu0 + mu1)
-        row[2, 2, t] += 0.5j * omega * (eps0 + eps1)
-        row[3, 3, t] += 0.5j * omega * (eps0 + eps1)
+        if formulation == "direct":
+            jJ, jM = 0.5j * omega * (mu0 + mu1), 0.5j * omega * (eps0 + eps1)
+        else:
+            jJ, jM = -0.5j * omega * (eps0 + eps1), -0.5j * omega * (mu0 + mu1)
+        row[0, 0, t] += jJ
+        row[1, 1, t] += jJ
+        row[2, 2, t] += jM
+        row[3, 3, t] += jM
         # [4, 4, N] -> rows 4i..4i+3, columns 4j + beta; L2 weighting
         blk = row.transpose(0, 2, 1).reshape(4, 4 * N)
         A[4 * i:4 * i + 4] = blk * (sw[t] / np.repeat(sw, 4))[None, :]

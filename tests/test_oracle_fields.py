@@ -1,0 +1,153 @@
+"""Pins for the indirect formulation and the off-surface fields of the oracle.
+
+* The current-loop field (eq. loop) satisfies Maxwell's equations: central
+  differences of E and H against i w mu1 H and -i w eps1 E.
+* The extinction test of Section 6: the indirect system (eq. dualmullrep)
+  solved with the loop data reproduces the loop field inside the torus of
+  Example 1 (interior_dual representation) and a vanishing field outside
+  (exteriorfield).  Table 1 prints E_error = 2.32e-9 for k0 = 1, k1 = 2; the
+  oracle must stay below it.
+* The extinction theorem for the direct system (eq. mullerrep): with the
+  currents of a plane-wave solve, the exterior representation evaluated inside
+  the body is -E_inc, and the interior representation evaluated outside is 0.
+* Mode parity A_{-m} = D A_m D also for the indirect system.
+A dropped term or a wrong sign in any weight of the indirect blocks, the jump
+terms, the representations or the loop field breaks one of these."""
+import numpy as np
+import pytest
+
+from oracle import assemble, discretize, fields, modal, solve
+from workloads import geometry, incident, rules
+
+
+def _setup(curve, k0, eps1, mu1, M, formulation):
+    (ys, ws), (ya, wa) = rules.load_rules()
+    sup = discretize.support_points(curve, (ys, ws), (ya, wa))
+    omega = k0
+    k1 = omega * np.sqrt(complex(eps1 * mu1))
+    L = 64
+    while not modal.KernelParams(k0, k1, M, L, float(curve.r.max())).valid:
+        L *= 2
+    tab = modal.tabulate(curve, sup, modal.KernelParams(k0, k1, M, L, float(curve.r.max())))
+    w = geometry.gl_weights(curve)
+    mats = [assemble.assemble_mode(curve, sup, tab, m, k0, k1, omega, 1.0, 1.0, eps1, mu1, w,
+                                   formulation=formulation) for m in range(M + 1)]
+    return sup, tab, w, mats, k1, omega
+
+
+def torus_points(rng, P, frac=0.5):
+    """Random points inside the torus r = 2 + cos t, z = 0.5 sin t (within
+    `frac` of its cross-section)."""
+    rho = frac * np.sqrt(rng.uniform(0, 1, P))
+    ph = rng.uniform(0, 2 * np.pi, P)
+    th = rng.uniform(0, 2 * np.pi, P)
+    rr = 2 + rho * np.cos(ph)
+    zz = 0.5 * rho * np.sin(ph)
+    return np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+
+
+LOOP = dict(center=[0.4, 0.5, 5.0], radius=0.42)  # Section 6
+
+
+@pytest.mark.parametrize("k1", [2.0, 20.0 + 0.5j])
+def test_loop_field_satisfies_maxwell(k1):
+    omega, mu1 = 1.0, 1.3
+    eps1 = k1 * k1 / (omega * omega * mu1)
+    E, H = incident.current_loop(LOOP["center"], LOOP["radius"], k1, omega, mu1)
+    h = 1e-4
+    for x in np.array([[0.3, -0.2, 0.1], [1.5, 0.4, -0.6]]):
+        def curl(F):
+            d = np.zeros((3, 3), dtype=complex)  # d[i, j] = d F_j / d x_i
+            for i in range(3):
+                e = np.zeros(3)
+                e[i] = h
+                d[i] = (-F(x + 2 * e) + 8 * F(x + e) - 8 * F(x - e) + F(x - 2 * e)) / (12 * h)
+            return np.array([d[1, 2] - d[2, 1], d[2, 0] - d[0, 2], d[0, 1] - d[1, 0]])
+        cE, cH = curl(E), curl(H)
+        assert np.linalg.norm(cE - 1j * omega * mu1 * H(x)) < 1e-7 * np.linalg.norm(cE)
+        assert np.linalg.norm(cH + 1j * omega * eps1 * E(x)) < 1e-7 * np.linalg.norm(cH)
+
+
+@pytest.fixture(scope="module", params=[(4.0, 1.0), (2.0, 2.0)], ids=["dielectric", "magnetic"])
+def torus_extinction(request):
+    """Table 1, first row (k0 = 1, k1 = 2, N_f = 13), as eps1 = 4 and as
+    eps1 = mu1 = 2 (the same k1 with magnetic contrast, which exercises the
+    mu1/mu0 weights)."""
+    curve = geometry.torus(8)
+    (eps1, mu1), k0, M = request.param, 1.0, 13
+    sup, tab, w, mats, k1, omega = _setup(curve, k0, eps1, mu1, M, "indirect")
+    rhs = incident.loop_rhs_modes(curve, LOOP["center"], LOOP["radius"], k1, omega, mu1, -M, M)
+    x = solve.solve_modes(mats, w, rhs, -M, M)
+    return dict(curve=curve, w=w, x=x, M=M, k0=k0, k1=k1, omega=omega, eps1=eps1, mu1=mu1, rhs=rhs)
+
+
+def e_error(E, H, Er, Hr):
+    """Relative l2 error of the electric and magnetic fields together (the
+    E_error of Section 6)."""
+    num = np.linalg.norm(E - Er) ** 2 + np.linalg.norm(H - Hr) ** 2
+    return np.sqrt(num / (np.linalg.norm(Er) ** 2 + np.linalg.norm(Hr) ** 2))
+
+
+def test_extinction_torus_interior(torus_extinction):
+    c = torus_extinction
+    assert np.abs(c["rhs"][[0, -1]]).max() < 1e-15 * np.abs(c["rhs"]).max()  # N_f = 13 resolves the data
+    pts = torus_points(np.random.default_rng(3), 6)
+    E, H = fields.fields(c["curve"], c["w"], c["x"][:, 0], -c["M"], pts, c["k0"], c["k1"], c["omega"],
+                         1.0, 1.0, c["eps1"], c["mu1"], "interior", "indirect")
+    El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], c["k1"], c["omega"], c["mu1"])
+    err = e_error(E, H, El(pts), Hl(pts))
+    assert err < 2.32e-9, err
+
+
+def test_extinction_torus_exterior_vanishes(torus_extinction):
+    c = torus_extinction
+    pts = np.array([[0.0, 0.0, 0.3], [4.0, 0.5, 0.2], [-3.5, -1.0, 1.2], [0.5, 0.2, -1.5]])
+    E, H = fields.fields(c["curve"], c["w"], c["x"][:, 0], -c["M"], pts, c["k0"], c["k1"], c["omega"],
+                         1.0, 1.0, c["eps1"], c["mu1"], "exterior", "indirect")
+    El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], c["k1"], c["omega"], c["mu1"])
+    ref = torus_points(np.random.default_rng(3), 6)
+    scale = np.sqrt(np.linalg.norm(El(ref)) ** 2 + np.linalg.norm(Hl(ref)) ** 2)
+    assert np.sqrt(np.linalg.norm(E) ** 2 + np.linalg.norm(H) ** 2) < 5e-9 * scale
+
+
+def test_direct_extinction_theorem_sphere():
+    curve = geometry.sphere(8)
+    k0, eps1, mu1, M = 1.0, 2.25, 1.0, 16
+    sup, tab, w, mats, k1, omega = _setup(curve, k0, eps1, mu1, M, "direct")
+    d, p = incident.tilted_direction(30.0)
+    rhs = incident.rhs_modes(curve, [(d, p)], k0, -M, M)
+    x = solve.solve_modes(mats, w, rhs, -M, M)
+    Ei, Hi = incident.plane_wave(d, p, k0)
+    inside = np.array([[0.1, 0.2, -0.1], [-0.3, 0.1, 0.35], [0.0, -0.4, 0.2]])
+    E, H = fields.fields(curve, w, x[:, 0], -M, inside, k0, k1, omega, 1.0, 1.0, eps1, mu1, "exterior")
+    # this 8-panel sphere reaches the Mie series to 1.7e-9, a floor set by
+    # kernel rounding amplified next to the poles (test_oracle_system); the
+    # extinction residual measures 1.2e-9 and 2e-10 (outside)
+    assert e_error(E, H, -Ei(inside), -Hi(inside)) < 3e-9
+    outside = np.array([[2.0, 0.5, -0.3], [-1.0, -1.5, 1.2], [0.2, 0.1, -2.5]])
+    E, H = fields.fields(curve, w, x[:, 0], -M, outside, k0, k1, omega, 1.0, 1.0, eps1, mu1, "interior")
+    scale = np.sqrt(np.linalg.norm(Ei(outside)) ** 2 + np.linalg.norm(Hi(outside)) ** 2)
+    assert np.sqrt(np.linalg.norm(E) ** 2 + np.linalg.norm(H) ** 2) < 1e-9 * scale
+
+
+def test_indirect_mode_parity():
+    curve = geometry.sphere(4)
+    (ys, ws), (ya, wa) = rules.load_rules()
+    sup = discretize.support_points(curve, (ys, ws), (ya, wa))
+    k1 = 1.5 + 0.1j
+    tab = modal.tabulate(curve, sup, modal.KernelParams(1.0, k1, 6, 64, 1.0))
+    w = geometry.gl_weights(curve)
+
+    class Even:  # g_{-m} = g_m: index the table by |m|
+        def __init__(self, t):
+            self.t = t
+
+        def __getitem__(self, key):
+            idx, *rest = key
+            return self.t[([abs(i) for i in idx], *rest)]
+    D = solve.parity_diag(curve.n)
+    for m in (1, 4):
+        args = (1.0, k1, 1.0, 1.0, 1.0, k1 * k1, 1.0, w)  # eps1 = k1^2 at omega = 1
+        Ap = assemble.assemble_mode(curve, sup, tab, m, *args, formulation="indirect")
+        An = assemble.assemble_mode(curve, sup, Even(tab), -m, *args, formulation="indirect")
+        assert np.max(np.abs(An - D[:, None] * Ap * D[None, :])) < 1e-14 * np.max(np.abs(Ap))
