@@ -85,6 +85,16 @@ typedef struct {
                                 complex128 iterative refinement */
   double ir_tol;             /* precision 1: stop when ||b - A x|| <= ir_tol ||b|| */
   int32_t ir_max_iter;       /* precision 1: at most this many refinement steps */
+  int32_t formulation;       /* 0: the direct system (eq. mullerrep), whose
+                                currents are J = n x H, M = n x E; 1: the
+                                indirect system (eq. dualmullrep, Section 2.2),
+                                whose currents generate the exterior field by
+                                eq. exteriorfield and the interior one by
+                                eq. interior_dual.  Rows 4j, 4j+1 of every
+                                right-hand side carry i w mu0 (n x H_inc)
+                                (direct) or i w eps0 (n x H_inc) (indirect),
+                                rows 4j+2, 4j+3 i w eps0 (n x E_inc) or
+                                i w mu0 (n x E_inc), in (t, e_theta) components */
 } msv_desc;
 
 /* Validate the inputs, upload the geometry, build the near-panel support
@@ -215,6 +225,39 @@ msv_status msv_solve(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_rhs,
 msv_status msv_solve_noalloc(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_rhs,
                              const msv_c128 *d_rhs, msv_c128 *d_x, void *stream);
 size_t msv_solve_noalloc_max_bytes(void);
+
+/* Fields from the currents of msv_solve (Sections 2.1, 2.2 and 6).  d_x holds
+ * the modes m_lo..m_hi (-M <= m_lo <= m_hi <= M) of n_vec solutions,
+ * [m - m_lo][v][4N] as msv_solve returns them (J^1, J^2, M^1, M^2 per node).
+ * Both calls synthesize the currents on a surface grid -- the N nodes times T
+ * equispaced azimuths, weighted by the Gauss-Legendre arclength weights and
+ * the trapezoid rule in theta -- in a stream-ordered workspace of
+ * n_vec * N * T * 64 + T * 16 bytes allocated and freed by the call
+ * (hipMallocAsync; MSV_ENOMEM if that fails), then reduce one sum over the
+ * grid per output on the device.  Outputs are complex, device, row-major.
+ *
+ * msv_far_field: the far-field pattern of the exterior field (eq.
+ * farfieldform, derived from eq. exteriorfield as |x| -> infinity, with the M
+ * term that the printed form leaves out):
+ *   E_inf(xhat) = (1/(4 pi)) [i k0 xhat x Mt - i omega mu0 xhat x (xhat x Jt)],
+ *   Jt = int_Gamma e^{-i k0 xhat.y} J(y) da(y), Mt likewise,
+ * so that the scattered field is e^{i k0 |x|}/|x| E_inf(x/|x|) + O(|x|^-2).
+ * d_dirs [n_dirs][3] unit vectors; d_out [n_vec][n_dirs][3].
+ * T = floor(2 (max |m| + k0 r_max) + 64).
+ *
+ * msv_fields: E and H at points off the surface.  region 0: points outside
+ * the body, the scattered field of eq. exteriorfield; region 1: points inside,
+ * the field of eq. interiorfield (direct system) or eq. interior_dual
+ * (indirect system, msv_desc.formulation).  The caller states the region;
+ * the quadrature is accurate for points whose distance to the surface is not
+ * small against the nearby panels.  d_points [n_points][3]; d_E, d_H
+ * [n_vec][n_points][3].  T = floor(4 (max |m| + |k| r_max) + 128) with k the
+ * region's wavenumber. */
+msv_status msv_far_field(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128 *d_x,
+                         int32_t n_dirs, const double *d_dirs, msv_c128 *d_out, void *stream);
+msv_status msv_fields(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128 *d_x,
+                      int32_t n_points, const double *d_points, int32_t region, msv_c128 *d_E,
+                      msv_c128 *d_H, void *stream);
 
 /* Iterations used by the last precision-1 msv_solve (max over modes). */
 int32_t msv_last_ir_iterations(const msv_plan *plan);

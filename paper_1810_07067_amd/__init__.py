@@ -23,7 +23,8 @@ EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nod
            "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations",
            "msv_batch_create", "msv_batch_factor", "msv_batch_destroy", "msv_batch_last_error",
            "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes",
-           "msv_tabulate_rows", "msv_assemble_rows", "msv_solve_noalloc", "msv_solve_noalloc_max_bytes"]
+           "msv_tabulate_rows", "msv_assemble_rows", "msv_solve_noalloc", "msv_solve_noalloc_max_bytes",
+           "msv_far_field", "msv_fields"]
 
 
 class MsvError(RuntimeError):
@@ -50,7 +51,7 @@ class Rules(ctypes.Structure):
 class Desc(ctypes.Structure):
     _fields_ = [("k0", ctypes.c_double), ("eps0", c128), ("mu0", c128), ("eps1", c128), ("mu1", c128),
                 ("m_max", ctypes.c_int32), ("fft_len", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int32)]
+                ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int32), ("formulation", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,6 +88,11 @@ def load_library(path: str = LIB_PATH):
     lib.msv_solve.restype = ctypes.c_int
     lib.msv_solve_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.msv_solve_noalloc.restype = ctypes.c_int
+    lib.msv_far_field.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P, P]
+    lib.msv_far_field.restype = ctypes.c_int
+    lib.msv_fields.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P,
+                               ctypes.c_int32, P, P, P]
+    lib.msv_fields.restype = ctypes.c_int
     lib.msv_solve_noalloc_max_bytes.argtypes = []
     lib.msv_solve_noalloc_max_bytes.restype = ctypes.c_size_t
     lib.msv_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_int32,
@@ -130,7 +136,7 @@ class Plan:
 
     def __init__(self, r, z, nr, nz, dsdu, n_panels, closed, self_u, self_w, adj_u, adj_w,
                  k0, eps1, mu1=1.0, eps0=1.0, mu0=1.0, m_max=16, fft_len=64, precision=0,
-                 ir_tol=1e-13, ir_max_iter=10, stream=None, lib=None):
+                 ir_tol=1e-13, ir_max_iter=10, formulation=0, stream=None, lib=None):
         self.lib = lib or load_library()
         f64 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64))
         self._keep = [f64(a) for a in (r, z, nr, nz, dsdu, self_u, self_w, adj_u, adj_w)]
@@ -140,7 +146,7 @@ class Plan:
         ns = a[5].size // 16
         rules = Rules(int(ns), ptr(a[5]), ptr(a[6]), int(a[7].size), ptr(a[7]), ptr(a[8]))
         desc = Desc(float(k0), _c(eps0), _c(mu0), _c(eps1), _c(mu1), int(m_max), int(fft_len),
-                    int(precision), float(ir_tol), int(ir_max_iter))
+                    int(precision), float(ir_tol), int(ir_max_iter), int(formulation))
         self._h = ctypes.c_void_p()
         st = self.lib.msv_plan_create(ctypes.byref(self._h), ctypes.byref(curve), ctypes.byref(rules),
                                       ctypes.byref(desc), None)
@@ -151,6 +157,7 @@ class Plan:
         self.S = self.lib.msv_num_support(self._h)
         self.n = self.lib.msv_matrix_order(self._h)
         self.precision = int(precision)
+        self.formulation = int(formulation)
         self._factored = None
 
     def close(self):
@@ -273,6 +280,39 @@ class Plan:
                                                ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                                _stream_handle(stream)))
         return out
+
+
+    def far_field(self, m_lo, m_hi, x, dirs, stream=None):
+        """msv_far_field: E_inf [n_vec, n_dirs, 3] of the currents x
+        [m_hi - m_lo + 1, n_vec, 4N] at unit directions dirs [n_dirs, 3]."""
+        import torch
+        nm = m_hi - m_lo + 1
+        assert x.dtype == torch.complex128 and x.is_contiguous() and x.shape[0] == nm and x.shape[2] == self.n
+        dirs = torch.as_tensor(dirs, dtype=torch.float64, device=x.device).contiguous()
+        assert dirs.ndim == 2 and dirs.shape[1] == 3
+        out = torch.empty((x.shape[1], dirs.shape[0], 3), dtype=torch.complex128, device=x.device)
+        self._check(self.lib.msv_far_field(self._h, int(m_lo), int(m_hi), int(x.shape[1]),
+                                           ctypes.c_void_p(x.data_ptr()), int(dirs.shape[0]),
+                                           ctypes.c_void_p(dirs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                           _stream_handle(stream)))
+        return out
+
+    def fields(self, m_lo, m_hi, x, points, region, stream=None):
+        """msv_fields: E, H [n_vec, n_points, 3] at points [n_points, 3] of
+        `region` ("exterior" or "interior")."""
+        import torch
+        nm = m_hi - m_lo + 1
+        assert x.dtype == torch.complex128 and x.is_contiguous() and x.shape[0] == nm and x.shape[2] == self.n
+        pts = torch.as_tensor(points, dtype=torch.float64, device=x.device).contiguous()
+        assert pts.ndim == 2 and pts.shape[1] == 3
+        reg = {"exterior": 0, "interior": 1}[region]
+        E = torch.empty((x.shape[1], pts.shape[0], 3), dtype=torch.complex128, device=x.device)
+        H = torch.empty_like(E)
+        self._check(self.lib.msv_fields(self._h, int(m_lo), int(m_hi), int(x.shape[1]),
+                                        ctypes.c_void_p(x.data_ptr()), int(pts.shape[0]),
+                                        ctypes.c_void_p(pts.data_ptr()), reg, ctypes.c_void_p(E.data_ptr()),
+                                        ctypes.c_void_p(H.data_ptr()), _stream_handle(stream)))
+        return E, H
 
 
 class Batch:

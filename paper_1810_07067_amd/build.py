@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsv.so")
-SOURCES = ["plan.hip", "tabulate.hip", "assemble.hip", "lu.hip", "solve.hip", "trsv.hip"]
+SOURCES = ["plan.hip", "tabulate.hip", "assemble.hip", "lu.hip", "solve.hip", "trsv.hip", "fields.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-ffp-contract=fast", "-Wno-unused-command-line-argument"]

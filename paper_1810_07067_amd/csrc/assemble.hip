@@ -7,6 +7,14 @@
 //   rows 0,1:  -i w (mu0 N^{k0} - mu1 N^{k1}) on J,   -(K^{k0} - K^{k1}) on M
 //   rows 2,3:   (K^{k0} - K^{k1}) on J,   -i w (eps0 N^{k0} - eps1 N^{k1}) on M
 //
+// or, for the indirect system (eq. dualmullrep, Section 2.2), the same
+// operators with the materials exchanged and other weights:
+//
+//   rows 0,1:  -i w (eps0 N^{k0} - eps1 N^{k1}) on J,  -(eps0/mu0)(K^{k0} - K^{k1}) on M
+//   rows 2,3:   (mu0/eps0)(K^{k0} - K^{k1}) on J,   -i w (mu0 N^{k0} - mu1 N^{k1}) on M
+//
+// with jump terms -(i w/2)(eps0 + eps1) on J and -(i w/2)(mu0 + mu1) on M.
+//
 // The table holds g^{k0} and g^{k0} - g^{k1} (with derivatives), so
 // mu N^{k0} - mu' N^{k1} = (mu - mu') N^{k0} + mu' (N^{k0} - N^{k1}) and the
 // k^2 terms of K are (k0^2 - k1^2) c(g^{k0}) + k1^2 c(g^{k0} - g^{k1}).
@@ -50,24 +58,44 @@ __device__ __forceinline__ cd mul_i(cd a) { return mk(-a.im, a.re); }  // i a
 
 struct Consts {
   cd k12, kd2;      // k1^2, k0^2 - k1^2
-  cd cmu01, cmu1;   // -i w (mu0 - mu1), -i w mu1
-  cd ceps01, ceps1;
-  cd jmu, jeps;   // (i w/2)(mu0+mu1), (i w/2)(eps0+eps1)
+  cd cJ0, cJ1;      // J block of rows 0,1: cJ0 N^{k0} + cJ1 (N^{k0} - N^{k1})
+  cd cM0, cM1;      // M block of rows 2,3 likewise
+  cd kJM, kMJ;      // K^{k0} - K^{k1} weights: rows 0,1 on M, rows 2,3 on J
+  cd jJ, jM;        // jump terms on J (rows 0,1) and M (rows 2,3)
 };
+
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return mk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
 
 __device__ Consts make_consts(const AsmParams& P) {
   Consts c;
   cd k1 = mk(P.k1r, P.k1i);
   c.k12 = k1 * k1;
   c.kd2 = mk(P.k0 * P.k0, 0) - c.k12;
-  cd miw = mk(0, -P.omega);
-  c.cmu01 = miw * mk(P.mu0r - P.mu1r, P.mu0i - P.mu1i);
-  c.cmu1 = miw * mk(P.mu1r, P.mu1i);
-  c.ceps01 = miw * mk(P.eps0r - P.eps1r, P.eps0i - P.eps1i);
-  c.ceps1 = miw * mk(P.eps1r, P.eps1i);
-  cd hiw = mk(0, 0.5 * P.omega);
-  c.jmu = hiw * mk(P.mu0r + P.mu1r, P.mu0i + P.mu1i);
-  c.jeps = hiw * mk(P.eps0r + P.eps1r, P.eps0i + P.eps1i);
+  const cd miw = mk(0, -P.omega), hiw = mk(0, 0.5 * P.omega);
+  const cd e0 = mk(P.eps0r, P.eps0i), m0 = mk(P.mu0r, P.mu0i);
+  const cd e1 = mk(P.eps1r, P.eps1i), m1 = mk(P.mu1r, P.mu1i);
+  // the J equations weigh N by mu (direct) or eps (indirect), the M equations
+  // by the other material
+  const cd a0 = P.formulation ? e0 : m0, a1 = P.formulation ? e1 : m1;
+  const cd b0 = P.formulation ? m0 : e0, b1 = P.formulation ? m1 : e1;
+  c.cJ0 = miw * (a0 - a1);
+  c.cJ1 = miw * a1;
+  c.cM0 = miw * (b0 - b1);
+  c.cM1 = miw * b1;
+  if (P.formulation) {
+    c.kJM = -cdiv(e0, m0);
+    c.kMJ = cdiv(m0, e0);
+    c.jJ = -(hiw * (e0 + e1));
+    c.jM = -(hiw * (m0 + m1));
+  } else {
+    c.kJM = mk(-1.0, 0.0);
+    c.kMJ = mk(1.0, 0.0);
+    c.jJ = hiw * (m0 + m1);
+    c.jM = hiw * (e0 + e1);
+  }
   return c;
 }
 
@@ -143,10 +171,10 @@ __device__ void block4(const cd T[3][kTypes], int m, double rt, double trt, doub
 #pragma unroll
     for (int be = 0; be < 2; ++be) {
       // N[0] = N^{k0}, N[1] = N^{k0} - N^{k1}
-      B[al][be] = C.cmu01 * N[0][al][be] + C.cmu1 * N[1][al][be];
-      B[al][2 + be] = -K[al][be];
-      B[2 + al][be] = K[al][be];
-      B[2 + al][2 + be] = C.ceps01 * N[0][al][be] + C.ceps1 * N[1][al][be];
+      B[al][be] = C.cJ0 * N[0][al][be] + C.cJ1 * N[1][al][be];
+      B[al][2 + be] = C.kJM * K[al][be];
+      B[2 + al][be] = C.kMJ * K[al][be];
+      B[2 + al][2 + be] = C.cM0 * N[0][al][be] + C.cM1 * N[1][al][be];
     }
 }
 
@@ -286,7 +314,7 @@ __global__ __launch_bounds__(kNearThreads) void assemble_near(AsmParams P, int n
     re *= sc;
     im *= sc;
     if (j == t && al == be) {  // identity term, unchanged by the weighting
-      const cd jt = (al < 2) ? C.jmu : C.jeps;
+      const cd jt = (al < 2) ? C.jJ : C.jM;
       re += jt.re;
       im += jt.im;
     }

@@ -68,6 +68,7 @@ struct AsmParams {
   int t0, nt;           // equations of targets t0 .. t0+nt-1; kern holds their rows
   double k0, k1r, k1i, omega;
   double eps0r, eps0i, mu0r, mu0i, eps1r, eps1i, mu1r, mu1i;
+  int formulation;      // 0: eq. mullerrep, 1: eq. dualmullrep
   const double* r;      // [N]
   const double* tr;     // [N] unit tangent r' = -nz
   const double* tz;     // [N] unit tangent z' = nr
@@ -84,6 +85,29 @@ struct AsmParams {
 
 hipError_t launch_tabulate(const TabParams& p, hipStream_t s);
 hipError_t launch_assemble(const AsmParams& p, hipStream_t s);
+
+// Off-surface evaluation (fields.hip): the currents of nvec solves synthesized
+// on the N x T surface grid, then one reduction per (vector, direction or point).
+struct FieldParams {
+  int N, T, nm, m_lo, nvec;
+  const double* r;      // [N]
+  const double* z;      // [N]
+  const double* tr;     // [N] r'
+  const double* tz;     // [N] z'
+  const double* w;      // [N] arclength weights
+  const double2* x;     // [nm][nvec][4N] modes m_lo .. m_lo + nm - 1 of the currents
+  double2* tw;          // [T] (cos, sin)(2 pi j / T)
+  double2* grid;        // [nvec][N][T][4] J^1, J^2, M^1, M^2 times the area weight
+  int npts;
+  const double* pts;    // [npts][3] unit directions (far field) or points
+  double k0, kr, ki, omega, mu0;
+  double2 aE, bE, aH, bH;  // E = aE ccS J + bE cS M, H = aH ccS M + bH cS J
+  double2* out;         // [nvec][npts][3]: E_inf, or E
+  double2* out2;        // [nvec][npts][3]: H
+};
+hipError_t launch_surface_grid(const FieldParams& p, hipStream_t s);
+hipError_t launch_far_field(const FieldParams& p, hipStream_t s);
+hipError_t launch_fields(const FieldParams& p, hipStream_t s);
 
 // Batched dense LU / solve (row-major, complex), see lu.hip.
 // Inverses of 64 x 64 unit-lower diagonal blocks kept per matrix by the LU:

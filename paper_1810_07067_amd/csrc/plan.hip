@@ -30,6 +30,7 @@ struct msv_plan {
   double k0 = 0, omega = 0;
   cplx k1, eps0, mu0, eps1, mu1;
   int precision = 0;
+  int formulation = 0;  // 0: eq. mullerrep, 1: eq. dualmullrep
   double ir_tol = 1e-13;
   int ir_max_iter = 10;
   int last_ir_iters = 0;
@@ -292,6 +293,7 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   if (d->fft_len < 8 || d->fft_len > 1024 || (d->fft_len & (d->fft_len - 1)))
     return fail(nullptr, MSV_EINVAL, "fft_len must be a power of two in [8, 1024]");
   if (d->precision != 0 && d->precision != 1) return fail(nullptr, MSV_EINVAL, "precision must be 0 or 1");
+  if (d->formulation != 0 && d->formulation != 1) return fail(nullptr, MSV_EINVAL, "formulation must be 0 or 1");
   const int N = c->n_panels * kOrder;
   if (4 * N > 8192) return fail(nullptr, MSV_EINVAL, "4N > 8192 exceeds the LU panel kernel");
   for (int i = 0; i < N; ++i) {
@@ -321,6 +323,7 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   p->k1 = p->omega * std::sqrt(p->eps1 * p->mu1);
   if (p->k1.imag() < 0) p->k1 = -p->k1;
   p->precision = d->precision;
+  p->formulation = d->formulation;
   p->ir_tol = d->ir_tol > 0 ? d->ir_tol : 1e-13;
   p->ir_max_iter = d->ir_max_iter > 0 ? d->ir_max_iter : 10;
 
@@ -646,6 +649,7 @@ msv_status msv_assemble_rows(msv_plan* p, const msv_c128* d_kern, int32_t t0, in
   A.eps1i = p->eps1.imag();
   A.mu1r = p->mu1.real();
   A.mu1i = p->mu1.imag();
+  A.formulation = p->formulation;
   A.r = p->d_r;
   A.tr = p->d_tr;
   A.tz = p->d_tz;
@@ -1116,5 +1120,116 @@ msv_status msv_solve_noalloc(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_
 }
 
 size_t msv_solve_noalloc_max_bytes(void) { return kScratchBytes; }
+
+// ---------------------------------------------------------------------------
+// fields off the surface and far field
+// ---------------------------------------------------------------------------
+namespace {
+
+msv_status field_common(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128* d_x,
+                        int32_t n_pts, const void* d_pts, double kabs, double tmul, double tadd,
+                        msv::FieldParams& F, void** buf, hipStream_t s) {
+  if (!d_x || !d_pts) return fail(p, MSV_EINVAL, "null buffer");
+  if (m_lo < -p->M || m_hi < m_lo || m_hi > p->M) return fail(p, MSV_EINVAL, "need -M <= m_lo <= m_hi <= M");
+  if (n_vec < 1 || n_pts < 1) return fail(p, MSV_EINVAL, "need n_vec >= 1 and at least one point");
+  const int mmax = std::max(std::abs(m_lo), std::abs(m_hi));
+  double rmax = 0.0;
+  for (double r : p->h_r) rmax = std::max(rmax, r);
+  const int T = (int)(tmul * (mmax + kabs * rmax) + tadd);
+  const size_t grid_elems = (size_t)n_vec * p->N * T * 4;
+  if ((long long)n_vec * p->N >= (1LL << 23) || (long long)n_vec * n_pts >= (1LL << 23))
+    return fail(p, MSV_EINVAL, "too many vectors x nodes or vectors x points for one launch");
+  const size_t bytes = (grid_elems + T) * sizeof(double2);
+  if (hipMallocAsync(buf, bytes, s) != hipSuccess) {
+    hipGetLastError();
+    return fail(p, MSV_ENOMEM, "surface-grid workspace allocation failed");
+  }
+  F.N = p->N;
+  F.T = T;
+  F.nm = m_hi - m_lo + 1;
+  F.m_lo = m_lo;
+  F.nvec = n_vec;
+  F.r = p->d_r;
+  F.z = p->d_z;
+  F.tr = p->d_tr;
+  F.tz = p->d_tz;
+  F.w = p->d_w;
+  F.x = reinterpret_cast<const double2*>(d_x);
+  F.grid = static_cast<double2*>(*buf);
+  F.tw = F.grid + grid_elems;
+  F.npts = n_pts;
+  F.pts = static_cast<const double*>(d_pts);
+  F.k0 = p->k0;
+  F.omega = p->omega;
+  F.mu0 = p->mu0.real();
+  return MSV_OK;
+}
+
+inline double2 d2(cplx z) { return make_double2(z.real(), z.imag()); }
+
+}  // namespace
+
+msv_status msv_far_field(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128* d_x,
+                         int32_t n_dirs, const double* d_dirs, msv_c128* d_out, void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  if (!d_out) return fail(p, MSV_EINVAL, "null buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  msv::FieldParams F{};
+  void* buf = nullptr;
+  msv_status st = field_common(p, m_lo, m_hi, n_vec, d_x, n_dirs, d_dirs, p->k0, 2.0, 64.0, F, &buf, s);
+  if (st != MSV_OK) return st;
+  F.out = reinterpret_cast<double2*>(d_out);
+  hipError_t e = msv::launch_surface_grid(F, s);
+  if (e == hipSuccess) e = msv::launch_far_field(F, s);
+  hipError_t ef = hipFreeAsync(buf, s);
+  if (e != hipSuccess || ef != hipSuccess) return fail(p, MSV_EHIP, "far-field launch failed");
+  return MSV_OK;
+}
+
+msv_status msv_fields(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128* d_x,
+                      int32_t n_points, const double* d_points, int32_t region, msv_c128* d_E, msv_c128* d_H,
+                      void* stream) {
+  if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
+  if (!d_E || !d_H) return fail(p, MSV_EINVAL, "null buffer");
+  if (region != 0 && region != 1) return fail(p, MSV_EINVAL, "region must be 0 (exterior) or 1 (interior)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const cplx k = region == 0 ? cplx(p->k0, 0.0) : p->k1;
+  msv::FieldParams F{};
+  void* buf = nullptr;
+  msv_status st = field_common(p, m_lo, m_hi, n_vec, d_x, n_points, d_points, std::abs(k), 4.0, 128.0, F, &buf, s);
+  if (st != MSV_OK) return st;
+  F.kr = k.real();
+  F.ki = k.imag();
+  // E = aE curl curl S J + bE curl S M, H = aH curl curl S M + bH curl S J
+  const cplx iw(0.0, p->omega);
+  cplx aE, bE, aH, bH;
+  if (region == 0) {  // eq. exteriorfield
+    aE = -1.0 / (iw * p->eps0);
+    bE = 1.0;
+    aH = 1.0 / (iw * p->mu0);
+    bH = 1.0;
+  } else if (p->formulation == 0) {  // eq. interiorfield
+    aE = 1.0 / (iw * p->eps1);
+    bE = -1.0;
+    aH = -1.0 / (iw * p->mu1);
+    bH = -1.0;
+  } else {  // eq. interior_dual
+    aE = -1.0 / (iw * p->eps0);
+    bE = p->mu1 / p->mu0;
+    aH = 1.0 / (iw * p->mu0);
+    bH = p->eps1 / p->eps0;
+  }
+  F.aE = d2(aE);
+  F.bE = d2(bE);
+  F.aH = d2(aH);
+  F.bH = d2(bH);
+  F.out = reinterpret_cast<double2*>(d_E);
+  F.out2 = reinterpret_cast<double2*>(d_H);
+  hipError_t e = msv::launch_surface_grid(F, s);
+  if (e == hipSuccess) e = msv::launch_fields(F, s);
+  hipError_t ef = hipFreeAsync(buf, s);
+  if (e != hipSuccess || ef != hipSuccess) return fail(p, MSV_EHIP, "field launch failed");
+  return MSV_OK;
+}
 
 }  // extern "C"
