@@ -22,7 +22,7 @@ eight plane waves from seed 2) instead.  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cylinder|spheroid]
                        [--no-cpu-baseline] [--no-forms]
-       python bench.py --form batching|serving   (the batching and serving forms)
+       python bench.py --form batching|serving|extinction   (the batching and serving forms, the accuracy experiment)
        python bench.py --profile-target lu|tabulate|copy [--config ...]   (one piece, for counters)
 """
 from __future__ import annotations
@@ -341,7 +341,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the complex128-path comparison and the secondary workload")
-    ap.add_argument("--form", choices=["batching", "serving"],
+    ap.add_argument("--form", choices=["batching", "serving", "extinction"],
                     help="measure one AI-systems form instead of the step (separate JSON line)")
     ap.add_argument("--modes", type=int, default=None,
                     help="with --profile-target lu: factor modes 0..modes-1 only")

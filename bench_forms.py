@@ -5,6 +5,8 @@ the step for hardware counters (see bench.py).
             launch sequence, against the same bodies factored one at a time
   serving   a request stream of mixed bodies, wavenumbers and plane-wave
             counts through the continuous-batching server (paper_1810_07067_amd.serve)
+  extinction the accuracy experiment of Section 6 (indirect system, current
+            loop) at the sizes of Tables 1 and 2, with the tables' phases
 """
 from __future__ import annotations
 
@@ -107,11 +109,102 @@ def bench_serving(rules, precision, count=48, seed=5, load=0.8):
             "cache_hit_rate": srv2.hits / max(1, srv2.hits + srv2.misses), "wall_s": wall}
 
 
+# Section 6, Tables 1 and 2: (k0, k1, N_f, N_pts) and the printed E_error
+TABLE1_TORUS = [(1, 2, 13, 64, 2.32e-9), (1, 5, 16, 160, 4.61e-9), (1, 10, 21, 320, 3.11e-8),
+                (5, 2, 13, 160, 1.01e-9), (5, 10, 21, 320, 3.84e-9), (5, 20, 30, 640, 4.63e-9),
+                (10, 5, 17, 320, 1.61e-9), (10, 20, 30, 640, 2.08e-9), (10, 40, 45, 640, 2.66e-8),
+                (20, 5, 17, 320, 4.78e-9), (20, 10, 22, 640, 3.37e-9), (20, 40, 45, 640, 1.10e-8)]
+TABLE2_STARFISH = [(5, 2, 10, 224, 1.24e-9), (5, 10, 16, 304, 3.44e-10), (5, 20, 21, 464, 1.51e-9),
+                   (10, 5, 13, 304, 2.04e-10), (10, 20, 21, 464, 9.74e-10), (10, 40, 30, 784, 1.45e-8),
+                   (20, 5, 13, 464, 1.05e-10), (20, 10, 16, 464, 4.41e-10), (20, 40, 30, 784, 4.60e-9),
+                   (40, 5, 13, 784, 3.39e-10), (40, 10, 16, 784, 3.58e-9), (40, 20, 21, 784, 3.01e-9)]
+LOOP = dict(center=[0.4, 0.5, 5.0], radius=0.42)  # Section 6
+
+
+def _interior_points(body, rng, P):
+    if body == "torus":  # within half of the cross-section of r = 2 + cos t, z = sin(t)/2
+        rho = 0.5 * np.sqrt(rng.uniform(0, 1, P))
+        ph, th = rng.uniform(0, 2 * np.pi, P), rng.uniform(0, 2 * np.pi, P)
+        rr, zz = 2 + rho * np.cos(ph), 0.5 * rho * np.sin(ph)
+        return np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+    v = rng.standard_normal((P, 3))  # the starfish contains the ball of radius 1.5
+    return v / np.linalg.norm(v, axis=1)[:, None] * rng.uniform(0, 0.75, (P, 1))
+
+
+def bench_extinction(rules, body, rows, precision=1, seed=3, n_points=6):
+    """The accuracy experiment of Section 6 on the GPU: the indirect system
+    (eq. dualmullrep) with the current-loop data of eq. loop, at the sizes of
+    Tables 1 (torus) and 2 (rotated starfish); E_error over random interior
+    points (eq. interior_dual, evaluated on 4 sub-panels per panel) and the
+    four phases of the tables: T_kernel
+    (tabulation), T_matgen (assembly), T_solve (factor and solve all modes),
+    T_add (one more right-hand side)."""
+    import time
+
+    import torch
+    import paper_1810_07067_amd as msv
+    from workloads import geometry, incident
+    out = []
+    for k0, k1, Nf, npts, paper_err in rows:
+        curve = geometry.torus(npts // 16) if body == "torus" else geometry.starfish(npts // 16)
+        eps1 = (k1 / k0) ** 2
+        L = valid_fft_len(curve, k0, eps1, Nf)
+        rhs = torch.from_numpy(incident.loop_rhs_modes(curve, LOOP["center"], LOOP["radius"], k1, k0, 1.0,
+                                                       -Nf, Nf)).cuda()
+        pts = _interior_points(body, np.random.default_rng(seed), n_points)
+
+        def phase(fn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            return r, time.perf_counter() - t0
+        used = precision
+        for prec in (precision, 0) if precision else (0,):
+            # complex64 factors whose refinement does not converge (the
+            # system too ill-conditioned for them) fall back to complex128
+            plan = msv.plan_from_curve(curve, rules, k0, eps1, 1.0, m_max=Nf, fft_len=L, precision=prec,
+                                       formulation=1)
+            kern, t_kernel = phase(plan.tabulate)
+            A, t_matgen = phase(lambda: plan.assemble(kern, 0, Nf))
+            del kern
+            try:
+                x, t_solve = phase(lambda: (plan.factor(A, 0, Nf), plan.solve(-Nf, Nf, rhs))[1])
+            except msv.MsvError as exc:
+                if exc.status != msv.MSV_ENOCONV or prec == 0:
+                    raise
+                plan.close()
+                del A
+                continue
+            used = prec
+            break
+        _, t_add = phase(lambda: plan.solve(-Nf, Nf, rhs))
+        E, H = plan.fields(-Nf, Nf, x, pts, "interior", upsample=4)
+        El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], k1, k0, 1.0)
+        Er, Hr = El(pts), Hl(pts)
+        E, H = E[0].cpu().numpy(), H[0].cpu().numpy()
+        err = np.sqrt((np.linalg.norm(E - Er) ** 2 + np.linalg.norm(H - Hr) ** 2)
+                      / (np.linalg.norm(Er) ** 2 + np.linalg.norm(Hr) ** 2))
+        out.append({"k0": k0, "k1": k1, "N_f": Nf, "N_pts": npts, "L": L, "T_kernel_s": t_kernel,
+                    "T_matgen_s": t_matgen, "T_solve_s": t_solve, "T_add_s": t_add, "E_error": float(err),
+                    "paper_E_error": paper_err, "precision": used,
+                    "ir_iterations": plan.last_ir_iterations() if used else 0})
+        print(f"[extinction] {body} {out[-1]}", file=sys.stderr, flush=True)
+        plan.close()
+        del A, x
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_form(form):
     from workloads import rules
     rls = rules.load_rules()
     if form == "batching":
         return {"form": "batching", **bench_batching(rls)}
+    if form == "extinction":
+        return {"form": "extinction", "precision": "complex64 LU + complex128 refinement",
+                "torus_table1": bench_extinction(rls, "torus", TABLE1_TORUS),
+                "starfish_table2": bench_extinction(rls, "starfish", TABLE2_STARFISH)}
     return {"form": "serving", "complex64_lu_refined": bench_serving(rls, 1), "complex128_lu": bench_serving(rls, 0)}
 
 

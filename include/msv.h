@@ -249,15 +249,21 @@ size_t msv_solve_noalloc_max_bytes(void);
  * the body, the scattered field of eq. exteriorfield; region 1: points inside,
  * the field of eq. interiorfield (direct system) or eq. interior_dual
  * (indirect system, msv_desc.formulation).  The caller states the region;
- * the quadrature is accurate for points whose distance to the surface is not
- * small against the nearby panels.  d_points [n_points][3]; d_E, d_H
- * [n_vec][n_points][3].  T = floor(4 (max |m| + |k| r_max) + 128) with k the
- * region's wavenumber. */
+ * the rule along the curve loses accuracy for points whose distance to the
+ * surface is small against the nearby panels, so with upsample = U in [2, 8]
+ * each panel's current modes, r, z, dr/du and dz/du are first interpolated
+ * (Legendre interpolation from its 16 nodes) to U sub-panels of 16
+ * Gauss-Legendre nodes (the grid then has N U nodes and the workspace holds
+ * the interpolated modes too).  The first call with a new U synchronizes
+ * `stream` and uploads that sub-panel geometry, (5 N U + 256 U) * 8 bytes kept
+ * by the plan (counted by msv_plan_device_bytes).  d_points [n_points][3];
+ * d_E, d_H [n_vec][n_points][3].  T = floor(4 (max |m| + |k| r_max) + 128)
+ * with k the region's wavenumber. */
 msv_status msv_far_field(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128 *d_x,
                          int32_t n_dirs, const double *d_dirs, msv_c128 *d_out, void *stream);
 msv_status msv_fields(msv_plan *plan, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128 *d_x,
-                      int32_t n_points, const double *d_points, int32_t region, msv_c128 *d_E,
-                      msv_c128 *d_H, void *stream);
+                      int32_t n_points, const double *d_points, int32_t region, int32_t upsample,
+                      msv_c128 *d_E, msv_c128 *d_H, void *stream);
 
 /* Iterations used by the last precision-1 msv_solve (max over modes). */
 int32_t msv_last_ir_iterations(const msv_plan *plan);

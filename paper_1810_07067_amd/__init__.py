@@ -91,7 +91,7 @@ def load_library(path: str = LIB_PATH):
     lib.msv_far_field.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P, P]
     lib.msv_far_field.restype = ctypes.c_int
     lib.msv_fields.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P,
-                               ctypes.c_int32, P, P, P]
+                               ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.msv_fields.restype = ctypes.c_int
     lib.msv_solve_noalloc_max_bytes.argtypes = []
     lib.msv_solve_noalloc_max_bytes.restype = ctypes.c_size_t
@@ -297,9 +297,10 @@ class Plan:
                                            _stream_handle(stream)))
         return out
 
-    def fields(self, m_lo, m_hi, x, points, region, stream=None):
+    def fields(self, m_lo, m_hi, x, points, region, upsample=1, stream=None):
         """msv_fields: E, H [n_vec, n_points, 3] at points [n_points, 3] of
-        `region` ("exterior" or "interior")."""
+        `region` ("exterior" or "interior"), the currents interpolated to
+        `upsample` sub-panels per panel."""
         import torch
         nm = m_hi - m_lo + 1
         assert x.dtype == torch.complex128 and x.is_contiguous() and x.shape[0] == nm and x.shape[2] == self.n
@@ -310,7 +311,8 @@ class Plan:
         H = torch.empty_like(E)
         self._check(self.lib.msv_fields(self._h, int(m_lo), int(m_hi), int(x.shape[1]),
                                         ctypes.c_void_p(x.data_ptr()), int(pts.shape[0]),
-                                        ctypes.c_void_p(pts.data_ptr()), reg, ctypes.c_void_p(E.data_ptr()),
+                                        ctypes.c_void_p(pts.data_ptr()), reg, int(upsample),
+                                        ctypes.c_void_p(E.data_ptr()),
                                         ctypes.c_void_p(H.data_ptr()), _stream_handle(stream)))
         return E, H
 

@@ -214,7 +214,42 @@ __global__ __launch_bounds__(kFieldThreads) void near_fields(FieldParams P) {
   }
 }
 
+// Current modes at the sub-panel nodes: xf[kv][4 nf + c] = sum_j L[f][j]
+// x[kv][4 (16 p + j) + c] for fine node nf = 16 U p + f (L: [16 U][16]).
+__global__ __launch_bounds__(kFieldThreads) void interp_currents(const double2* __restrict__ x,
+                                                                 double2* __restrict__ xf, const double* L, int N,
+                                                                 int U, long long total) {
+  const int NU = N * U, F = 16 * U;
+  for (long long i = (long long)blockIdx.x * kFieldThreads + threadIdx.x; i < total;
+       i += (long long)gridDim.x * kFieldThreads) {
+    const int c = (int)(i & 3);
+    const long long q = i >> 2;
+    const long long kv = q / NU;
+    const int nf = (int)(q - kv * NU);
+    const int p = nf / F, f = nf - p * F;
+    const double2* src = x + kv * 4 * N + 4 * 16 * p + c;
+    const double* l = L + 16 * f;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double2 v = src[4 * j];
+      re = fma(l[j], v.x, re);
+      im = fma(l[j], v.y, im);
+    }
+    xf[i] = make_double2(re, im);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_interp_currents(const double2* x, double2* xf, const double* L, int N, int U, int nmv,
+                                  hipStream_t s) {
+  const long long total = (long long)nmv * N * U * 4;
+  const long long blocks = (total + kFieldThreads - 1) / kFieldThreads;
+  hipLaunchKernelGGL(interp_currents, dim3((unsigned)(blocks < (1 << 20) ? blocks : (1 << 20))),
+                     dim3(kFieldThreads), 0, s, x, xf, L, N, U, total);
+  return hipGetLastError();
+}
 
 hipError_t launch_surface_grid(const FieldParams& P, hipStream_t s) {
   if (P.T < 1 || P.N < 1 || P.nvec < 1 || P.nm < 1) return hipErrorInvalidValue;

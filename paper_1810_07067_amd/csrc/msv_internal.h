@@ -106,6 +106,9 @@ struct FieldParams {
   double2* out2;        // [nvec][npts][3]: H
 };
 hipError_t launch_surface_grid(const FieldParams& p, hipStream_t s);
+// current modes [nmv][4N] at U sub-panels of 16 nodes per panel: [nmv][4NU]
+hipError_t launch_interp_currents(const double2* x, double2* xf, const double* L, int N, int U, int nmv,
+                                  hipStream_t s);
 hipError_t launch_far_field(const FieldParams& p, hipStream_t s);
 hipError_t launch_fields(const FieldParams& p, hipStream_t s);
 

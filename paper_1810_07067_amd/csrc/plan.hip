@@ -35,7 +35,12 @@ struct msv_plan {
   int ir_max_iter = 10;
   int last_ir_iters = 0;
   int ir_pred = 0;  // refinement steps of the last converged solve
-  std::vector<double> h_r, h_w;
+  std::vector<double> h_r, h_w, h_z, h_dru, h_dzu;  // nodes, weights, dr/du, dz/du
+  // sub-panel geometry of msv_fields with upsample = up_U > 1: [5][N U]
+  // (r, z, r', z', arclength weight) then the [16 U][16] interpolation matrix
+  int up_U = 0;
+  double* d_up = nullptr;
+  size_t up_bytes = 0;
   // device
   double *d_r = nullptr, *d_z = nullptr, *d_tr = nullptr, *d_tz = nullptr, *d_w = nullptr, *d_sqw = nullptr;
   double *d_sup = nullptr, *d_lag_self = nullptr, *d_lag_adj = nullptr;
@@ -209,7 +214,7 @@ size_t msv_table_entries(const msv_plan* p) {
 static void plan_free(msv_plan* p) {
   void* bufs[] = {p->d_r, p->d_z, p->d_tr, p->d_tz, p->d_w, p->d_sqw, p->d_sup, p->d_lag_self,
                   p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
-                  p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_work, p->d_spec, p->d_tabs};
+                  p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_work, p->d_spec, p->d_tabs, p->d_up};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -259,7 +264,7 @@ size_t msv_plan_device_bytes(const msv_plan* p) {
   const size_t nbf = p->ipiv_elems / n;  // modes of the pivot storage
   b += p->ipiv_elems * 2 * sizeof(int32_t) + nbf * sizeof(int32_t) + p->luw_bytes + p->fac32_elems * sizeof(float2) +
        p->inv_bytes;
-  b += p->work_bytes;
+  b += p->work_bytes + p->up_bytes;
   return b;
 }
 
@@ -515,6 +520,13 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   for (int t = 0; t < N; ++t) p->near_start[t + 1] += p->near_start[t];
   p->h_r.assign(c->h_r, c->h_r + N);
   p->h_w = w;
+  p->h_z.assign(c->h_z, c->h_z + N);
+  p->h_dru.resize(N);
+  p->h_dzu.resize(N);
+  for (int i = 0; i < N; ++i) {
+    p->h_dru[i] = tr[i] * c->h_dsdu[i];
+    p->h_dzu[i] = tz[i] * c->h_dsdu[i];
+  }
 
   msv_status st;
 #define UP(dst, vec) \
@@ -1127,8 +1139,8 @@ size_t msv_solve_noalloc_max_bytes(void) { return kScratchBytes; }
 namespace {
 
 msv_status field_common(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128* d_x,
-                        int32_t n_pts, const void* d_pts, double kabs, double tmul, double tadd,
-                        msv::FieldParams& F, void** buf, hipStream_t s) {
+                        int32_t n_pts, const void* d_pts, double kabs, double tmul, double tadd, int U,
+                        size_t extra_elems, msv::FieldParams& F, void** buf, hipStream_t s) {
   if (!d_x || !d_pts) return fail(p, MSV_EINVAL, "null buffer");
   if (m_lo < -p->M || m_hi < m_lo || m_hi > p->M) return fail(p, MSV_EINVAL, "need -M <= m_lo <= m_hi <= M");
   if (n_vec < 1 || n_pts < 1) return fail(p, MSV_EINVAL, "need n_vec >= 1 and at least one point");
@@ -1136,15 +1148,15 @@ msv_status field_common(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec, 
   double rmax = 0.0;
   for (double r : p->h_r) rmax = std::max(rmax, r);
   const int T = (int)(tmul * (mmax + kabs * rmax) + tadd);
-  const size_t grid_elems = (size_t)n_vec * p->N * T * 4;
-  if ((long long)n_vec * p->N >= (1LL << 23) || (long long)n_vec * n_pts >= (1LL << 23))
+  const size_t grid_elems = (size_t)n_vec * p->N * U * T * 4;
+  if ((long long)n_vec * p->N * U >= (1LL << 23) || (long long)n_vec * n_pts >= (1LL << 23))
     return fail(p, MSV_EINVAL, "too many vectors x nodes or vectors x points for one launch");
-  const size_t bytes = (grid_elems + T) * sizeof(double2);
+  const size_t bytes = (grid_elems + T + extra_elems) * sizeof(double2);
   if (hipMallocAsync(buf, bytes, s) != hipSuccess) {
     hipGetLastError();
     return fail(p, MSV_ENOMEM, "surface-grid workspace allocation failed");
   }
-  F.N = p->N;
+  F.N = p->N * U;
   F.T = T;
   F.nm = m_hi - m_lo + 1;
   F.m_lo = m_lo;
@@ -1176,7 +1188,7 @@ msv_status msv_far_field(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec,
   hipStream_t s = static_cast<hipStream_t>(stream);
   msv::FieldParams F{};
   void* buf = nullptr;
-  msv_status st = field_common(p, m_lo, m_hi, n_vec, d_x, n_dirs, d_dirs, p->k0, 2.0, 64.0, F, &buf, s);
+  msv_status st = field_common(p, m_lo, m_hi, n_vec, d_x, n_dirs, d_dirs, p->k0, 2.0, 64.0, 1, 0, F, &buf, s);
   if (st != MSV_OK) return st;
   F.out = reinterpret_cast<double2*>(d_out);
   hipError_t e = msv::launch_surface_grid(F, s);
@@ -1186,18 +1198,94 @@ msv_status msv_far_field(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec,
   return MSV_OK;
 }
 
+// Sub-panel geometry for msv_fields: each panel's r, z, dr/du, dz/du
+// interpolated (Legendre, from its 16 nodes) to U sub-panels of 16
+// Gauss-Legendre nodes, sub-panel q spanning u in [-1 + 2q/U, -1 + 2(q+1)/U].
+static msv_status ensure_upsampled(msv_plan* p, int U, hipStream_t s) {
+  if (p->up_U == U && p->d_up) return MSV_OK;
+  std::vector<double> ug, wg;
+  gauss_legendre(kOrder, ug, wg);
+  std::vector<double> bw(kOrder, 1.0);
+  for (int j = 0; j < kOrder; ++j)
+    for (int k = 0; k < kOrder; ++k)
+      if (k != j) bw[j] /= (ug[j] - ug[k]);
+  const int F = kOrder * U, NU = p->N * U;
+  std::vector<double> h(5 * (size_t)NU + (size_t)F * kOrder);
+  double* L = h.data() + 5 * (size_t)NU;
+  for (int q = 0; q < U; ++q)
+    for (int v = 0; v < kOrder; ++v) lagrange_row(ug, bw, -1.0 + (2.0 * q + ug[v] + 1.0) / U, L + (q * kOrder + v) * kOrder);
+  for (int pn = 0; pn < p->npan; ++pn)
+    for (int f = 0; f < F; ++f) {
+      double r = 0, z = 0, ru = 0, zu = 0;
+      for (int j = 0; j < kOrder; ++j) {
+        const int n = pn * kOrder + j;
+        const double l = L[f * kOrder + j];
+        r += l * p->h_r[n];
+        z += l * p->h_z[n];
+        ru += l * p->h_dru[n];
+        zu += l * p->h_dzu[n];
+      }
+      const double sp = std::hypot(ru, zu);
+      const size_t nf = (size_t)pn * F + f;
+      h[nf] = r;
+      h[NU + nf] = z;
+      h[2 * (size_t)NU + nf] = ru / sp;
+      h[3 * (size_t)NU + nf] = zu / sp;
+      h[4 * (size_t)NU + nf] = wg[f % kOrder] * sp / U;
+    }
+  // the previous sub-panel geometry may still be read by work on `s`
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(p, MSV_EHIP, "stream synchronize failed");
+  if (p->d_up) (void)hipFree(p->d_up);
+  p->d_up = nullptr;
+  p->up_bytes = 0;
+  p->up_U = 0;
+  if (hipMalloc(&p->d_up, h.size() * sizeof(double)) != hipSuccess) {
+    hipGetLastError();
+    p->d_up = nullptr;
+    return fail(p, MSV_ENOMEM, "sub-panel geometry allocation failed");
+  }
+  if (hipMemcpy(p->d_up, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(p, MSV_EHIP, "sub-panel geometry upload failed");
+  p->up_bytes = h.size() * sizeof(double);
+  p->up_U = U;
+  return MSV_OK;
+}
+
 msv_status msv_fields(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec, const msv_c128* d_x,
-                      int32_t n_points, const double* d_points, int32_t region, msv_c128* d_E, msv_c128* d_H,
-                      void* stream) {
+                      int32_t n_points, const double* d_points, int32_t region, int32_t upsample, msv_c128* d_E,
+                      msv_c128* d_H, void* stream) {
   if (!p) return fail(nullptr, MSV_EINVAL, "null plan");
   if (!d_E || !d_H) return fail(p, MSV_EINVAL, "null buffer");
   if (region != 0 && region != 1) return fail(p, MSV_EINVAL, "region must be 0 (exterior) or 1 (interior)");
+  if (upsample < 1 || upsample > 8) return fail(p, MSV_EINVAL, "upsample must be in [1, 8]");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const cplx k = region == 0 ? cplx(p->k0, 0.0) : p->k1;
+  if (upsample > 1) {
+    msv_status su = ensure_upsampled(p, upsample, s);
+    if (su != MSV_OK) return su;
+  }
   msv::FieldParams F{};
   void* buf = nullptr;
-  msv_status st = field_common(p, m_lo, m_hi, n_vec, d_x, n_points, d_points, std::abs(k), 4.0, 128.0, F, &buf, s);
+  const size_t x_elems = (size_t)(m_hi - m_lo + 1) * n_vec * 4 * p->N * upsample;
+  msv_status st = field_common(p, m_lo, m_hi, n_vec, d_x, n_points, d_points, std::abs(k), 4.0, 128.0, upsample,
+                               upsample > 1 ? x_elems : 0, F, &buf, s);
   if (st != MSV_OK) return st;
+  if (upsample > 1) {
+    const int NU = p->N * upsample;
+    double2* xf = F.tw + F.T;
+    hipError_t ei = msv::launch_interp_currents(F.x, xf, p->d_up + 5 * (size_t)NU, p->N, upsample,
+                                                (m_hi - m_lo + 1) * n_vec, s);
+    if (ei != hipSuccess) {
+      (void)hipFreeAsync(buf, s);
+      return fail(p, MSV_EHIP, "current interpolation launch failed");
+    }
+    F.x = xf;
+    F.r = p->d_up;
+    F.z = p->d_up + NU;
+    F.tr = p->d_up + 2 * (size_t)NU;
+    F.tz = p->d_up + 3 * (size_t)NU;
+    F.w = p->d_up + 4 * (size_t)NU;
+  }
   F.kr = k.real();
   F.ki = k.imag();
   // E = aE curl curl S J + bE curl S M, H = aH curl curl S M + bH curl S J

@@ -98,6 +98,21 @@ def torus(n_panels: int, R0: float = 2.0, a: float = 1.0, b: float = 0.5) -> Cur
     return _from_panels("torus", panels, True, {"kind": "torus"})
 
 
+def starfish(n_panels: int) -> Curve:
+    """The rotated starfish of Example 2: r = rho cos(pi (t - 1/2)),
+    z = rho sin(pi (t - 1/2)), rho = 2 + cos(5 pi (t - 1))/2, t in [0, 1]
+    (pole to pole), equal panels in t."""
+    def f(t):
+        rho = 2.0 + 0.5 * np.cos(5 * np.pi * (t - 1.0))
+        drho = -2.5 * np.pi * np.sin(5 * np.pi * (t - 1.0))
+        ph = np.pi * (t - 0.5)
+        c, s = np.cos(ph), np.sin(ph)
+        return rho * c, rho * s, drho * c - np.pi * rho * s, drho * s + np.pi * rho * c
+    edges = np.linspace(0.0, 1.0, n_panels + 1)
+    panels = [(a_, b_, f) for a_, b_ in zip(edges[:-1], edges[1:])]
+    return _from_panels("starfish", panels, False, {"kind": "starfish"})
+
+
 def _segment(p0, p1):
     p0 = np.asarray(p0, float)
     p1 = np.asarray(p1, float)

@@ -24,6 +24,9 @@ whose rows take them in the order
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 
@@ -84,7 +87,8 @@ def current_loop(center, radius, k, omega, mu, n_quad=None):
     a = float(radius)
     k = complex(k)
     if n_quad is None:
-        n_quad = 64 + 8 * int(np.ceil(abs(k) * a))
+        # the integrand's bandwidth along the loop is about |k| a
+        n_quad = 64 + 4 * int(np.ceil(abs(k) * a))
     s = 2 * np.pi * np.arange(n_quad) / n_quad
     ys = c[None, :] + a * np.stack([np.cos(s), np.sin(s), np.zeros_like(s)], axis=1)
     dl = (2 * np.pi / n_quad) * a * np.stack([-np.sin(s), np.cos(s), np.zeros_like(s)], axis=1)
@@ -127,7 +131,10 @@ def rhs_from_fields(curve, fields, coefs, m_lo, m_hi, n_theta):
     ms = np.arange(m_lo, m_hi + 1)
     for w, (Ef, Hf) in enumerate(fields):
         for fld, base, coef in ((Hf, 0, coefs[0]), (Ef, 2, coefs[1])):
-            V = fld(x)
+            # in node chunks: a field given by a quadrature (the loop) holds a
+            # [points, quadrature nodes, 3] array per call
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+                V = np.concatenate(list(pool.map(fld, [x[i:i + 16] for i in range(0, N, 16)])), axis=0)
             Vr = V[..., 0] * ct + V[..., 1] * st
             Vt = -V[..., 0] * st + V[..., 1] * ct
             Vz = V[..., 2]
@@ -159,8 +166,8 @@ def loop_rhs_modes(curve, center, radius, k1, omega, mu1, m_lo, m_hi, eps0=1.0, 
     rmax = float(np.max(curve.r))
     mmax = max(abs(m_lo), abs(m_hi))
     if n_theta is None:
-        # the loop field seen from the body's rings: its angular bandwidth is
-        # set by the distance to the loop relative to the ring radius
-        n_theta = 1 << int(np.ceil(np.log2(4 * (mmax + abs(k1) * rmax + np.hypot(c[0], c[1]) * 8) + 64)))
+        # the traces on a ring of radius r carry modes up to about |k1| r plus
+        # the offset of the loop's axis from the body's; 32 modes of margin
+        n_theta = 1 << int(np.ceil(np.log2(2 * (mmax + abs(k1) * rmax + 8 * np.hypot(c[0], c[1])) + 64)))
     E, H = current_loop(c, radius, k1, omega, mu1)
     return rhs_from_fields(curve, [(E, H)], (1j * omega * eps0, 1j * omega * mu0), m_lo, m_hi, n_theta)
