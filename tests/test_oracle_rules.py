@@ -43,6 +43,16 @@ def test_adjacent_rule_exact(delta, alpha):
             assert abs(got - exact) < 1e-14 * max(1.0, abs(exact))
 
 
+def test_self_rules_keep_their_distance():
+    """No self-rule node lies within 1e-5 of its target: nodes closer than that,
+    paired with weights of opposite sign, multiplied the rounding of the
+    derivative kernels (which grow like 1/|x - y|) by sum |w| / |y - x| ~ 1e8."""
+    for i in range(16):
+        d = np.abs(YS[i] - XG[i])
+        assert d.min() >= 1e-5
+        assert np.sum(np.abs(WS[i]) / d) < 3e4
+
+
 def test_rules_are_polynomially_exact_and_inside():
     assert np.all(np.abs(YS) < 1) and np.all(np.abs(YA) < 1)
     for j in range(16):

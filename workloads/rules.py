@@ -19,6 +19,12 @@ until the rule can shrink no further.
   (deg p, q < 16) exactly -- the exactness of the paper's self-panel rules.
   Nodes are chosen from a composite rule graded toward ``x_i`` by pivoted QR
   on the family; the weights solve the moment equations with exact moments.
+  Candidates closer than ``SELF_DMIN`` to ``x_i`` are left out: unconstrained,
+  the selection takes pairs of nodes within 1e-9 of targets near the panel
+  ends, with weights of opposite sign around 0.1.  The derivative kernels grow
+  like 1/|x - y| there and cancel in the combinations the operators use, so
+  those pairs multiply the kernels' rounding by sum |w| / |y - x| ~ 1e8.  With
+  the bound the factor is at most 2e4 and the rules stay as accurate.
 * ``adjacent`` rule on [-1, 1], accurate for ``P_j(y)`` and
   ``P_j(y) log|y - x|`` (j < 16) for every singular point ``x`` that a target on
   a neighbouring panel can produce: outside the panel, at distance
@@ -219,6 +225,7 @@ _TANH_PARAM = (np.arctanh, np.tanh, lambda x: 1.0 - x * x)
 
 
 NSELF = 2 * ORDER
+SELF_DMIN = 1e-5  # smallest |y - x| of a self-rule node (panel coordinate)
 
 
 def _self_family(y, x):
@@ -249,6 +256,8 @@ def build_self_rules():
     for i, x in enumerate(xg):
         xo = np.concatenate([x - (x + 1) * xa, x + (1 - x) * xa])
         wo = np.concatenate([(x + 1) * wa, (1 - x) * wa])
+        keep = np.abs(xo - x) >= SELF_DMIN
+        xo, wo = xo[keep], wo[keep]
         F, _ = _self_family(xo, x)
         A = F * np.sqrt(wo)[None, :]
         A /= np.linalg.norm(A, axis=1)[:, None]
@@ -256,7 +265,20 @@ def build_self_rules():
         idx = _qr_select(Vt, NSELF)
         y = xo[idx]
         B, _ = _self_family(y, x)
-        w = np.linalg.solve(B, _self_moments(x))
+        mom = _self_moments(x)
+        w = np.linalg.solve(B, mom)
+        # refine the weights: residual of the moment equations in extended
+        # precision, so that the rule is exact to the moments' own rounding
+        yl, xl = y.astype(np.longdouble), np.longdouble(x)
+        P = np.zeros((ORDER, y.size), dtype=np.longdouble)
+        P[0] = 1
+        P[1] = yl
+        for j in range(1, ORDER - 1):
+            P[j + 1] = ((2 * j + 1) * yl * P[j] - j * P[j - 1]) / (j + 1)
+        Bl = np.vstack([P, P * np.log(np.abs(yl - xl))])
+        for _ in range(2):
+            res = mom.astype(np.longdouble) - Bl @ w.astype(np.longdouble)
+            w = w + np.linalg.solve(B, res.astype(np.float64))
         srt = np.argsort(y)
         nodes[i], weights[i] = y[srt], w[srt]
     # the node set is symmetric under y -> -y; keep, for each mirror pair of
