@@ -67,6 +67,164 @@ def bench_batching(rules, seed=4, n_bodies=16, M=16):
             "tflops": flops / (bat_ms * 1e-3) / 1e12}
 
 
+def random_bodies(seed=4, n_bodies=64):
+    """The batched workload at its stated size: n_bodies seeded random bodies
+    (Fourier-perturbed spheroids, about a quarter with a dyadically refined
+    conical tip) with 256..2048 nodes, k0 uniform in [1, 30], eps1 uniform in
+    [1.5, 6]."""
+    from workloads import geometry
+    out = []
+    for b in range(n_bodies):
+        rng = np.random.default_rng([seed, b])
+        npan = max(16, int(rng.integers(256, 2049)) // 16)
+        tip = rng.random() < 0.25
+        k0, eps1 = float(rng.uniform(1.0, 30.0)), float(rng.uniform(1.5, 6.0))
+        while True:  # a tip adds panels: stay within 2048 nodes
+            curve = geometry.random_body(np.random.default_rng([seed, b, 1]), npan, tip_levels=4 if tip else 0)
+            if curve.n <= 2048:
+                break
+            npan -= 1
+        out.append((curve, k0, eps1))
+    return out
+
+
+def bench_batching_random_bodies(rules, M=64, budget=200e9, seed=4, n_bodies=64):
+    """Batching form at the stated size: all modes |m| <= M of every body.
+    The bodies do not fit in HBM together, so they stream through in groups
+    whose matrices and plan memory fit `budget`; each group is tabulated and
+    assembled body by body (row blocks of at most 8 GB of table), then
+    factored one body after another and again as one batch (one captured
+    launch sequence over all (body, mode) matrices, outer panel width tuned),
+    and solved for one plane wave.  Per group the faster of the two schedules
+    is kept (the batch's outer panels can only be as wide as every smaller
+    order's divisor, 64 for these mixed orders, while a lone body uses 512).
+    The smallest body of each group is also solved with the complex128 LU, and
+    the two solutions compared.  A body whose mixed-precision refinement does
+    not converge is refactored with the complex128 LU, timed apart."""
+    import torch
+    import paper_1810_07067_amd as msv
+    from workloads import incident
+    bodies = random_bodies(seed, n_bodies)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    S = rules[0][0].shape[1] + 2 * rules[1][0].size
+
+    def need(curve, k0, eps1):
+        L = valid_fft_len(curve, k0, eps1, M)
+        n = 4 * curve.n
+        return L, (M + 1) * n * n * 16 + msv.workspace_bytes(curve.n, S, L, M + 1, 2 * (2 * M + 1), 1)
+    # the batch also holds, per (body, mode) matrix, the inverse slots and the
+    # bf16 planes of one trailing update at the group's largest order
+    def batch_ws(nmax, nmat):
+        R = (nmax + 127) // 128 * 128
+        return nmat * (8 * 64 * 64 * 8 + 2 * 4 * R * 512 * 2)
+    groups, cur, used, nmax = [], [], 0, 0
+    for bd in bodies:
+        L, b = need(*bd)
+        nm = max(nmax, 4 * bd[0].n)
+        if cur and used + b + batch_ws(nm, (len(cur) + 1) * (M + 1)) > budget:
+            groups.append(cur)
+            cur, used, nm = [], 0, 4 * bd[0].n
+        cur.append((bd, L))
+        used += b
+        nmax = nm
+    groups.append(cur)
+    tot_solo = tot_batch = tot_sched = flops = fallback_ms = 0.0
+    rows, parity, skipped, noconv = [], [], 0, 0
+    for gi, grp in enumerate(groups):
+        plans, mats, meta = [], [], []
+        for (curve, k0, eps1), L in grp:
+            try:
+                p = msv.plan_from_curve(curve, rules, k0, eps1, 1.0, m_max=M, fft_len=L, precision=1)
+            except msv.MsvError:
+                skipped += 1  # a tip whose panels grade too steeply, or L beyond 1024
+                continue
+            nb = max(16, min(curve.n, int(8e9 // ((M + 2) * 9 * (curve.n + S) * 16))))
+            mats.append(p.assemble_streamed(0, M, rows_per_block=nb))
+            plans.append(p)
+            meta.append((curve, k0, eps1, L))
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        for p, A in zip(plans, mats):  # warm, and the factor storage
+            p.factor(A, 0, M)
+        e0, e1 = ev(), ev()
+        e0.record()
+        for p, A in zip(plans, mats):
+            p.factor(A, 0, M)
+        e1.record()
+        torch.cuda.synchronize()
+        solo = e0.elapsed_time(e1)
+        batch = msv.Batch(plans, mats, 0, M)
+        batch.factor()
+        torch.cuda.synchronize()
+        e0.record()
+        batch.factor()
+        e1.record()
+        torch.cuda.synchronize()
+        bat = e0.elapsed_time(e1)
+        gflops = sum((8.0 / 3.0) * p.n ** 3 * (M + 1) for p in plans)
+        tot_solo += solo
+        tot_batch += bat
+        flops += gflops
+        # one plane wave per body, all modes, from the batched factors; where
+        # the refinement does not converge (the system too ill-conditioned for
+        # the split-bf16 factors) the body is refactored with the complex128 LU
+        sols, gpar, gfall = [], None, 0
+        for j, (p, (curve, k0, eps1, L)) in enumerate(zip(plans, meta)):
+            rhs = torch.from_numpy(incident.rhs_modes(curve, [incident.paper_default_direction()], k0, -M, M)).cuda()
+            try:
+                sols.append(p.solve(-M, M, rhs))
+            except msv.MsvError as exc:
+                if exc.status != msv.MSV_ENOCONV:
+                    raise
+                noconv += 1
+                gfall += 1
+                pf = msv.plan_from_curve(curve, rules, k0, eps1, 1.0, m_max=M, fft_len=L, precision=0)
+                e0.record()
+                pf.factor(mats[j], 0, M)  # in place: the matrices are not needed again
+                e1.record()
+                xf = pf.solve(-M, M, rhs)
+                torch.cuda.synchronize()
+                fallback_ms += e0.elapsed_time(e1)
+                assert bool(torch.isfinite(xf).all())
+                sols.append(None)  # (kept out of the parity check below)
+                pf.close()
+                del xf
+        # the smallest body of the group against its complex128 LU
+        i = min(range(len(plans)), key=lambda j: plans[j].n)
+        if sols[i] is not None:
+            curve, k0, eps1, L = meta[i]
+            pref = msv.plan_from_curve(curve, rules, k0, eps1, 1.0, m_max=M, fft_len=L, precision=0)
+            A0 = mats[i].clone()
+            pref.factor(A0, 0, M)
+            rhs = torch.from_numpy(incident.rhs_modes(curve, [incident.paper_default_direction()], k0, -M, M)).cuda()
+            xr = pref.solve(-M, M, rhs)
+            gpar = float(((sols[i] - xr).abs().max() / xr.abs().max()).item())
+            parity.append(gpar)
+            pref.close()
+            del A0, xr
+        rows.append({"group": gi, "bodies": len(plans), "orders": [p.n for p in plans],
+                     "one_by_one_factor_ms": solo, "batched_factor_ms": bat, "speedup": solo / bat,
+                     "complex128_fallback": gfall, "parity_vs_complex128": gpar, "panel": batch.panel, "scheduled": "batched" if bat < solo else "one by one",
+                     "scheduled_tflops": gflops / (min(bat, solo) * 1e-3) / 1e12})
+        tot_sched += min(bat, solo)
+        print(f"[bodies] group {gi}: {len(plans)} bodies, orders {min(p.n for p in plans)}..{max(p.n for p in plans)}, "
+              f"one by one {solo:.1f} ms, batched {bat:.1f} ms, complex128 fallback {gfall}, parity {gpar}",
+              file=sys.stderr, flush=True)
+        del batch, sols
+        for p in plans:
+            p.close()
+        del plans, mats
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    nb = sum(r["bodies"] for r in rows)
+    return {"bodies": nb, "skipped": skipped, "groups": rows,
+            "modes_per_body": M + 1, "one_by_one_factor_ms": tot_solo, "batched_factor_ms": tot_batch,
+            "scheduled_factor_ms": tot_sched, "scheduled_tflops": flops / (tot_sched * 1e-3) / 1e12,
+            "per_mode_factorizations_per_s": nb * (M + 1) / (tot_sched * 1e-3),
+            "refinement_not_converged": noconv, "complex128_fallback_factor_ms": fallback_ms,
+            "max_parity_vs_complex128": max(parity) if parity else None}
+
+
 def serving_requests(seed, count, arrivals):
     """Mixed stream: sphere (8 panels, k0 = 1, eps 2.25, |m| <= 16), prolate
     spheroid 1:3 (16 panels, k0 = 4, eps 4), cylinder with dyadic corners
@@ -200,7 +358,8 @@ def run_form(form):
     from workloads import rules
     rls = rules.load_rules()
     if form == "batching":
-        return {"form": "batching", **bench_batching(rls)}
+        return {"form": "batching", "small_bodies": bench_batching(rls),
+                "random_bodies_all_modes": bench_batching_random_bodies(rls)}
     if form == "extinction":
         return {"form": "extinction", "precision": "complex64 LU + complex128 refinement",
                 "torus_table1": bench_extinction(rls, "torus", TABLE1_TORUS),

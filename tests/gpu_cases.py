@@ -12,7 +12,7 @@ from workloads import geometry, incident, rules
 RULES = rules.load_rules()
 
 
-def config1_curve():
+def sphere8_curve():
     return geometry.sphere(8)
 
 
