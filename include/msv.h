@@ -51,7 +51,9 @@ typedef struct msv_plan msv_plan;
  * starts and ends on the axis (south pole to north pole).  Per node: r > 0, z,
  * the outward unit normal (nr, nz) = (z', -r') (' = d/ds), and ds/du > 0.
  * Panels p and p+1 are adjacent; for closed != 0 so are n_panels-1 and 0.
- * Adjacent panels must differ in arclength by at most a factor 2.2. */
+ * Adjacent panels must differ in arclength by at most a factor 2.2.
+ * N <= 3072 (matrix order 4N <= 12288: an LU panel strip keeps its column in
+ * the registers of one 1024-thread workgroup, 12 rows per thread). */
 typedef struct {
   int32_t n_panels;
   int32_t order;            /* must be 16 */

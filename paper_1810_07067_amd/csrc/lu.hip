@@ -57,7 +57,7 @@ __device__ __forceinline__ Mz<T> mat_at(const Mats<T>& B, int z) {
 }
 
 constexpr int kPanelThreads = 1024;
-constexpr int kMaxRowsPerThread = 8;  // n <= kPanelThreads * kMaxRowsPerThread
+constexpr int kMaxRowsPerThread = 12;  // n <= kPanelThreads * kMaxRowsPerThread
 
 // One row of a strip, columns [0, W) of rowp with w valid: loaded without a
 // condition (row and column indices clamped by the caller and here) and
@@ -1434,7 +1434,10 @@ hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, int k0, h
       return hipGetLastError();
     }
     if (rows > 4 * kPanelThreads && w <= 4) {
-      hipLaunchKernelGGL((base_panel<R, 8, 4, false>), g, t, 0, s, b.d, c0, w);
+      if (rows <= 8 * kPanelThreads)
+        hipLaunchKernelGGL((base_panel<R, 8, 4, false>), g, t, 0, s, b.d, c0, w);
+      else
+        hipLaunchKernelGGL((base_panel<R, kMaxRowsPerThread, 4, false>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
   } else {
@@ -1445,8 +1448,10 @@ hipError_t panel_rec(const Batch<typename V2<R>::T>& b, int c0, int w, int k0, h
     if (rows > 2 * kPanelThreads && w <= 4) {
       if (rows <= 4 * kPanelThreads)
         hipLaunchKernelGGL((base_panel<R, 4, 4, false>), g, t, 0, s, b.d, c0, w);
-      else
+      else if (rows <= 8 * kPanelThreads)
         hipLaunchKernelGGL((base_panel<R, 8, 4, false>), g, t, 0, s, b.d, c0, w);
+      else
+        hipLaunchKernelGGL((base_panel<R, kMaxRowsPerThread, 4, false>), g, t, 0, s, b.d, c0, w);
       return hipGetLastError();
     }
   }

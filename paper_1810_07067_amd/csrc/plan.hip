@@ -300,7 +300,7 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   if (d->precision != 0 && d->precision != 1) return fail(nullptr, MSV_EINVAL, "precision must be 0 or 1");
   if (d->formulation != 0 && d->formulation != 1) return fail(nullptr, MSV_EINVAL, "formulation must be 0 or 1");
   const int N = c->n_panels * kOrder;
-  if (4 * N > 8192) return fail(nullptr, MSV_EINVAL, "4N > 8192 exceeds the LU panel kernel");
+  if (4 * N > 12288) return fail(nullptr, MSV_EINVAL, "4N > 12288 exceeds the LU panel kernel");
   for (int i = 0; i < N; ++i) {
     if (!(c->h_r[i] > 0.0)) return fail(nullptr, MSV_EINVAL, "r must be > 0 at every node");
     if (!(c->h_dsdu[i] > 0.0)) return fail(nullptr, MSV_EINVAL, "ds/du must be > 0");

@@ -5,8 +5,11 @@
               triangular solves take 8 per workgroup), a factored mode range
               that starts above 0 and single-mode solves.
   degenerate  a single azimuthal mode (m_max = 0).
-  (4N = 8192, the largest order the LU accepts, and the full-size workloads
-  are in test_gpu_fullsize.py.)
+  past 8192   orders 8768 and 12288 (the largest the plan accepts), where the
+              LU's panel strips hold 12 rows per thread: seeded matrices in
+              both precisions, the residual of each solve and the two
+              solutions against each other; N = 3088 is refused.
+  (4N = 8192 and the full-size workloads are in test_gpu_fullsize.py.)
   errors      invalid calls return EINVAL and leave the plan usable.
 """
 import numpy as np
@@ -109,3 +112,56 @@ def test_invalid_calls_raise_einval():
     # the plan still works after the errors
     x = plan.solve(-2, -1, torch.ones((2, 1, n), dtype=torch.complex128, device="cuda"))
     assert torch.isfinite(torch.view_as_real(x)).all()
+
+
+def _seeded_system(n, seed=7):
+    """Complex Gaussian entries over sqrt(n), plus 1.5 on a random permutation
+    of the diagonal positions (condition ~5, every column needs an
+    interchange), and one right-hand side."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    A = torch.randn((1, n, n), dtype=torch.complex128, device="cuda", generator=g)
+    A.mul_(1.0 / np.sqrt(n))
+    perm = torch.randperm(n, device="cuda", generator=g)
+    A[0, perm, torch.arange(n, device="cuda")] += 1.5
+    b = torch.randn((1, 1, n), dtype=torch.complex128, device="cuda", generator=g)
+    return A, b
+
+
+@pytest.mark.parametrize("n_nodes", [2192, 3072])
+def test_orders_past_8192(n_nodes):
+    """A seeded matrix of order 4 n_nodes factored with the complex64 LU +
+    refinement and with the complex128 LU: each solution's relative residual
+    (of the weighted system the solve works on) below 1e-12, the two within
+    1e-10 of each other."""
+    curve = geometry.sphere(n_nodes // 16)
+    p1 = make_plan(curve, 1.0, 2.0, 1.0, 0, 64, precision=1)
+    n = p1.n
+    assert n == 4 * n_nodes
+    A, b = _seeded_system(n)
+    # the library solves the L2-weighted system: sqrt(w) x from sqrt(w) b
+    sw = torch.from_numpy(l2w(curve)).cuda()
+    rel = lambda M, x: (torch.linalg.vector_norm(sw * b[0, 0] - M[0] @ (sw * x[0, 0]))
+                        / torch.linalg.vector_norm(sw * b[0, 0])).item()
+    p1.factor(A, 0, 0)  # complex64 factors of their own; A is kept
+    x1 = p1.solve(0, 0, b)
+    r1 = rel(A, x1)
+    print(f"[order {n}] complex64 + refinement: residual {r1:.3e} after {p1.last_ir_iterations()} steps",
+          flush=True)
+    p1.close()
+    p0 = make_plan(curve, 1.0, 2.0, 1.0, 0, 64, precision=0)
+    p0.factor(A, 0, 0)  # the complex128 LU factors A in place
+    x0 = p0.solve(0, 0, b)
+    p0.close()
+    A, _ = _seeded_system(n)
+    r0 = rel(A, x0)
+    d = (torch.linalg.vector_norm(x0 - x1) / torch.linalg.vector_norm(x0)).item()
+    print(f"[order {n}] complex128: residual {r0:.3e}; the solutions differ by {d:.3e}", flush=True)
+    assert r1 < 1e-12 and r0 < 1e-12, (r1, r0)
+    assert d < 1e-10, d
+
+
+def test_order_past_12288_is_refused():
+    with pytest.raises(msv.MsvError) as exc:
+        make_plan(geometry.sphere(193), 1.0, 2.0, 1.0, 0, 64)
+    assert exc.value.status == msv.MSV_EINVAL
