@@ -276,7 +276,55 @@ TABLE2_STARFISH = [(5, 2, 10, 224, 1.24e-9), (5, 10, 16, 304, 3.44e-10), (5, 20,
                    (10, 5, 13, 304, 2.04e-10), (10, 20, 21, 464, 9.74e-10), (10, 40, 30, 784, 1.45e-8),
                    (20, 5, 13, 464, 1.05e-10), (20, 10, 16, 464, 4.41e-10), (20, 40, 30, 784, 4.60e-9),
                    (40, 5, 13, 784, 3.39e-10), (40, 10, 16, 784, 3.58e-9), (40, 20, 21, 784, 3.01e-9)]
+TABLE3_DROPLET = [(5, 2, 7, 224, 2.71e-10), (5, 10, 10, 320, 1.86e-9), (5, 20, 11, 480, 5.11e-9),
+                  (10, 5, 9, 320, 1.24e-10), (10, 20, 11, 480, 2.59e-9), (10, 40, 14, 800, 6.76e-9),
+                  (20, 5, 9, 480, 5.81e-10), (20, 10, 10, 480, 1.31e-10), (20, 40, 14, 800, 3.43e-9),
+                  (40, 5, 9, 800, 3.48e-10), (40, 10, 10, 800, 6.12e-10), (40, 20, 12, 800, 1.45e-10)]
+TABLE4_CYLINDER = [(2, 1, 9, 1312, 4.11e-9), (2, 5, 11, 1440, 2.56e-8), (2, 10, 14, 1696, 9.32e-7),
+                   (5, 2, 10, 1440, 1.54e-8), (5, 10, 14, 1696, 5.92e-8), (5, 20, 17, 2208, 9.74e-7),
+                   (10, 2, 10, 1696, 1.91e-8), (10, 5, 11, 1696, 3.95e-8), (10, 20, 17, 2208, 2.24e-6),
+                   (20, 2, 10, 2208, 3.54e-8), (20, 5, 11, 2208, 1.39e-7), (20, 10, 14, 2208, 1.32e-7)]
 LOOP = dict(center=[0.4, 0.5, 5.0], radius=0.42)  # Section 6
+CYLINDER_CORNER_LEVELS = 14  # corner panels of 1/(base panels per unit)/2^14, about 1e-5 (Example 4)
+CYLINDER_MAX_LEVELS = 24     # the deepest corner grading the full-size cylinder checks (7.45e-9 panels)
+
+
+def cylinder_split(npts, k):
+    """Base panels per unit length and corner levels for a cylinder of about
+    npts nodes: base panels no longer than half a wavelength at wavenumber k
+    (at least 2 per unit), every other panel spent on dyadic corner levels
+    (at most CYLINDER_MAX_LEVELS), the base panels then filling the rest."""
+    npan = npts // 16
+    p_min = max(2.0, k / np.pi)
+    levels = int(min(CYLINDER_MAX_LEVELS, (npan - 4 * p_min) // 4))
+    base = lambda q: sum(max(1, int(round(ln * q))) for ln in (1.0, 2.0, 1.0))  # as geometry.polygon
+    p = npan / 4 - levels
+    while base(p) + 4 * levels > npan:
+        p -= 0.25
+    return p, levels
+
+
+def extinction_body(body, npts, k=None):
+    """The generating curve of Tables 1-4 with about npts nodes (16 per panel).
+    For the cylinder with k given, the nodes go to the corners as far as
+    cylinder_split allows; without k, the corner panels end near 1e-5 as in
+    Example 4."""
+    from workloads import geometry
+    npan = npts // 16
+    if body == "torus":
+        return geometry.torus(npan)
+    if body == "starfish":
+        return geometry.starfish(npan)
+    if body == "droplet":
+        return geometry.droplet(npan)
+    if body == "cylinder":
+        # 4 p base panels over the perimeter (bottom 1, side 2, top 1) and the
+        # four corner panels split `levels` times each
+        if k is None:
+            return geometry.cylinder(CYLINDER_CORNER_LEVELS, npan / 4 - CYLINDER_CORNER_LEVELS)
+        p, levels = cylinder_split(npts, k)
+        return geometry.cylinder(levels, p)
+    raise ValueError(body)
 
 
 def _interior_points(body, rng, P):
@@ -285,18 +333,31 @@ def _interior_points(body, rng, P):
         ph, th = rng.uniform(0, 2 * np.pi, P), rng.uniform(0, 2 * np.pi, P)
         rr, zz = 2 + rho * np.cos(ph), 0.5 * rho * np.sin(ph)
         return np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
-    v = rng.standard_normal((P, 3))  # the starfish contains the ball of radius 1.5
-    return v / np.linalg.norm(v, axis=1)[:, None] * rng.uniform(0, 0.75, (P, 1))
+    th = rng.uniform(0, 2 * np.pi, P)
+    if body == "starfish":  # the starfish contains the ball of radius 1.5
+        v = rng.standard_normal((P, 3))
+        return v / np.linalg.norm(v, axis=1)[:, None] * rng.uniform(0, 0.75, (P, 1))
+    if body == "droplet":  # z increases along the curve: (s r(t), z(t)) lies inside for s < 1
+        t = rng.uniform(0.6, 0.9, P)
+        sc = rng.uniform(0.0, 0.5, P)
+        rr = sc * np.sin(np.pi * t) * np.cos(0.5 * np.pi * (t - 1.5))
+        zz = np.sin(np.pi * t) * np.sin(0.5 * np.pi * (t - 1.5)) + 0.5
+        return np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+    if body == "cylinder":
+        rr, zz = 0.5 * np.sqrt(rng.uniform(0, 1, P)), rng.uniform(-0.5, 0.5, P)
+        return np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+    raise ValueError(body)
 
 
-def bench_extinction(rules, body, rows, precision=1, seed=3, n_points=6):
+def bench_extinction(rules, body, rows, precision=1, seed=3, n_points=6, corner_first=False):
     """The accuracy experiment of Section 6 on the GPU: the indirect system
     (eq. dualmullrep) with the current-loop data of eq. loop, at the sizes of
-    Tables 1 (torus) and 2 (rotated starfish); E_error over random interior
+    Tables 1-4 (torus, rotated starfish, droplet, cylinder); E_error over random interior
     points (eq. interior_dual, evaluated on 4 sub-panels per panel) and the
     four phases of the tables: T_kernel
     (tabulation), T_matgen (assembly), T_solve (factor and solve all modes),
-    T_add (one more right-hand side)."""
+    T_add (one more right-hand side).  corner_first: the cylinder's nodes go
+    to the corners first (cylinder_split) instead of the paper's 1e-5 grading."""
     import time
 
     import torch
@@ -304,11 +365,12 @@ def bench_extinction(rules, body, rows, precision=1, seed=3, n_points=6):
     from workloads import geometry, incident
     out = []
     for k0, k1, Nf, npts, paper_err in rows:
-        curve = geometry.torus(npts // 16) if body == "torus" else geometry.starfish(npts // 16)
+        curve = extinction_body(body, npts, max(k0, k1) if corner_first else None)
         eps1 = (k1 / k0) ** 2
         L = valid_fft_len(curve, k0, eps1, Nf)
-        rhs = torch.from_numpy(incident.loop_rhs_modes(curve, LOOP["center"], LOOP["radius"], k1, k0, 1.0,
-                                                       -Nf, Nf)).cuda()
+        rhs_h = incident.loop_rhs_modes(curve, LOOP["center"], LOOP["radius"], k1, k0, 1.0, -Nf, Nf)
+        tail = float(np.abs(rhs_h[[0, -1]]).max() / np.abs(rhs_h).max())  # data beyond N_f
+        rhs = torch.from_numpy(rhs_h).cuda()
         pts = _interior_points(body, np.random.default_rng(seed), n_points)
 
         def phase(fn):
@@ -343,7 +405,8 @@ def bench_extinction(rules, body, rows, precision=1, seed=3, n_points=6):
         E, H = E[0].cpu().numpy(), H[0].cpu().numpy()
         err = np.sqrt((np.linalg.norm(E - Er) ** 2 + np.linalg.norm(H - Hr) ** 2)
                       / (np.linalg.norm(Er) ** 2 + np.linalg.norm(Hr) ** 2))
-        out.append({"k0": k0, "k1": k1, "N_f": Nf, "N_pts": npts, "L": L, "T_kernel_s": t_kernel,
+        out.append({"k0": k0, "k1": k1, "N_f": Nf, "N_pts": curve.n, "paper_N_pts": npts, "L": L,
+                    "data_tail": tail, "smallest_panel": float(curve.panel_len.min()), "T_kernel_s": t_kernel,
                     "T_matgen_s": t_matgen, "T_solve_s": t_solve, "T_add_s": t_add, "E_error": float(err),
                     "paper_E_error": paper_err, "precision": used,
                     "ir_iterations": plan.last_ir_iterations() if used else 0})
@@ -363,7 +426,10 @@ def run_form(form):
     if form == "extinction":
         return {"form": "extinction", "precision": "complex64 LU + complex128 refinement",
                 "torus_table1": bench_extinction(rls, "torus", TABLE1_TORUS),
-                "starfish_table2": bench_extinction(rls, "starfish", TABLE2_STARFISH)}
+                "starfish_table2": bench_extinction(rls, "starfish", TABLE2_STARFISH),
+                "droplet_table3": bench_extinction(rls, "droplet", TABLE3_DROPLET),
+                "cylinder_table4": bench_extinction(rls, "cylinder", TABLE4_CYLINDER, corner_first=True),
+                "cylinder_table4_panels_to_1e-5": bench_extinction(rls, "cylinder", TABLE4_CYLINDER)}
     return {"form": "serving", "complex64_lu_refined": bench_serving(rls, 1), "complex128_lu": bench_serving(rls, 0)}
 
 

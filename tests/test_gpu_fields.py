@@ -17,6 +17,10 @@
                      currents equal to the oracle's to max(1e-10, 4 sens)
                      (L2-weighted), sens being the oracle's own change under
                      1e-14 kernel noise.
+  droplet, cylinder  the same test at the sizes of the first rows of Tables 3
+                     and 4 (a conical point on the axis; edges with corner
+                     panels near 1e-5), E_error below the printed values; the
+                     droplet's currents also against the oracle's.
   extinction theorem for the direct system on the sphere: the exterior
                      representation evaluated inside is -E_inc (3e-9, the
                      oracle's own floor on this body).
@@ -28,6 +32,7 @@ from gpu_cases import RULES, oracle_setup, oracle_table
 from oracle import assemble as oasm
 from oracle import farfield, fields
 from oracle import solve as osolve
+from oracle.modal import KernelParams
 from workloads import geometry, incident
 
 torch = pytest.importorskip("torch")
@@ -154,6 +159,78 @@ def test_extinction_at_the_paper_size():
     err = e_error(E[0].cpu().numpy(), H[0].cpu().numpy(), El(pts), Hl(pts))
     print(f"[extinction] 64 points, upsample 4: E_error {err:.3e}", flush=True)
     assert err < 2.32e-9, err
+
+
+def _loop_solve(curve, k0, k1, M, L, precision):
+    """Tabulate, assemble, factor and solve the indirect system for the loop
+    data; complex64 factors whose refinement does not converge fall back to
+    complex128, as the extinction form does."""
+    eps1 = (k1 / k0) ** 2
+    rhs = torch.from_numpy(incident.loop_rhs_modes(curve, LOOP["center"], LOOP["radius"], k1, k0, 1.0,
+                                                   -M, M)).cuda()
+    for prec in (precision, 0):
+        plan = _plan(curve, k0, eps1, 1.0, M, L, precision=prec, formulation=1)
+        A = plan.assemble(plan.tabulate(), 0, M)
+        plan.factor(A, 0, M)
+        try:
+            return plan, plan.solve(-M, M, rhs), rhs
+        except msv.MsvError as exc:
+            if exc.status != msv.MSV_ENOCONV or prec == 0:
+                raise
+            print("[extinction] refinement did not converge: complex128 LU", flush=True)
+            plan.close()
+
+
+def droplet_points(rng, P):
+    t = rng.uniform(0.6, 0.9, P)
+    sc = rng.uniform(0.0, 0.5, P)
+    th = rng.uniform(0, 2 * np.pi, P)
+    rr = sc * np.sin(np.pi * t) * np.cos(0.5 * np.pi * (t - 1.5))
+    zz = np.sin(np.pi * t) * np.sin(0.5 * np.pi * (t - 1.5)) + 0.5
+    return np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+
+
+def test_extinction_droplet():
+    """Table 3's first row: k0 = 5, k1 = 2, N_f = 7, 224 points (14 panels,
+    five dyadic levels at the tip); printed E_error 2.71e-10."""
+    curve, k0, k1, M, L = geometry.droplet(14), 5.0, 2.0, 7, 64
+    sup, kp = oracle_setup(curve, k0, (k1 / k0) ** 2, M, L)
+    while not kp.valid:
+        L *= 2
+        sup, kp = oracle_setup(curve, k0, (k1 / k0) ** 2, M, L)
+    tab = oracle_table(curve, sup, kp)
+    w = geometry.gl_weights(curve)
+    args = (k0, kp.k1, k0, 1.0, 1.0, (k1 / k0) ** 2, 1.0, w)
+    mats = [oasm.assemble_mode(curve, sup, tab, m, *args, formulation="indirect") for m in range(M + 1)]
+    plan, x, rhs = _loop_solve(curve, k0, k1, M, L, 1)
+    xo = osolve.solve_modes(mats, w, rhs.cpu().numpy(), -M, M)
+    sw = np.sqrt(np.repeat(w, 4))
+    cur = np.linalg.norm(sw * (x.cpu().numpy() - xo)) / np.linalg.norm(sw * xo)
+    pts = droplet_points(np.random.default_rng(3), 6)
+    E, H = plan.fields(-M, M, x, pts, "interior", upsample=4)
+    El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], k1, k0, 1.0)
+    err = e_error(E[0].cpu().numpy(), H[0].cpu().numpy(), El(pts), Hl(pts))
+    print(f"[extinction] droplet 224 points: E_error {err:.3e}, currents vs oracle {cur:.3e}", flush=True)
+    assert cur < 1e-10, cur
+    assert err < 2.71e-10, err
+
+
+def test_extinction_cylinder():
+    """Table 4's first row: k0 = 2, k1 = 1, N_f = 9, about 1312 points (81
+    panels: 26 base panels, the four corner panels refined 14 levels down to
+    about 1e-5); printed E_error 4.11e-9."""
+    curve, k0, k1, M, L = geometry.cylinder(14, 6.5), 2.0, 1.0, 9, 64
+    while not KernelParams(k0, k1, M, L, float(curve.r.max())).valid:
+        L *= 2
+    plan, x, _ = _loop_solve(curve, k0, k1, M, L, 1)
+    rng = np.random.default_rng(3)
+    rr, zz, th = 0.5 * np.sqrt(rng.uniform(0, 1, 6)), rng.uniform(-0.5, 0.5, 6), rng.uniform(0, 2 * np.pi, 6)
+    pts = np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+    E, H = plan.fields(-M, M, x, pts, "interior", upsample=4)
+    El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], k1, k0, 1.0)
+    err = e_error(E[0].cpu().numpy(), H[0].cpu().numpy(), El(pts), Hl(pts))
+    print(f"[extinction] cylinder {curve.n} points: E_error {err:.3e}", flush=True)
+    assert err < 4.11e-9, err
 
 
 @pytest.fixture(scope="module")

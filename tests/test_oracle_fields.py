@@ -10,6 +10,9 @@
 * The extinction theorem for the direct system (eq. mullerrep): with the
   currents of a plane-wave solve, the exterior representation evaluated inside
   the body is -E_inc, and the interior representation evaluated outside is 0.
+* The same test on the droplet of Example 3 (a conical point on the axis,
+  dyadically refined toward it) at the size of Table 3's first row, below the
+  2.71e-10 printed there.
 * Mode parity A_{-m} = D A_m D also for the indirect system.
 A dropped term or a wrong sign in any weight of the indirect blocks, the jump
 terms, the representations or the loop field breaks one of these."""
@@ -171,3 +174,31 @@ def test_extinction_at_the_paper_size():
     assert err < 2.32e-9, err
     E1, H1 = fields.fields(curve, w, x, -M, pts, k0, k1, omega, 1.0, 1.0, eps1, mu1, "interior", "indirect")
     assert e_error(E1, H1, El(pts), Hl(pts)) > 10 * err
+
+
+def droplet_points(rng, P):
+    """Random points inside the droplet of Example 3: z grows along its
+    generating curve, so (s r(t), z(t)) lies inside for 0 <= s < 1."""
+    t = rng.uniform(0.6, 0.9, P)
+    sc = rng.uniform(0.0, 0.5, P)
+    th = rng.uniform(0, 2 * np.pi, P)
+    rr = sc * np.sin(np.pi * t) * np.cos(0.5 * np.pi * (t - 1.5))
+    zz = np.sin(np.pi * t) * np.sin(0.5 * np.pi * (t - 1.5)) + 0.5
+    return np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+
+
+def test_extinction_droplet():
+    """Table 3's first row (k0 = 5, k1 = 2, N_f = 7, 224 points): 14 panels,
+    the last of them five dyadic levels deep at the tip; E_error below the
+    printed 2.71e-10 (measured 2.1e-11)."""
+    curve = geometry.droplet(14)
+    k0, eps1, mu1, M = 5.0, 0.16, 1.0, 7
+    sup, tab, w, mats, k1, omega = _setup(curve, k0, eps1, mu1, M, "indirect")
+    rhs = incident.loop_rhs_modes(curve, LOOP["center"], LOOP["radius"], k1, omega, mu1, -M, M)
+    assert np.abs(rhs[[0, -1]]).max() < 1e-11 * np.abs(rhs).max()  # N_f = 7 resolves the data
+    x = solve.solve_modes(mats, w, rhs, -M, M)[:, 0]
+    pts = droplet_points(np.random.default_rng(3), 6)
+    El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], k1, omega, mu1)
+    E, H = fields.fields(curve, w, x, -M, pts, k0, k1, omega, 1.0, 1.0, eps1, mu1, "interior", "indirect")
+    err = e_error(E, H, El(pts), Hl(pts))
+    assert err < 2.71e-10, err

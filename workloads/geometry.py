@@ -113,6 +113,26 @@ def starfish(n_panels: int) -> Curve:
     return _from_panels("starfish", panels, False, {"kind": "starfish"})
 
 
+def droplet(n_panels: int, tip_levels: int = 5) -> Curve:
+    """The droplet of Example 3: r = sin(pi t) cos(pi (t - 3/2)/2),
+    z = sin(pi t) sin(pi (t - 3/2)/2) + 1/2, t in [1/2, 1] (pole to pole), with
+    a conical point on the axis at t = 1.  n_panels - tip_levels equal panels
+    in t, the one ending at t = 1 refined dyadically tip_levels times toward it."""
+    def f(t):
+        s, c = np.sin(np.pi * t), np.cos(np.pi * t)
+        a = 0.5 * np.pi * (t - 1.5)
+        sa, ca = np.sin(a), np.cos(a)
+        return (s * ca, s * sa + 0.5, np.pi * c * ca - 0.5 * np.pi * s * sa,
+                np.pi * c * sa + 0.5 * np.pi * s * ca)
+    nb = n_panels - tip_levels
+    if nb < 1:
+        raise ValueError("droplet needs more panels than tip levels")
+    edges = np.linspace(0.5, 1.0, nb + 1)
+    cuts = np.concatenate([edges[:-1], _dyadic(edges[-2], 1.0, tip_levels, True)[1:]])
+    panels = [(lo, hi, f) for lo, hi in zip(cuts[:-1], cuts[1:])]
+    return _from_panels("droplet", panels, False, {"kind": "droplet", "tip_levels": tip_levels})
+
+
 def _segment(p0, p1):
     p0 = np.asarray(p0, float)
     p1 = np.asarray(p1, float)
@@ -168,11 +188,12 @@ def polygon(vertices, panels_per_unit: float, corner_levels: int, name: str) -> 
     return _from_panels(name, panels, False, {"kind": "polygon", "vertices": vertices})
 
 
-def cylinder(corner_levels: int = 24) -> Curve:
-    """Cylinder of radius 1, height 2 (vertices of Example 4), 32 base panels of
-    length 0.125, the four corner-adjacent base panels refined toward the edges."""
+def cylinder(corner_levels: int = 24, panels_per_unit: float = 8.0) -> Curve:
+    """Cylinder of radius 1, height 2 (vertices of Example 4), base panels of
+    length about 1/panels_per_unit (32 of 0.125 by default), the four
+    corner-adjacent base panels refined toward the edges."""
     v = [(0.0, -1.0), (1.0, -1.0), (1.0, 1.0), (0.0, 1.0)]
-    return polygon(v, 8.0, corner_levels, "cylinder")
+    return polygon(v, panels_per_unit, corner_levels, "cylinder")
 
 
 def random_body(rng: np.random.Generator, n_panels: int, tip_levels: int = 0) -> Curve:
