@@ -99,6 +99,28 @@ typedef struct {
                                 i w mu0 (n x E_inc), in (t, e_theta) components */
 } msv_desc;
 
+/* Device memory for the library's own buffers (plan geometry and workspace,
+ * LU factors and inverses, solve workspace, batch lists).  By default the
+ * library calls hipMalloc and hipFree.  A caller that runs its own pool of
+ * device memory (a framework's caching allocator, a serving process that
+ * recycles the memory of evicted bodies instead of returning it to the
+ * driver) passes `alloc` and `free_fn`: alloc(bytes, device, ctx) returns
+ * device memory of at least `bytes` on `device` (the current device), or
+ * NULL when it cannot (the call then fails with MSV_ENOMEM);
+ * free_fn(ptr, device, ctx) takes it back.  Inside a stream-ordered call
+ * (storage regrown for more modes) the library waits for the device, as
+ * hipFree does, before it hands a buffer back.  msv_plan_destroy does not
+ * wait: with a pool the caller must have waited for the plan's last call
+ * (synchronized its stream) before destroying it, so that destroying one
+ * plan does not stall work on other streams.  Both hooks or neither
+ * (NULL, NULL restores hipMalloc / hipFree); they may be changed only while
+ * no plan or batch exists (MSV_EINVAL otherwise), and they are called from
+ * the thread that makes the msv call.  Not part of the paper's method: the
+ * memory management of a long-running process. */
+typedef void *(*msv_alloc_fn)(size_t bytes, int32_t device, void *ctx);
+typedef void (*msv_free_fn)(void *ptr, int32_t device, void *ctx);
+msv_status msv_set_allocator(msv_alloc_fn alloc, msv_free_fn free_fn, void *ctx);
+
 /* Validate the inputs, upload the geometry, build the near-panel support
  * nodes and the pair classification.  Synchronizes `stream` once. */
 msv_status msv_plan_create(msv_plan **out, const msv_curve *curve, const msv_rules *rules,

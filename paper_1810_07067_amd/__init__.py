@@ -22,7 +22,7 @@ EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nod
            "msv_num_support", "msv_table_entries", "msv_matrix_order", "msv_tabulate",
            "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations",
            "msv_batch_create", "msv_batch_factor", "msv_batch_destroy", "msv_batch_last_error",
-           "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes",
+           "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes", "msv_set_allocator",
            "msv_tabulate_rows", "msv_assemble_rows", "msv_solve_noalloc", "msv_solve_noalloc_max_bytes",
            "msv_far_field", "msv_fields"]
 
@@ -116,8 +116,47 @@ def load_library(path: str = LIB_PATH):
     lib.msv_workspace_bytes.restype = ctypes.c_size_t
     lib.msv_plan_device_bytes.argtypes = [P]
     lib.msv_plan_device_bytes.restype = ctypes.c_size_t
+    lib.msv_set_allocator.argtypes = [P, P, P]
+    lib.msv_set_allocator.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p)
+_hooks = None  # the registered callbacks, kept alive while the library may call them
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's own device allocations through torch's caching
+    allocator (msv_set_allocator), or back to hipMalloc / hipFree.  Every block
+    is taken on the device's default stream, so that memory a destroyed plan
+    gives back can serve any later plan or tensor allocated there.  Raises
+    MsvError while plans or batches exist."""
+    global _hooks
+    lib = load_library()
+    if not enable:
+        st = lib.msv_set_allocator(None, None, None)
+        if st:
+            raise MsvError(st, lib.msv_last_error(None).decode())
+        _hooks = None
+        return
+    import torch
+
+    def alloc(nbytes, device, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), int(device),
+                                                      torch.cuda.default_stream(int(device)))
+        except RuntimeError:  # out of memory: the library reports MSV_ENOMEM
+            return None
+
+    def free(ptr, device, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+    hooks = (_ALLOC_FN(alloc), _FREE_FN(free))
+    st = lib.msv_set_allocator(ctypes.cast(hooks[0], ctypes.c_void_p), ctypes.cast(hooks[1], ctypes.c_void_p), None)
+    if st:
+        raise MsvError(st, lib.msv_last_error(None).decode())
+    _hooks = hooks
 
 
 def _c(z):
@@ -160,8 +199,21 @@ class Plan:
         self.formulation = int(formulation)
         self._factored = None
 
-    def close(self):
+    def _sh(self, stream):
+        """The call's stream handle; the stream is remembered for close()."""
+        import torch
+        self._last_stream = stream if stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(self._last_stream.cuda_stream)
+
+    def close(self, wait=True):
+        """Destroy the plan.  With a caller pool the library does not wait at
+        destroy: the plan's last call must have finished, which close() makes
+        sure of by synchronizing that call's stream unless the caller knows
+        it has (wait=False)."""
         if getattr(self, "_h", None) and self._h.value:
+            last = getattr(self, "_last_stream", None)
+            if wait and _hooks is not None and last is not None:
+                last.synchronize()
             self.lib.msv_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -196,7 +248,7 @@ class Plan:
             out = torch.empty(self.table_shape, dtype=torch.complex128, device="cuda")
         assert out.dtype == torch.complex128 and out.is_cuda and out.is_contiguous()
         self._check(self.lib.msv_tabulate(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(),
-                                          _stream_handle(stream)))
+                                          self._sh(stream)))
         return out
 
     def table_rows_shape(self, nt):
@@ -208,7 +260,7 @@ class Plan:
             out = torch.empty(self.table_rows_shape(nt), dtype=torch.complex128, device="cuda")
         assert out.dtype == torch.complex128 and out.is_cuda and out.is_contiguous()
         self._check(self.lib.msv_tabulate_rows(self._h, int(t0), int(nt), ctypes.c_void_p(out.data_ptr()),
-                                               out.numel(), _stream_handle(stream)))
+                                               out.numel(), self._sh(stream)))
         return out
 
     def assemble_rows(self, kern, t0, nt, m_lo, m_hi, out, stream=None):
@@ -218,7 +270,7 @@ class Plan:
         assert kern.is_contiguous() and tuple(kern.shape) == self.table_rows_shape(nt)
         self._check(self.lib.msv_assemble_rows(self._h, ctypes.c_void_p(kern.data_ptr()), int(t0), int(nt),
                                                int(m_lo), int(m_hi), ctypes.c_void_p(out.data_ptr()),
-                                               _stream_handle(stream)))
+                                               self._sh(stream)))
         return out
 
     def assemble_streamed(self, m_lo, m_hi, out=None, rows_per_block=None, block=None, stream=None):
@@ -246,13 +298,13 @@ class Plan:
         assert out.dtype == torch.complex128 and out.is_contiguous() and out.shape == (nm, self.n, self.n)
         assert kern.is_contiguous() and tuple(kern.shape) == self.table_shape
         self._check(self.lib.msv_assemble(self._h, ctypes.c_void_p(kern.data_ptr()), int(m_lo), int(m_hi),
-                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+                                          ctypes.c_void_p(out.data_ptr()), self._sh(stream)))
         return out
 
     def factor(self, A, m_lo, m_hi, stream=None):
         assert A.is_contiguous() and A.shape == (m_hi - m_lo + 1, self.n, self.n)
         self._check(self.lib.msv_factor(self._h, ctypes.c_void_p(A.data_ptr()), int(m_lo), int(m_hi),
-                                        _stream_handle(stream)))
+                                        self._sh(stream)))
         self._factored = A  # the library keeps using this buffer
         return A
 
@@ -265,7 +317,7 @@ class Plan:
             out = torch.empty_like(rhs)
         self._check(self.lib.msv_solve(self._h, int(m_lo), int(m_hi), int(rhs.shape[1]),
                                        ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                       _stream_handle(stream)))
+                                       self._sh(stream)))
         return out
 
 
@@ -278,7 +330,7 @@ class Plan:
         assert rhs.shape[2] == self.n and out.shape == rhs.shape and out.is_contiguous()
         self._check(self.lib.msv_solve_noalloc(self._h, int(m_lo), int(m_hi), int(rhs.shape[1]),
                                                ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                               _stream_handle(stream)))
+                                               self._sh(stream)))
         return out
 
 
@@ -294,7 +346,7 @@ class Plan:
         self._check(self.lib.msv_far_field(self._h, int(m_lo), int(m_hi), int(x.shape[1]),
                                            ctypes.c_void_p(x.data_ptr()), int(dirs.shape[0]),
                                            ctypes.c_void_p(dirs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                           _stream_handle(stream)))
+                                           self._sh(stream)))
         return out
 
     def fields(self, m_lo, m_hi, x, points, region, upsample=1, stream=None):
@@ -313,7 +365,7 @@ class Plan:
                                         ctypes.c_void_p(x.data_ptr()), int(pts.shape[0]),
                                         ctypes.c_void_p(pts.data_ptr()), reg, int(upsample),
                                         ctypes.c_void_p(E.data_ptr()),
-                                        ctypes.c_void_p(H.data_ptr()), _stream_handle(stream)))
+                                        ctypes.c_void_p(H.data_ptr()), self._sh(stream)))
         return E, H
 
 

@@ -84,6 +84,63 @@ struct msv_plan {
 
 static thread_local std::string g_create_err;
 
+// Device memory of the library's own buffers: hipMalloc / hipFree, or the
+// caller's pool when one is set (msv_set_allocator).  The hook may change
+// only while no plan or batch exists, so every buffer goes back to the
+// allocator that gave it.
+namespace {
+std::mutex g_alloc_mu;
+msv_alloc_fn g_alloc = nullptr;
+msv_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+int g_live = 0;  // plans and batches alive (under g_alloc_mu)
+
+hipError_t dev_alloc(void** ptr, size_t bytes) {
+  msv_alloc_fn a;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> l(g_alloc_mu);
+    a = g_alloc;
+    ctx = g_alloc_ctx;
+  }
+  if (!a) return hipMalloc(ptr, bytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  *ptr = a(bytes, dev, ctx);
+  return *ptr ? hipSuccess : hipErrorOutOfMemory;
+}
+
+// hipFree waits for the device.  A buffer given back to a pool inside a
+// stream-ordered call (storage regrown for more modes) may still be touched
+// by queued work, so the same wait comes first there (wait = true).  A plan
+// being destroyed has no work left in flight: with a pool the caller has
+// waited for its last call (see msv_set_allocator), and no device-wide wait
+// holds up the other streams.
+void dev_free(void* ptr, bool wait = true) {
+  msv_free_fn f;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> l(g_alloc_mu);
+    f = g_free;
+    ctx = g_alloc_ctx;
+  }
+  if (!f) {
+    (void)hipFree(ptr);
+    return;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (wait) (void)hipDeviceSynchronize();
+  f(ptr, dev, ctx);
+}
+
+void live_add(int d) {
+  std::lock_guard<std::mutex> l(g_alloc_mu);
+  g_live += d;
+}
+}  // namespace
+
 // Per-device address of `scratch`, resolved once per device with that device
 // current.
 namespace {
@@ -168,7 +225,7 @@ void lagrange_row(const std::vector<double>& xn, const std::vector<double>& bw, 
 template <typename T>
 msv_status upload(msv_plan* p, T** dst, const T* src, size_t count) {
   if (count == 0) return MSV_OK;
-  if (hipMalloc(dst, sizeof(T) * count) != hipSuccess) return fail(p, MSV_ENOMEM, "hipMalloc failed");
+  if (dev_alloc((void**)dst, sizeof(T) * count) != hipSuccess) return fail(p, MSV_ENOMEM, "hipMalloc failed");
   p->geom_bytes += sizeof(T) * count;
   if (hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice) != hipSuccess)
     return fail(p, MSV_EHIP, "hipMemcpy failed");
@@ -202,6 +259,16 @@ int bandwidth(double kmax, double rmax) {
 
 extern "C" {
 
+msv_status msv_set_allocator(msv_alloc_fn alloc, msv_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) return fail(nullptr, MSV_EINVAL, "give both hooks or neither");
+  std::lock_guard<std::mutex> l(g_alloc_mu);
+  if (g_live > 0) return fail(nullptr, MSV_EINVAL, "plans or batches exist: destroy them first");
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_alloc_ctx = alloc ? ctx : nullptr;
+  return MSV_OK;
+}
+
 const char* msv_last_error(const msv_plan* p) { return p ? p->err.c_str() : g_create_err.c_str(); }
 int32_t msv_num_nodes(const msv_plan* p) { return p ? p->N : 0; }
 int32_t msv_num_support(const msv_plan* p) { return p ? p->S : 0; }
@@ -216,8 +283,9 @@ static void plan_free(msv_plan* p) {
                   p->d_lag_adj, p->d_left, p->d_right, p->d_cls, p->d_near, p->d_fac32, p->d_ipiv,
                   p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_work, p->d_spec, p->d_tabs, p->d_up};
   for (void* b : bufs)
-    if (b) (void)hipFree(b);
+    if (b) dev_free(b, false);
   delete p;
+  live_add(-1);
 }
 
 // Device bytes of the factor storage for nb modes of order n.
@@ -309,6 +377,7 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   }
 
   msv_plan* p = new msv_plan();
+  live_add(1);
   p->N = N;
   p->npan = c->n_panels;
   p->closed = c->closed ? 1 : 0;
@@ -575,7 +644,7 @@ msv_status msv_plan_create(msv_plan** out, const msv_curve* c, const msv_rules* 
   p->spec_cap = std::min(p->n_near, msv::kSpecCap);
   if (p->spec_cap > 0) {
     const size_t sb = msv::spec_bytes(p->L, p->n_near);
-    if (hipMalloc(&p->d_spec, sb) != hipSuccess) {
+    if (dev_alloc((void**)&p->d_spec, sb) != hipSuccess) {
       msv_plan_destroy(p);
       return fail(nullptr, MSV_ENOMEM, "spectra scratch allocation failed");
     }
@@ -704,41 +773,41 @@ static msv_status factor_buffers(msv_plan* p, int n, int nb) {
     return MSV_OK;
   }
   if ((size_t)nb * n > p->ipiv_elems) {
-    if (p->d_ipiv) (void)hipFree(p->d_ipiv);
-    if (p->d_info) (void)hipFree(p->d_info);
-    if (p->d_perm) (void)hipFree(p->d_perm);
+    if (p->d_ipiv) dev_free(p->d_ipiv);
+    if (p->d_info) dev_free(p->d_info);
+    if (p->d_perm) dev_free(p->d_perm);
     p->d_ipiv = nullptr;
     p->d_info = nullptr;
     p->d_perm = nullptr;
     p->ipiv_elems = 0;
-    if (hipMalloc(&p->d_ipiv, sizeof(int32_t) * (size_t)nb * n) != hipSuccess ||
-        hipMalloc(&p->d_perm, sizeof(int32_t) * (size_t)nb * n) != hipSuccess ||
-        hipMalloc(&p->d_info, sizeof(int32_t) * nb) != hipSuccess)
+    if (dev_alloc((void**)&p->d_ipiv, sizeof(int32_t) * (size_t)nb * n) != hipSuccess ||
+        dev_alloc((void**)&p->d_perm, sizeof(int32_t) * (size_t)nb * n) != hipSuccess ||
+        dev_alloc((void**)&p->d_info, sizeof(int32_t) * nb) != hipSuccess)
       return fail(p, MSV_ENOMEM, "pivot allocation failed");
     p->ipiv_elems = (size_t)nb * n;
   }
   const size_t luw_bytes = msv::lu_work_bytes(n, nb, p->precision == 0);
   if (luw_bytes > p->luw_bytes) {
-    if (p->d_luw) (void)hipFree(p->d_luw);
+    if (p->d_luw) dev_free(p->d_luw);
     p->d_luw = nullptr;
     p->luw_bytes = 0;
-    if (hipMalloc(&p->d_luw, luw_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "LU workspace allocation failed");
+    if (dev_alloc((void**)&p->d_luw, luw_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "LU workspace allocation failed");
     p->luw_bytes = luw_bytes;
   }
   if (p->precision == 1 && (size_t)nb * nn > p->fac32_elems) {
-    if (p->d_fac32) (void)hipFree(p->d_fac32);
+    if (p->d_fac32) dev_free(p->d_fac32);
     p->d_fac32 = nullptr;
     p->fac32_elems = 0;
-    if (hipMalloc(&p->d_fac32, sizeof(float2) * (size_t)nb * nn) != hipSuccess)
+    if (dev_alloc((void**)&p->d_fac32, sizeof(float2) * (size_t)nb * nn) != hipSuccess)
       return fail(p, MSV_ENOMEM, "complex64 factor allocation failed");
     p->fac32_elems = (size_t)nb * nn;
   }
   const size_t inv_bytes = (size_t)nb * ((n + 63) / 64) * 2 * 64 * 64 * (p->precision == 0 ? 16 : 8);
   if (inv_bytes > p->inv_bytes) {
-    if (p->d_inv) (void)hipFree(p->d_inv);
+    if (p->d_inv) dev_free(p->d_inv);
     p->d_inv = nullptr;
     p->inv_bytes = 0;
-    if (hipMalloc(&p->d_inv, inv_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "block inverse allocation failed");
+    if (dev_alloc((void**)&p->d_inv, inv_bytes) != hipSuccess) return fail(p, MSV_ENOMEM, "block inverse allocation failed");
     p->inv_bytes = inv_bytes;
   }
   return MSV_OK;
@@ -847,12 +916,13 @@ void msv_batch_destroy(msv_batch* b) {
   }
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->d_list) (void)hipFree(b->d_list);
-  if (b->d_work) (void)hipFree(b->d_work);
+  if (b->d_list) dev_free(b->d_list);
+  if (b->d_work) dev_free(b->d_work);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->st) (void)hipStreamDestroy(b->st);
   delete b;
+  live_add(-1);
 }
 
 const char* msv_batch_last_error(const msv_batch* b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
@@ -884,6 +954,7 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
     if (n != nmax && n % 512 != 0) ok512 = false;
   }
   msv_batch* b = new msv_batch();
+  live_add(1);
   b->plans.assign(plans, plans + n_plans);
   b->A.assign(d_A, d_A + n_plans);
   b->m_lo = m_lo;
@@ -904,8 +975,8 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
     for (int k = 0; k < nbp; ++k)
       list.push_back(msv::LuMat{p->d_fac32 + (size_t)k * n * n, p->d_ipiv + (size_t)k * n, p->d_info + k, n, 0});
   }
-  if (hipMalloc(&b->d_list, sizeof(msv::LuMat) * list.size()) != hipSuccess ||
-      hipMalloc(&b->d_work, msv::lu_work_bytes(nmax, b->nb, false)) != hipSuccess ||
+  if (dev_alloc((void**)&b->d_list, sizeof(msv::LuMat) * list.size()) != hipSuccess ||
+      dev_alloc((void**)&b->d_work, msv::lu_work_bytes(nmax, b->nb, false)) != hipSuccess ||
       hipMemcpy(b->d_list, list.data(), sizeof(msv::LuMat) * list.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&b->ev_in) != hipSuccess || hipEventCreate(&b->ev_out) != hipSuccess) {
@@ -1104,10 +1175,10 @@ msv_status msv_solve(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_rhs, con
   const size_t n = 4 * (size_t)p->N, vectors = (size_t)(m_hi - m_lo + 1) * n_rhs;
   const size_t need = solve_work_bytes(n, vectors, (size_t)nvb, p->precision);
   if (need > p->work_bytes) {
-    if (p->d_work) (void)hipFree(p->d_work);
+    if (p->d_work) dev_free(p->d_work);
     p->d_work = nullptr;
     p->work_bytes = 0;
-    if (hipMalloc(&p->d_work, need) != hipSuccess) return fail(p, MSV_ENOMEM, "solve workspace allocation failed");
+    if (dev_alloc((void**)&p->d_work, need) != hipSuccess) return fail(p, MSV_ENOMEM, "solve workspace allocation failed");
     p->work_bytes = need;
   }
   const SolveWork w = carve_solve_work(static_cast<char*>(p->d_work), n, vectors, (size_t)nvb, p->precision);
@@ -1235,11 +1306,11 @@ static msv_status ensure_upsampled(msv_plan* p, int U, hipStream_t s) {
     }
   // the previous sub-panel geometry may still be read by work on `s`
   if (hipStreamSynchronize(s) != hipSuccess) return fail(p, MSV_EHIP, "stream synchronize failed");
-  if (p->d_up) (void)hipFree(p->d_up);
+  if (p->d_up) dev_free(p->d_up);
   p->d_up = nullptr;
   p->up_bytes = 0;
   p->up_U = 0;
-  if (hipMalloc(&p->d_up, h.size() * sizeof(double)) != hipSuccess) {
+  if (dev_alloc((void**)&p->d_up, h.size() * sizeof(double)) != hipSuccess) {
     hipGetLastError();
     p->d_up = nullptr;
     return fail(p, MSV_ENOMEM, "sub-panel geometry allocation failed");

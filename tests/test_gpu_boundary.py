@@ -10,7 +10,14 @@
   pinning     a batch pins its plans: factoring more modes than the batch
               holds is refused, and destroying a plan before its batch defers
               the free until the batch goes.
+  allocator   with msv_set_allocator routing the library's buffers through
+              torch's caching allocator, the plan's storage is counted by
+              torch while the plan lives and handed back when it is destroyed,
+              the solution equals the one on hipMalloc'd storage, and the hooks
+              cannot change while a plan exists.
 """
+import gc
+
 import numpy as np
 import pytest
 
@@ -107,3 +114,45 @@ def test_batch_pins_its_plans():
     after = free_bytes()
     print(f"[pinning] plan held {held} B; freed at batch destroy {after - before} B", flush=True)
     assert after - before >= 0.9 * held
+
+
+def test_plans_allocate_from_a_caller_pool():
+    curve, k0, eps1, M, L = geometry.sphere(8), 1.0, 2.25, 16, 64
+    d, p = incident.tilted_direction(30.0)
+    rhs = torch.from_numpy(incident.rhs_modes(curve, [(d, p)], k0, -M, M)).cuda()
+
+    def run():
+        plan = make(curve, k0, eps1, M, L, 1)
+        A = plan.assemble(plan.tabulate(), 0, M)
+        x = torch.empty_like(rhs)
+        torch.cuda.synchronize()
+        before = torch.cuda.memory_allocated()
+        plan.factor(A, 0, M)
+        plan.solve(-M, M, rhs, out=x)
+        torch.cuda.synchronize()
+        return plan, x, torch.cuda.memory_allocated() - before
+
+    gc.collect()
+    msv.use_torch_allocator(False)
+    p0, x0, grown0 = run()
+    p0.close()
+    msv.use_torch_allocator(True)
+    try:
+        p1, x1, grown1 = run()
+        with pytest.raises(msv.MsvError):
+            msv.use_torch_allocator(False)  # a plan is alive
+        live = torch.cuda.memory_allocated()
+        p1.close()
+        freed = live - torch.cuda.memory_allocated()
+    finally:
+        gc.collect()
+        msv.use_torch_allocator(False)
+    n = 4 * curve.n
+    fac = (M + 1) * n * n * 8  # the complex64 factors alone
+    diff = float((x1 - x0).abs().max() / x0.abs().max())
+    print(f"[allocator] torch counts {grown1} B for the factor and solve (hipMalloc: {grown0} B), "
+          f"{freed} B back at destroy; solutions differ by {diff:.1e}", flush=True)
+    assert grown0 == 0
+    assert grown1 >= fac
+    assert freed >= grown1
+    assert diff < 1e-14

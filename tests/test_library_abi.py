@@ -96,3 +96,12 @@ def test_workspace_bytes_without_a_device(lib):
     vec = 129 * 8
     bs = msv.workspace_bytes(1024, 228, 256, nb, vec, 1, lib=lib)
     assert bs - b1 >= vec * n * (3 * 16 + 2 * 8)  # solve workspace
+
+
+def test_allocator_hooks_come_in_pairs(lib):
+    """msv_set_allocator takes both hooks or neither, and with no plan alive
+    (NULL, NULL) restores hipMalloc / hipFree."""
+    alloc = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p)(lambda n, d, c: None)
+    assert lib.msv_set_allocator(ctypes.cast(alloc, ctypes.c_void_p), None, None) == msv.MSV_EINVAL
+    assert b"both hooks" in lib.msv_last_error(None)
+    assert lib.msv_set_allocator(None, None, None) == msv.MSV_OK
