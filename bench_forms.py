@@ -11,6 +11,7 @@ the step for hardware counters (see bench.py).
 from __future__ import annotations
 
 import sys
+import time
 
 import numpy as np
 
@@ -248,6 +249,110 @@ def serving_requests(seed, count, arrivals):
     return reqs
 
 
+SERVING_BODIES = {  # the three workloads at their full sizes: curve, k0, eps1, M, smallest L
+    "sphere": (lambda g: g.sphere(8), 1.0, 2.25, 16, 64),
+    "spheroid": (lambda g: g.spheroid(64, 3.0), 10.0, 4.0, 64, 256),
+    "cylinder": (lambda g: g.cylinder(24), 20.0, 4.0 + 0.1j, 128, 512),
+}
+POOL_WAVES = 32
+
+
+def serving_pools(seed, factors=(1.0, 1.5)):
+    """Per (body, k0 factor): the body and the incident modes of a seeded pool
+    of 32 plane waves, [2M+1, 32, 4N] (a request's incident data is an input:
+    it brings its modes, a subset of its body's pool)."""
+    from workloads import geometry, incident
+    pools = {}
+    for name, (mk, k0, eps1, M, L0) in SERVING_BODIES.items():
+        curve = mk(geometry)
+        for f in factors:
+            k = k0 * f
+            L = valid_fft_len(curve, k, eps1, M, lo=L0)
+            waves = incident.random_directions(seed * 100 + len(pools), POOL_WAVES)
+            t0 = time.perf_counter()
+            rhs = incident.rhs_modes(curve, waves, k, -M, M)
+            print(f"[serving] pool {name} k0={k}: {rhs.shape}, {time.perf_counter() - t0:.1f} s on the host",
+                  file=sys.stderr, flush=True)
+            pools[(name, f)] = (curve, k, eps1, M, L, waves, rhs)
+    return pools
+
+
+def serving_requests_full(pools, seed, count, arrivals, factors=(1.0, 1.5)):
+    """Poisson-stream requests over the three full-size bodies (sphere 1/2,
+    spheroid 1/3, cylinder 1/6), k0 = base times one of `factors`, 1..32
+    plane waves drawn from the body's pool."""
+    from paper_1810_07067_amd.serve import Request
+    rng = np.random.default_rng(seed)
+    names = list(SERVING_BODIES)
+    reqs = []
+    for i in range(count):
+        name = names[int(rng.choice(3, p=[0.5, 1 / 3, 1 / 6]))]
+        f = factors[int(rng.integers(len(factors)))]
+        curve, k, eps1, M, L, waves, pool = pools[(name, f)]
+        idx = np.sort(rng.permutation(POOL_WAVES)[: int(rng.integers(1, POOL_WAVES + 1))])
+        reqs.append(Request(i, name, curve, k, eps1, M, L, [waves[j] for j in idx], float(arrivals[i]),
+                            rhs=np.ascontiguousarray(pool[:, idx, :])))
+    return reqs
+
+
+def bench_serving_full(rules, count=36, seed=9, loads=(0.5, 0.8, 0.95), budget=250 << 30, slots=4,
+                       factors=(1.0, 1.5)):
+    """Serving at the full body sizes, both precisions: the closed-loop rate
+    (every request at t = 0), the two precisions' currents compared request by
+    request, then Poisson streams at `loads` times each precision's own
+    closed-loop rate (cold cache each run).  `factors`: the k0 multiples a
+    body is requested at (more of them, fewer repeated bodies)."""
+    from paper_1810_07067_amd.serve import Server, latency_stats, poisson_arrivals
+    pools = serving_pools(seed, factors)
+    mk = lambda arrivals: serving_requests_full(pools, seed, count, arrivals, factors)
+    names = {r.rid: r.body for r in mk(np.zeros(count))}
+
+    def per_body(res):
+        """Mean build, wait and solve seconds per body, and the builds."""
+        out = {}
+        for b in SERVING_BODIES:
+            rs = [r for r in res.values() if names[r.rid] == b]
+            built = [r.build_s for r in rs if not r.cached]
+            out[b] = {"requests": len(rs), "builds": len(built),
+                      "mean_build_s": float(np.mean(built)) if built else None,
+                      "mean_wait_s": float(np.mean([r.wait_s for r in rs])) if rs else None,
+                      "mean_solve_s": float(np.mean([r.solve_s for r in rs])) if rs else None}
+        return out
+    out, ref = {}, {}
+    for precision in (0, 1):
+        tag = "complex128_lu" if precision == 0 else "complex64_lu_refined"
+        srv = Server(rules, hbm_budget=budget, slots=slots, precision=precision)
+        res, wall = srv.run(mk(np.zeros(count)), realtime=False)
+        srv.close()
+        cap = count / wall
+        row = {"closed_loop_requests_per_s": cap, "closed_loop_wall_s": wall,
+               "closed_loop_mode_solves_per_s": sum(r.mode_solves for r in res.values()) / wall,
+               "cache_hits": srv.hits, "cache_misses": srv.misses, "evictions": srv.evictions,
+               "complex128_fallbacks": srv.fallbacks, "per_body": per_body(res)}
+        if precision == 0:
+            ref = {rid: np.array(r.x) for rid, r in res.items()}  # copies, independent of the server's buffers
+        else:
+            row["max_rel_diff_vs_complex128"] = max(
+                float(np.max(np.abs(r.x - ref[rid])) / np.max(np.abs(ref[rid]))) for rid, r in res.items())
+            ref = {}
+        del res
+        print(f"[serving] {tag} closed loop: {row}", file=sys.stderr, flush=True)
+        for load in loads:
+            t = poisson_arrivals(np.random.default_rng(seed + 1), count, load * cap)
+            srv = Server(rules, hbm_budget=budget, slots=slots, precision=precision)
+            res, wall = srv.run(mk(t), realtime=True)
+            srv.close()
+            st = latency_stats(res)
+            row[f"load_{load}"] = {"qps": load * cap, **st, "requests_per_s": count / wall,
+                                   "mode_solves_per_s": sum(r.mode_solves for r in res.values()) / wall,
+                                   "cache_hit_rate": srv.hits / max(1, srv.hits + srv.misses),
+                                   "evictions": srv.evictions, "wall_s": wall}
+            print(f"[serving] {tag} load {load}: {row[f'load_{load}']}", file=sys.stderr, flush=True)
+            del res
+        out[tag] = row
+    return {"requests": count, "slots": slots, "hbm_budget_bytes": budget, "k0_factors": list(factors), **out}
+
+
 def bench_serving(rules, precision, count=48, seed=5, load=0.8):
     """Closed-loop capacity first (all requests at t = 0), then a Poisson stream
     at `load` times that rate; p50/p99 latency, mode-solves/s, cache hit rate."""
@@ -358,7 +463,6 @@ def bench_extinction(rules, body, rows, precision=1, seed=3, n_points=6, corner_
     (tabulation), T_matgen (assembly), T_solve (factor and solve all modes),
     T_add (one more right-hand side).  corner_first: the cylinder's nodes go
     to the corners first (cylinder_split) instead of the paper's 1e-5 grading."""
-    import time
 
     import torch
     import paper_1810_07067_amd as msv
@@ -430,7 +534,9 @@ def run_form(form):
                 "droplet_table3": bench_extinction(rls, "droplet", TABLE3_DROPLET),
                 "cylinder_table4": bench_extinction(rls, "cylinder", TABLE4_CYLINDER, corner_first=True),
                 "cylinder_table4_panels_to_1e-5": bench_extinction(rls, "cylinder", TABLE4_CYLINDER)}
-    return {"form": "serving", "complex64_lu_refined": bench_serving(rls, 1), "complex128_lu": bench_serving(rls, 0)}
+    return {"form": "serving", "full_size": bench_serving_full(rls),
+            "full_size_mostly_new_bodies": bench_serving_full(rls, loads=(), factors=(1.0, 1.1, 1.2, 1.3, 1.4, 1.5)),
+            "small_bodies": {"complex64_lu_refined": bench_serving(rls, 1), "complex128_lu": bench_serving(rls, 0)}}
 
 
 def profile_target(what, config, modes=None):

@@ -10,7 +10,8 @@ interior material, a mode range and 1..32 incident plane waves.  The server
 * admits requests continuously, in arrival order, as soon as a slot (a worker
   with its own HIP stream) and HBM budget are free -- requests that arrive
   while others are on the GPU start without waiting for them, and their
-  kernels overlap on the device;
+  kernels overlap on the device; while the oldest request waits for memory,
+  requests for bodies already in the cache go ahead of it;
 * evicts idle cache entries, least recently used first, when a new body does
   not fit the budget;
 * records per request the latency from arrival to currents on the host.
@@ -42,6 +43,7 @@ class Request:
     waves: list               # [(d, p)] plane waves
     arrival: float = 0.0      # seconds after the start of the stream
     mu1: complex = 1.0
+    rhs: object = None        # [2M+1, n_waves, 4N] incident modes (host); synthesized from waves if None
 
 
 @dataclass
@@ -52,9 +54,25 @@ class Result:
     cached: bool              # factors came from the cache
     ir_iterations: int
     mode_solves: int          # (2M+1) x n_waves
+    build_s: float = 0.0      # tabulate, assemble and factor (the request that built the entry)
+    wait_s: float = 0.0       # waiting for another request's build of the entry
+    solve_s: float = 0.0      # upload, solve (and refinement), download
+    host: object = None       # the pinned host tensor that x views, held for as long as x is
 
 
 MAX_WAVES = 32  # plane waves per request
+# a modal-kernel table larger than this is never resident: the body is
+# tabulated and assembled in target-row blocks through one reused block
+TABLE_BLOCK_BYTES = 8 << 30
+MAX_SPLIT_MB = 2048  # cached allocator blocks above this are never split
+
+
+def table_block_rows(curve, m_max, n_support):
+    """Target rows per tabulate/assemble block, or None for the whole table."""
+    row = (m_max + 2) * 9 * (curve.n + n_support) * 16
+    if row * curve.n <= TABLE_BLOCK_BYTES:
+        return None
+    return max(16, TABLE_BLOCK_BYTES // row)
 
 
 def entry_bytes(curve, m_max, fft_len, precision, n_support):
@@ -65,7 +83,8 @@ def entry_bytes(curve, m_max, fft_len, precision, n_support):
     MAX_WAVES vectors), as bounded by the library (msv_workspace_bytes:
     geometry, pivots, LU workspace, complex64 factors, block inverses, solve
     workspace), plus the request's right-hand sides and solutions.
-    Transient: the modal-kernel table, freed once the matrices are assembled."""
+    Transient: the modal-kernel table, or the one row block of it that a
+    large body is assembled through, freed once the matrices are assembled."""
     import paper_1810_07067_amd as msv
     N = curve.n
     n = 4 * N
@@ -74,7 +93,8 @@ def entry_bytes(curve, m_max, fft_len, precision, n_support):
     mats = nm * n * n * 16
     plan = msv.workspace_bytes(N, n_support, fft_len, nm, vectors, precision)
     io = 2 * vectors * n * 16
-    table = (m_max + 2) * 9 * N * (N + n_support) * 16
+    rows = table_block_rows(curve, m_max, n_support) or N
+    table = (m_max + 2) * 9 * rows * (N + n_support) * 16
     return mats + plan + io, table
 
 
@@ -94,7 +114,7 @@ class _Entry:
 class Server:
     """Continuous-batching scheduler with a resident factorization cache."""
 
-    def __init__(self, rules, hbm_budget, slots=4, precision=1, ir_tol=1e-12, ir_max_iter=20):
+    def __init__(self, rules, hbm_budget, slots=4, precision=1, ir_tol=1e-12, ir_max_iter=20, torch_pool=True):
         self.rules = rules
         self.budget = int(hbm_budget)
         self.slots = int(slots)
@@ -106,8 +126,32 @@ class Server:
         self.hits = 0
         self.misses = 0
         self.evictions = 0
+        self.fallbacks = 0       # entries refactored with the complex128 LU
         self._mu = threading.Lock()
         self._streams = None
+        # Entries come and go in sizes from megabytes to a third of the
+        # device.  The caching allocator must not carve a freed entry's block
+        # into pieces for smaller ones: a block it may not split is handed
+        # back whole when a larger allocation fails, and the retry succeeds.
+        import torch
+        setting = f"max_split_size_mb:{MAX_SPLIT_MB}"
+        if hasattr(torch._C, "_accelerator_setAllocatorSettings"):
+            torch._C._accelerator_setAllocatorSettings(setting)
+        else:
+            torch.cuda.memory._set_allocator_settings(setting)
+        # The library's own buffers (LU factors, workspaces) from the same pool
+        # as the entries' matrices: memory that an evicted entry gives back is
+        # taken again as it is.  (Returned to the driver instead, a block of
+        # tens of GB has to be cleared again before the next allocation gets
+        # it, about a second per 70 GB.)  Not possible while plans exist.
+        self.torch_pool = False
+        if torch_pool:
+            import paper_1810_07067_amd as msv
+            try:
+                msv.use_torch_allocator()
+                self.torch_pool = True
+            except msv.MsvError:
+                pass
 
     # ------------------------------------------------------------------ keys
     @staticmethod
@@ -137,7 +181,8 @@ class Server:
             del self.cache[victim.key]
             self.used -= victim.bytes
             if victim.plan is not None:
-                victim.plan.close()
+                # every use of an idle entry ended with its stream synchronized
+                victim.plan.close(wait=False)
             victim.plan = None
             victim.A = None
             self.evictions += 1
@@ -163,15 +208,28 @@ class Server:
             plan = msv.plan_from_curve(req.curve, self.rules, req.k0, req.eps1, req.mu1, m_max=req.m_max,
                                        fft_len=req.fft_len, precision=self.precision, ir_tol=self.ir_tol,
                                        ir_max_iter=self.ir_max_iter)
-            torch.cuda.empty_cache()  # matrices of evicted entries go back to the device
+            if not self.torch_pool:
+                torch.cuda.empty_cache()  # matrices of evicted entries go back to the device
+            rows = table_block_rows(req.curve, req.m_max, plan.S)
+            # the matrices from the default stream's pool, where evicted
+            # entries' memory goes back (every use of an entry has finished
+            # before it is evicted)
+            with torch.cuda.stream(torch.cuda.default_stream()):
+                A = torch.empty((req.m_max + 1, plan.n, plan.n), dtype=torch.complex128, device="cuda")
             with torch.cuda.stream(stream):
-                kern = plan.tabulate(stream=stream)
-                A = plan.assemble(kern, 0, req.m_max, stream=stream)
+                if rows is None:
+                    kern = plan.tabulate(stream=stream)
+                    plan.assemble(kern, 0, req.m_max, out=A, stream=stream)
+                else:
+                    plan.assemble_streamed(0, req.m_max, out=A, rows_per_block=rows, stream=stream)
+                    kern = None
                 stream.synchronize()
-                # hand the table back to the device before the factor storage
-                # is allocated (at the largest bodies the two do not fit together)
+                # hand the table back before the factor storage is allocated
+                # (at the largest bodies the two do not fit together; a pooled
+                # allocation that fails releases the cached blocks and retries)
                 del kern
-                torch.cuda.empty_cache()
+                if not self.torch_pool:
+                    torch.cuda.empty_cache()
                 with self._mu:
                     self.used -= table_bytes
                     table_bytes = 0
@@ -189,30 +247,78 @@ class Server:
         import torch
 
         from workloads import incident
+        import paper_1810_07067_amd as msv
         e, builder, table_bytes = admitted
         stream = slot_streams.get()
         try:
+            ts = time.perf_counter()
             if builder:
                 self._build(e, req, table_bytes, stream)
             else:
                 e.ready.wait()
+            tb = time.perf_counter()
             if e.error is not None:
                 raise e.error
             M = req.m_max
-            rhs_h = incident.rhs_modes(req.curve, req.waves, req.k0, -M, M)
+            rhs_h = req.rhs if req.rhs is not None else incident.rhs_modes(req.curve, req.waves, req.k0, -M, M)
             with e.lock:
                 with torch.cuda.stream(stream):
                     rhs = torch.from_numpy(rhs_h).to("cuda", non_blocking=False)
-                    x = e.plan.solve(-M, M, rhs, stream=stream)
-                    xh = x.cpu().numpy()
+                    try:
+                        x = e.plan.solve(-M, M, rhs, stream=stream)
+                    except msv.MsvError as exc:
+                        if exc.status != msv.MSV_ENOCONV:
+                            raise
+                        self._fallback(e, req, stream)
+                        x = e.plan.solve(-M, M, rhs, stream=stream)
+                    # through pinned host memory (torch's host cache): a
+                    # pageable copy of a gigabyte of currents runs at 4 GB/s
+                    xp = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+                    xp.copy_(x, non_blocking=True)
+                    stream.synchronize()
+                    xh = xp.numpy()
                     iters = e.plan.last_ir_iterations()
-            done = time.perf_counter() - t0
-            return Result(req.rid, xh, done - req.arrival, not builder, iters, (2 * M + 1) * len(req.waves))
+            te = time.perf_counter()
+            return Result(req.rid, xh, te - t0 - req.arrival, not builder, iters, (2 * M + 1) * len(req.waves),
+                          build_s=tb - ts if builder else 0.0, wait_s=0.0 if builder else tb - ts,
+                          solve_s=te - tb, host=xp)
         finally:
             with self._mu:
                 e.users -= 1
                 e.last_used = time.perf_counter()
             slot_streams.put(stream)
+
+    def _fallback(self, e, req, stream):
+        """The entry's refinement did not converge (its matrices too
+        ill-conditioned for the complex64 factors): refactor them in place with
+        the complex128 LU, which also shrinks the entry.  Under e.lock."""
+        import paper_1810_07067_amd as msv
+        e.plan.close()
+        e.plan = None
+        plan = msv.plan_from_curve(req.curve, self.rules, req.k0, req.eps1, req.mu1, m_max=req.m_max,
+                                   fft_len=req.fft_len, precision=0)
+        plan.factor(e.A, 0, req.m_max, stream=stream)
+        e.plan = plan
+        (ys, _), (ya, _) = self.rules
+        keep, _ = entry_bytes(req.curve, req.m_max, req.fft_len, 0, ys.shape[1] + 2 * ya.size)
+        with self._mu:
+            self.used -= e.bytes - keep
+            e.bytes = keep
+            self.fallbacks += 1
+
+    def close(self):
+        """Release every cache entry (plans and matrices) back to the device."""
+        import torch
+        with self._mu:
+            for e in self.cache.values():
+                if e.plan is not None:
+                    e.plan.close()
+                e.plan = None
+                e.A = None
+            self.cache.clear()
+            self.used = 0
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------------- run
     def run(self, requests, realtime=True):
@@ -235,17 +341,27 @@ class Server:
             for r in requests:
                 r.arrival = 0.0
         inflight = set()
+        arrived = []  # arrived and not yet admitted, in arrival order
         with ThreadPoolExecutor(max_workers=self.slots) as pool:
-            while pending or inflight:
+            while pending or arrived or inflight:
                 now = time.perf_counter() - t0
-                # admit in arrival order while a slot and memory are free
-                while pending and pending[0][0] <= now and len(inflight) < self.slots:
-                    req = pending[0][2]
+                while pending and pending[0][0] <= now:
+                    arrived.append(heapq.heappop(pending)[2])
+                # admit in arrival order while a slot and memory are free; while
+                # the oldest request waits for memory, requests for bodies
+                # already in the cache (they need none) go ahead of it
+                i = 0
+                while i < len(arrived) and len(inflight) < self.slots:
+                    req = arrived[i]
+                    if i > 0 and self.key(req) not in self.cache:
+                        i += 1
+                        continue
                     with self._mu:
                         adm = self._try_admit(req)
                     if not adm:
-                        break
-                    heapq.heappop(pending)
+                        i += 1
+                        continue
+                    arrived.pop(i)
                     inflight.add(pool.submit(self._serve_one, req, adm, t0, slot_streams))
                 timeout = None
                 if pending and len(inflight) < self.slots:
