@@ -64,6 +64,8 @@ def bench_batching(rules, seed=4, n_bodies=16, M=16):
     return {"bodies": len(plans), "orders": orders, "modes_per_body": M + 1,
             "one_by_one_factor_ms": seq_ms, "batched_factor_ms": bat_ms, "speedup": seq_ms / bat_ms,
             "panel": batch.panel, "tuned_ms": {str(w): batch.tuned_ms(w) for w in (64, 128, 256, 512)},
+            "plane_min": batch.plane_min,
+            "tuned_plane_ms": {str(q): batch.tuned_plane_ms(q) for q in (256, 512, 1024)},
             "per_mode_factorizations_per_s": len(plans) * (M + 1) / (bat_ms * 1e-3),
             "tflops": flops / (bat_ms * 1e-3) / 1e12}
 
@@ -205,7 +207,8 @@ def bench_batching_random_bodies(rules, M=64, budget=200e9, seed=4, n_bodies=64)
             del A0, xr
         rows.append({"group": gi, "bodies": len(plans), "orders": [p.n for p in plans],
                      "one_by_one_factor_ms": solo, "batched_factor_ms": bat, "speedup": solo / bat,
-                     "complex128_fallback": gfall, "parity_vs_complex128": gpar, "panel": batch.panel, "scheduled": "batched" if bat < solo else "one by one",
+                     "complex128_fallback": gfall, "parity_vs_complex128": gpar, "panel": batch.panel,
+                     "plane_min": batch.plane_min, "scheduled": "batched" if bat < solo else "one by one",
                      "scheduled_tflops": gflops / (min(bat, solo) * 1e-3) / 1e12})
         tot_sched += min(bat, solo)
         print(f"[bodies] group {gi}: {len(plans)} bodies, orders {min(p.n for p in plans)}..{max(p.n for p in plans)}, "

@@ -326,11 +326,26 @@ msv_status msv_batch_create(msv_batch **out, msv_plan *const *plans, msv_c128 *c
 msv_status msv_batch_factor(msv_batch *batch, void *stream);
 void msv_batch_destroy(msv_batch *batch);
 const char *msv_batch_last_error(const msv_batch *batch);
+/* The autotuner chooses the tiling in two stages: the outer panel width (64,
+ * 128, 256 or 512 columns, with trailing updates of at least 256 rows and
+ * columns on 128 x 128 bf16 tiles), then at that width the smallest update
+ * that goes to the 128 x 128 tiles (256, 512 or 1024; smaller updates use
+ * 64 x 64 tiles).  The choice is kept per size class (device, largest order
+ * and matrix count each rounded up to a power of two, and the panel widths
+ * the orders allow); a later batch of a known class is captured with it
+ * untimed. */
 /* outer panel width the autotuner chose (64, 128, 256 or 512) */
 int32_t msv_batch_panel(const msv_batch *batch);
+/* smallest trailing update (rows and columns) on 128 x 128 tiles: 256, 512 or 1024 */
+int32_t msv_batch_plane_min(const msv_batch *batch);
 /* the timed duration in ms of one batched factorization with panel width 64,
  * 128, 256 or 512 (-1 if that candidate was not run) */
 float msv_batch_tuned_ms(const msv_batch *batch, int32_t panel);
+/* the same with the chosen panel width and plane_min 256, 512 or 1024 */
+float msv_batch_tuned_plane_ms(const msv_batch *batch, int32_t plane_min);
+/* 1 if the tiling came from the table of an earlier batch of the same size
+ * class (only the chosen configuration was timed), 0 if tuned here */
+int32_t msv_batch_tuned_from_table(const msv_batch *batch);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,7 @@ EXPORTS = ["msv_plan_create", "msv_plan_destroy", "msv_last_error", "msv_num_nod
            "msv_assemble", "msv_factor", "msv_solve", "msv_last_ir_iterations",
            "msv_batch_create", "msv_batch_factor", "msv_batch_destroy", "msv_batch_last_error",
            "msv_batch_panel", "msv_batch_tuned_ms", "msv_workspace_bytes", "msv_plan_device_bytes", "msv_set_allocator",
+           "msv_batch_plane_min", "msv_batch_tuned_plane_ms", "msv_batch_tuned_from_table",
            "msv_tabulate_rows", "msv_assemble_rows", "msv_solve_noalloc", "msv_solve_noalloc_max_bytes",
            "msv_far_field", "msv_fields"]
 
@@ -108,6 +109,12 @@ def load_library(path: str = LIB_PATH):
     lib.msv_batch_panel.restype = ctypes.c_int32
     lib.msv_batch_tuned_ms.argtypes = [P, ctypes.c_int32]
     lib.msv_batch_tuned_ms.restype = ctypes.c_float
+    lib.msv_batch_plane_min.argtypes = [P]
+    lib.msv_batch_plane_min.restype = ctypes.c_int32
+    lib.msv_batch_tuned_plane_ms.argtypes = [P, ctypes.c_int32]
+    lib.msv_batch_tuned_plane_ms.restype = ctypes.c_float
+    lib.msv_batch_tuned_from_table.argtypes = [P]
+    lib.msv_batch_tuned_from_table.restype = ctypes.c_int32
     lib.msv_tabulate_rows.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_size_t, P]
     lib.msv_tabulate_rows.restype = ctypes.c_int
     lib.msv_assemble_rows.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
@@ -394,6 +401,17 @@ class Batch:
 
     def tuned_ms(self, panel: int) -> float:
         return float(self.lib.msv_batch_tuned_ms(self._h, int(panel)))
+
+    @property
+    def plane_min(self) -> int:
+        return int(self.lib.msv_batch_plane_min(self._h))
+
+    def tuned_plane_ms(self, plane_min: int) -> float:
+        return float(self.lib.msv_batch_tuned_plane_ms(self._h, int(plane_min)))
+
+    @property
+    def from_table(self) -> bool:
+        return bool(self.lib.msv_batch_tuned_from_table(self._h))
 
     def factor(self, stream=None):
         st = self.lib.msv_batch_factor(self._h, _stream_handle(stream))

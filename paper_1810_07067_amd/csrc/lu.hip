@@ -1315,6 +1315,9 @@ struct Batch {
   T* linv;  // [nb][kLinvSlots][64][64] diagonal-block inverses
   __bf16* planes = nullptr;  // bf16 operand planes of the large complex64 updates
   size_t planes_stride = 0;  // elements per matrix
+  // complex64 updates of at least plane_min rows and columns take the
+  // 128 x 128-tile planes kernel, smaller ones the 64 x 64-tile kernels
+  int plane_min = 2 * kBT;
 };
 
 // Workspace split: diagonal-block inverses, then (complex64) room for the
@@ -1343,7 +1346,7 @@ hipError_t gemm(const Batch<typename V2<R>::T>& b, int r0, int rend, int c0, int
   dim3 g((Nc + kGT - 1) / kGT, (Mr + kGT - 1) / kGT, b.nb);
   if constexpr (sizeof(R) == 4) {
     const int RA = (Mr + kBT - 1) / kBT * kBT, RB = (Nc + kBT - 1) / kBT * kBT;
-    if (K % kBK == 0 && Mr >= 2 * kBT && Nc >= 2 * kBT && b.planes &&
+    if (K % kBK == 0 && Mr >= b.plane_min && Nc >= b.plane_min && b.planes &&
         (size_t)kPlanes * (RA + RB) * K <= b.planes_stride) {
       static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_update_planes),
                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBfLds);
@@ -1524,8 +1527,11 @@ hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& 
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
   return factor<float>(make_batch(Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, work), 512, s);
 }
-hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s) {
-  return factor<float>(make_batch(Mats<float2>{nullptr, nullptr, nullptr, 0, nmax, d_list}, nb, nmax, work), panel,
-                       s);
+hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, int plane_min, void* work,
+                            hipStream_t s) {
+  if (plane_min < 2 * kBT) return hipErrorInvalidValue;
+  Batch<float2> bt = make_batch(Mats<float2>{nullptr, nullptr, nullptr, 0, nmax, d_list}, nb, nmax, work);
+  bt.plane_min = plane_min;
+  return factor<float>(bt, panel, s);
 }
 }  // namespace msv

@@ -192,8 +192,10 @@ hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& 
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 // complex64 factorization of a listed batch (d_list on the device) with outer
 // panels of `panel` = 64, 128, 256 or 512 columns; nmax is the largest order, every
-// other order a multiple of `panel`
-hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, void* work, hipStream_t s);
+// other order a multiple of `panel`.  Trailing updates of at least plane_min
+// (>= 256) rows and columns use 128 x 128 tiles, smaller ones 64 x 64.
+hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, int plane_min, void* work,
+                            hipStream_t s);
 
 // Right-hand-side batches for the solves (trsv.hip): up to kVB vectors that
 // use factor `fac`; vector v is stored at element off[v] * n of the work

@@ -7,7 +7,9 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -866,9 +868,24 @@ struct msv_batch {
   hipGraphExec_t exec = nullptr;
   bool pinned = false;  // holds a reference on every plan
   int panel = 128;
-  float tuned_ms[4] = {-1.f, -1.f, -1.f, -1.f};  // panel 64, 128, 256, 512
+  int plane_min = 256;
+  float tuned_ms[4] = {-1.f, -1.f, -1.f, -1.f};   // panel 64, 128, 256, 512 (plane_min 256)
+  float tuned_plane_ms[3] = {-1.f, -1.f, -1.f};   // plane_min 256, 512, 1024 (the chosen panel)
+  bool from_table = false;
   std::string err;
 };
+
+// Tuned (panel, plane_min) per size class: device, largest order and matrix
+// count rounded up to powers of two, and which panel widths the orders allow.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;
+int ceil_log2(long long v) {
+  int l = 0;
+  while ((1LL << l) < v) ++l;
+  return l;
+}
+}  // namespace
 
 static thread_local std::string g_batch_err;
 
@@ -879,14 +896,14 @@ static msv_status batch_fail(msv_batch* b, msv_status st, const std::string& msg
 }
 
 // The launch sequence of one batched factorization, on stream s.
-static hipError_t batch_sequence(msv_batch* b, int panel, hipStream_t s) {
+static hipError_t batch_sequence(msv_batch* b, int panel, int plane_min, hipStream_t s) {
   hipError_t e;
   for (size_t i = 0; i < b->plans.size(); ++i) {
     msv_plan* p = b->plans[i];
     const size_t n = 4 * (size_t)p->N, cnt = (size_t)(b->m_hi - b->m_lo + 1) * n * n;
     if ((e = msv::conv_c64(reinterpret_cast<const double2*>(b->A[i]), p->d_fac32, cnt, s)) != hipSuccess) return e;
   }
-  if ((e = msv::lu_factor_list_c(b->d_list, b->nb, b->nmax, panel, b->d_work, s)) != hipSuccess) return e;
+  if ((e = msv::lu_factor_list_c(b->d_list, b->nb, b->nmax, panel, plane_min, b->d_work, s)) != hipSuccess) return e;
   const int nbp = b->m_hi - b->m_lo + 1;
   for (msv_plan* p : b->plans) {
     const int n = 4 * p->N;
@@ -897,10 +914,10 @@ static hipError_t batch_sequence(msv_batch* b, int panel, hipStream_t s) {
   return hipSuccess;
 }
 
-static hipError_t batch_capture(msv_batch* b, int panel, hipGraph_t* g, hipGraphExec_t* x) {
+static hipError_t batch_capture(msv_batch* b, int panel, int plane_min, hipGraph_t* g, hipGraphExec_t* x) {
   hipError_t e = hipStreamBeginCapture(b->st, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
-  hipError_t e2 = batch_sequence(b, panel, b->st);
+  hipError_t e2 = batch_sequence(b, panel, plane_min, b->st);
   e = hipStreamEndCapture(b->st, g);
   if (e2 != hipSuccess) return e2;
   if (e != hipSuccess) return e;
@@ -983,32 +1000,68 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
     msv_batch_destroy(b);
     return batch_fail(nullptr, MSV_ENOMEM, "batch allocation failed");
   }
-  // autotune the outer panel width: capture, run once to warm up, time once
+  // Autotune the tiling: the outer panel width (64, 128, 256, 512) with the
+  // planes kernel from 256, then at that width the smallest update that goes
+  // to the planes kernel (256, 512, 1024).  Each candidate is captured, run
+  // once to warm up and timed once; the fastest graph is kept.  A size class
+  // tuned before in this process takes its choice from the table untimed.
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  const int cands[4] = {64, 128, 256, 512};
-  int best_c = -1;
-  for (int c = 0; c < 4 && e == hipSuccess; ++c) {
-    if ((cands[c] == 128 && !ok128) || (cands[c] == 256 && !ok256) || (cands[c] == 512 && !ok512)) continue;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const auto key = std::make_tuple(dev, ceil_log2(b->nmax), ceil_log2(b->nb),
+                                   (ok128 ? 1 : 0) | (ok256 ? 2 : 0) | (ok512 ? 4 : 0));
+  std::pair<int, int> known{0, 0};
+  {
+    std::lock_guard<std::mutex> l(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) known = it->second;
+  }
+  float best_ms = -1.f;
+  auto try_one = [&](int panel, int plane_min, float* slot) {
     hipGraph_t g = nullptr;
     hipGraphExec_t x = nullptr;
-    e = batch_capture(b, cands[c], &g, &x);
+    float ms = -1.f;
+    e = batch_capture(b, panel, plane_min, &g, &x);
     if (e == hipSuccess) e = hipGraphLaunch(x, b->st);
     if (e == hipSuccess) e = hipEventRecord(b->ev_in, b->st);
     if (e == hipSuccess) e = hipGraphLaunch(x, b->st);
     if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->st);
     if (e == hipSuccess) e = hipEventSynchronize(b->ev_out);
-    if (e == hipSuccess) e = hipEventElapsedTime(&b->tuned_ms[c], b->ev_in, b->ev_out);
-    const bool best = e == hipSuccess && (best_c < 0 || b->tuned_ms[c] < b->tuned_ms[best_c]);
-    if (best) {
-      best_c = c;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev_in, b->ev_out);
+    if (slot) *slot = ms;
+    if (e == hipSuccess && (best_ms < 0.f || ms < best_ms)) {
+      best_ms = ms;
       if (b->exec) (void)hipGraphExecDestroy(b->exec);
       if (b->graph) (void)hipGraphDestroy(b->graph);
       b->exec = x;
       b->graph = g;
-      b->panel = cands[c];
+      b->panel = panel;
+      b->plane_min = plane_min;
     } else {
       if (x) (void)hipGraphExecDestroy(x);
       if (g) (void)hipGraphDestroy(g);
+    }
+  };
+  const int cands[4] = {64, 128, 256, 512}, planes[3] = {256, 512, 1024};
+  if (known.first) {
+    b->from_table = true;
+    try_one(known.first, known.second, nullptr);
+    for (int c = 0; c < 4; ++c)
+      if (cands[c] == b->panel) b->tuned_ms[c] = best_ms;
+    for (int q = 0; q < 3; ++q)
+      if (planes[q] == b->plane_min) b->tuned_plane_ms[q] = best_ms;
+  } else {
+    for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+      if ((cands[c] == 128 && !ok128) || (cands[c] == 256 && !ok256) || (cands[c] == 512 && !ok512)) continue;
+      try_one(cands[c], planes[0], &b->tuned_ms[c]);
+    }
+    const int panel = b->panel;
+    for (int c = 0; c < 4; ++c)
+      if (cands[c] == panel) b->tuned_plane_ms[0] = b->tuned_ms[c];
+    for (int q = 1; q < 3 && e == hipSuccess; ++q) try_one(panel, planes[q], &b->tuned_plane_ms[q]);
+    if (e == hipSuccess && b->exec) {
+      std::lock_guard<std::mutex> l(g_tune_mu);
+      g_tune[key] = std::make_pair(b->panel, b->plane_min);
     }
   }
   // leave the plans factored by the chosen configuration
@@ -1030,6 +1083,16 @@ msv_status msv_batch_create(msv_batch** out, msv_plan* const* plans, msv_c128* c
   *out = b;
   return MSV_OK;
 }
+
+int32_t msv_batch_plane_min(const msv_batch* b) { return b ? b->plane_min : 0; }
+
+float msv_batch_tuned_plane_ms(const msv_batch* b, int32_t plane_min) {
+  if (!b) return -1.f;
+  return plane_min == 256 ? b->tuned_plane_ms[0] : plane_min == 512 ? b->tuned_plane_ms[1]
+         : plane_min == 1024 ? b->tuned_plane_ms[2] : -1.f;
+}
+
+int32_t msv_batch_tuned_from_table(const msv_batch* b) { return b && b->from_table ? 1 : 0; }
 
 float msv_batch_tuned_ms(const msv_batch* b, int32_t panel) {
   if (!b) return -1.f;

@@ -1,7 +1,10 @@
 """Batching form through the C-ABI: the per-mode systems of several bodies of
 different orders factored by one captured launch sequence, compared with the
 plain complex128 path of each body on its own (1e-10 relative), replayed
-twice (bit-identical), and the argument checks."""
+twice (bit-identical), the autotuner's two stages (panel width, then the
+smallest update on 128 x 128 tiles) and its table (a second batch of the
+same size class takes the choice untimed, with the same factors), and the
+argument checks."""
 import numpy as np
 import pytest
 
@@ -52,9 +55,18 @@ def test_batched_factor_matches_plain_path():
     batch = msv.Batch(plans, mats, 0, M)
     print(f"[batch] panel {batch.panel}: " + ", ".join(f"{batch.tuned_ms(w):.3f} ms ({w})" for w in (64, 128, 256, 512)),
           flush=True)
+    print(f"[batch] plane_min {batch.plane_min}: " +
+          ", ".join(f"{batch.tuned_plane_ms(q):.3f} ms ({q})" for q in (256, 512, 1024)), flush=True)
     assert batch.panel in (64, 128, 256, 512) and batch.tuned_ms(batch.panel) > 0
-    # a timed candidate is never faster than the one kept
-    assert all(batch.tuned_ms(w) < 0 or batch.tuned_ms(w) >= batch.tuned_ms(batch.panel) for w in (64, 128, 256, 512))
+    assert batch.plane_min in (256, 512, 1024)
+    if not batch.from_table:  # (an earlier batch of this size class in the process would have tuned it)
+        # a timed candidate is never faster than the one kept; the second
+        # stage starts from the first stage's choice
+        kept = batch.tuned_plane_ms(batch.plane_min)
+        assert all(batch.tuned_ms(w) < 0 or batch.tuned_ms(w) >= batch.tuned_ms(batch.panel)
+                   for w in (64, 128, 256, 512))
+        assert all(0 < kept <= batch.tuned_plane_ms(q) for q in (256, 512, 1024))
+        assert batch.tuned_plane_ms(256) == batch.tuned_ms(batch.panel)
     first = []
     for p, rhs, ref in zip(plans, rhss, refs):
         x = p.solve(-M, M, rhs).cpu().numpy()
@@ -65,7 +77,17 @@ def test_batched_factor_matches_plain_path():
     batch.factor()  # graph replay
     for p, rhs, x0 in zip(plans, rhss, first):
         assert np.array_equal(p.solve(-M, M, rhs).cpu().numpy(), x0)
+    chosen = (batch.panel, batch.plane_min)
     batch.close()
+    # the same size class again: the tiling comes from the table, untimed
+    # except for the chosen configuration, and the factors are the same
+    again = msv.Batch(plans, mats, 0, M)
+    assert again.from_table and (again.panel, again.plane_min) == chosen
+    assert again.tuned_ms(again.panel) > 0 and again.tuned_plane_ms(again.plane_min) > 0
+    assert sum(again.tuned_ms(w) > 0 for w in (64, 128, 256, 512)) == 1
+    for p, rhs, x0 in zip(plans, rhss, first):
+        assert np.array_equal(p.solve(-M, M, rhs).cpu().numpy(), x0)
+    again.close()
 
 
 def test_batch_rejects_bad_arguments():
