@@ -17,14 +17,19 @@
                      currents equal to the oracle's to max(1e-10, 4 sens)
                      (L2-weighted), sens being the oracle's own change under
                      1e-14 kernel noise.
-  droplet, cylinder  the same test at the sizes of the first rows of Tables 3
-                     and 4 (a conical point on the axis; edges with corner
-                     panels near 1e-5), E_error below the printed values; the
-                     droplet's currents also against the oracle's.
+  starfish, droplet, the same test at the sizes of the first rows of Tables 2,
+  cylinder           3 and 4 (a body reaching toward the loop; a conical
+                     point on the axis; edges with corner panels near 1e-5),
+                     E_error below the printed values; the starfish's and the
+                     droplet's currents against the oracle's, the cylinder's
+                     interior fields against stored oracle fields.
   extinction theorem for the direct system on the sphere: the exterior
                      representation evaluated inside is -E_inc (3e-9, the
                      oracle's own floor on this body).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -215,22 +220,60 @@ def test_extinction_droplet():
     assert err < 2.71e-10, err
 
 
-def test_extinction_cylinder():
-    """Table 4's first row: k0 = 2, k1 = 1, N_f = 9, about 1312 points (81
-    panels: 26 base panels, the four corner panels refined 14 levels down to
-    about 1e-5); printed E_error 4.11e-9."""
-    curve, k0, k1, M, L = geometry.cylinder(14, 6.5), 2.0, 1.0, 9, 64
-    while not KernelParams(k0, k1, M, L, float(curve.r.max())).valid:
+def test_extinction_starfish():
+    """Table 2's first row: the rotated starfish of Example 2, k0 = 5, k1 = 2,
+    N_f = 10, 224 points (14 equal panels in t); printed E_error 1.24e-9.  The
+    currents against the oracle's on the same system."""
+    curve, k0, k1, M, L = geometry.starfish(14), 5.0, 2.0, 10, 64
+    sup, kp = oracle_setup(curve, k0, (k1 / k0) ** 2, M, L)
+    while not kp.valid:
         L *= 2
-    plan, x, _ = _loop_solve(curve, k0, k1, M, L, 1)
+        sup, kp = oracle_setup(curve, k0, (k1 / k0) ** 2, M, L)
+    tab = oracle_table(curve, sup, kp)
+    w = geometry.gl_weights(curve)
+    args = (k0, kp.k1, k0, 1.0, 1.0, (k1 / k0) ** 2, 1.0, w)
+    mats = [oasm.assemble_mode(curve, sup, tab, m, *args, formulation="indirect") for m in range(M + 1)]
+    plan, x, rhs = _loop_solve(curve, k0, k1, M, L, 1)
+    xo = osolve.solve_modes(mats, w, rhs.cpu().numpy(), -M, M)
+    sw = np.sqrt(np.repeat(w, 4))
+    cur = np.linalg.norm(sw * (x.cpu().numpy() - xo)) / np.linalg.norm(sw * xo)
     rng = np.random.default_rng(3)
-    rr, zz, th = 0.5 * np.sqrt(rng.uniform(0, 1, 6)), rng.uniform(-0.5, 0.5, 6), rng.uniform(0, 2 * np.pi, 6)
-    pts = np.stack([rr * np.cos(th), rr * np.sin(th), zz], axis=1)
+    v = rng.standard_normal((6, 3))
+    pts = v / np.linalg.norm(v, axis=1)[:, None] * rng.uniform(0, 0.75, (6, 1))  # inside the ball of radius 1.5
     E, H = plan.fields(-M, M, x, pts, "interior", upsample=4)
     El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], k1, k0, 1.0)
     err = e_error(E[0].cpu().numpy(), H[0].cpu().numpy(), El(pts), Hl(pts))
-    print(f"[extinction] cylinder {curve.n} points: E_error {err:.3e}", flush=True)
+    print(f"[extinction] starfish 224 points: E_error {err:.3e}, currents vs oracle {cur:.3e}", flush=True)
+    assert cur < 1e-10, cur
+    assert err < 1.24e-9, err
+
+
+def test_extinction_cylinder():
+    """Table 4's first row: k0 = 2, k1 = 1, N_f = 9, about 1312 points (81
+    panels: 26 base panels, the four corner panels refined 14 levels down to
+    about 1e-5); printed E_error 4.11e-9.  The interior fields also against
+    the oracle's (tests/golden/extinction_cylinder_row1.json, written by
+    make_extinction_cylinder.py from oracle/ alone) to 1e-10 relative, the
+    far-field bar, below the E_error itself."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "extinction_cylinder_row1.json")))
+    curve, k0, k1, M, L = geometry.cylinder(14, 6.5), 2.0, 1.0, 9, 64
+    while not KernelParams(k0, k1, M, L, float(curve.r.max())).valid:
+        L *= 2
+    assert (curve.n, L) == (int(gold["body"].split("N = ")[1]), gold["L"])
+    plan, x, _ = _loop_solve(curve, k0, k1, M, L, 1)
+    pts = np.array(gold["points"])
+    E, H = plan.fields(-M, M, x, pts, "interior", upsample=4)
+    E, H = E[0].cpu().numpy(), H[0].cpu().numpy()
+    El, Hl = incident.current_loop(LOOP["center"], LOOP["radius"], k1, k0, 1.0)
+    err = e_error(E, H, El(pts), Hl(pts))
+    cplx = lambda a: np.array([complex(*v) for v in a]).reshape(-1, 3)
+    Eo, Ho = cplx(gold["E"]), cplx(gold["H"])
+    scale = max(np.abs(Eo).max(), np.abs(Ho).max())
+    par = max(np.abs(E - Eo).max(), np.abs(H - Ho).max()) / scale
+    print(f"[extinction] cylinder {curve.n} points: E_error {err:.3e} (oracle {gold['E_error']:.3e}), "
+          f"fields vs oracle {par:.3e}", flush=True)
     assert err < 4.11e-9, err
+    assert par < 1e-10, par
 
 
 @pytest.fixture(scope="module")
