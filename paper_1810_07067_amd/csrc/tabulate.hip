@@ -272,10 +272,10 @@ __device__ void elliptic_ke(double kp2, double& K, double& E) {
 }
 
 // LDS position of element i of a transform sequence: one element of padding
-// per 16 spreads the bit-reversed stores of the transforms (indices that
+// per 32 spreads the bit-reversed stores of the transforms (indices that
 // differ only in their high bits) over distinct banks.
-__device__ __forceinline__ int lpos(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int seq_stride(int N) { return N + 1 + ((N + 1) >> 4) + 1; }
+__device__ __forceinline__ int lpos(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int seq_stride(int N) { return N + 1 + ((N + 1) >> 5) + 1; }
 
 // Spectra X1_n, X3_n (n = 0..Mq) of 1/rho and 1/rho^3 for one near pair:
 // xs(n) = (X1_n, X3_n) for n <= Mq, xs(Mq + 1) = 0 (xs(n) returns a reference).
@@ -568,10 +568,17 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
   const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (item >= n_items) return;
   const int stride = seq_stride(N), stride2 = seq_stride(2 * N);
-  double2* tw = smem2;                 // [N]: e^{-2 pi i k / 2N}
-  double2* cs = tw + N;                // [N/2 + 1] (cos, sin)(pi j / N)
-  double* s2 = reinterpret_cast<double*>(cs + H + 1);  // [N + 1] sin^2(pi j / 2N)
-  double2* geo2 = reinterpret_cast<double2*>(s2 + N + 2);  // [TP][3]: (rt, dr), (dz, flag), (1/sigma, -)
+  // Azimuth tables.  The twiddles live in LDS: near workgroups hold all N of
+  // e^{-2 pi i k / 2N} (the 2N-point synthesis, and every second entry for
+  // the N-point transforms), far ones only the N/2 of e^{-2 pi i k / N}.
+  // cs [N/2 + 1] = (cos, sin)(pi j / N) and s2 [N + 1] = sin^2(pi j / 2N) are
+  // read from the plan's copy in global memory (a few KB, cache-resident):
+  // at L = 512 that leaves room in LDS for a fourth far and a third near
+  // workgroup per CU.
+  double2* tw = smem2;
+  const double2* cs = P.tabs + N;
+  const double* s2 = reinterpret_cast<const double*>(P.tabs + N + H + 1);
+  double2* geo2 = tw + (NEAR ? N : H);  // [TP][3]: (rt, dr), (dz, flag), (1/sigma, -)
   double2* f1 = geo2 + 3 * TP;         // [9 TP]
   double2* S = f1 + 10 * TP;           // [TP][9][stride]
   double2* XS = S + (size_t)TP * kTypes * stride;  // NEAR: [TP][stride2]
@@ -579,11 +586,10 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
   int* srcs = tgt + TP;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kThreads / 64;
-  {
-    // the plan's azimuth tables: N + N/2 + 1 complex, then N + 2 doubles,
-    // laid out as in LDS
-    const int nt2 = N + H + 1 + (N + 2) / 2;
-    for (int i = tid; i < nt2; i += kThreads) tw[i] = P.tabs[i];
+  if constexpr (NEAR) {
+    for (int i = tid; i < N; i += kThreads) tw[i] = P.tabs[i];
+  } else {
+    for (int i = tid; i < H; i += kThreads) tw[i] = P.tabs[2 * i];
   }
   if (tid < TP) {
     int t, src;
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
   const Seqs qs{S, stride, kTypes * TP};
   dct_pre(qs, logN, cs, f1, wave, lane, nwaves);
   __syncthreads();
-  dct_fft(qs, logN, tw, 2, tid, kThreads);
+  dct_fft(qs, logN, tw, NEAR ? 2 : 1, tid, kThreads);
   const double scale = 1.0 / (2.0 * L);  // (2 pi / L) / (4 pi)
   dct_post(qs, logN, P.M2, scale, f1, wave, lane, nwaves);
   __syncthreads();
@@ -717,9 +723,10 @@ hipError_t launch_one(const TabParams& P, hipStream_t s) {
   int logTP = 0;
   while ((1 << logTP) < TP) ++logTP;
   const int stride = seq_stride(N);
-  const size_t lds = sizeof(double2) * ((size_t)N + (N / 2 + 1) + 3 * TP + 10 * TP +
-                                        (size_t)TP * kTypes * stride + (NEAR ? (size_t)TP * seq_stride(2 * N) : 0)) +
-                     sizeof(double) * (N + 2) + sizeof(int) * 2 * TP;
+  const size_t tables = sizeof(double2) * (size_t)(NEAR ? N : N / 2);
+  const size_t lds = tables + sizeof(double2) * ((size_t)3 * TP + 10 * TP + (size_t)TP * kTypes * stride +
+                                                 (NEAR ? (size_t)TP * seq_stride(2 * N) : 0)) +
+                     sizeof(int) * 2 * TP;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tabulate_kernel<NEAR, K1C>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
