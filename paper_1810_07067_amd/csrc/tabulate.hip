@@ -416,10 +416,19 @@ __device__ void dct_pre(const Seqs& q, int logN, const double2* cs, double2* f1,
   }
 }
 
+// Twiddle idx of a table holding hq entries: entry hq + k is -i times entry
+// k, which holds when the hq entries span a quarter turn (tables that span
+// more are never indexed past hq).
+__device__ __forceinline__ double2 twid(const double2* tw, int idx, int hq) {
+  if (idx < hq) return tw[idx];
+  const double2 w = tw[idx - hq];
+  return make_double2(w.y, -w.x);
+}
+
 // in-place FFT of length N = 2^logN of every sequence (bit-reversed input,
-// natural output); tw[ts * k] = e^{-2 pi i k / N}, k < N/2.  Ends with a
-// barrier.
-__device__ void dct_fft(const Seqs& q, int logN, const double2* tw, int ts, int tid, int nthreads) {
+// natural output); twiddle ts * k = e^{-2 pi i k / N}, k < N/2, from a table
+// of hq entries (twid).  Ends with a barrier.
+__device__ void dct_fft(const Seqs& q, int logN, const double2* tw, int ts, int hq, int tid, int nthreads) {
   const int N = 1 << logN;
   int h = 1, lh = 0;
   for (; 4 * h <= N; h *= 4, lh += 2) {
@@ -431,14 +440,14 @@ __device__ void dct_fft(const Seqs& q, int logN, const double2* tw, int ts, int 
       double2* x = q.base + (size_t)s * q.stride;
       const int i0 = b * 4 * h + p;
       double2 a0 = x[lpos(i0)], a1 = x[lpos(i0 + h)], a2 = x[lpos(i0 + 2 * h)], a3 = x[lpos(i0 + 3 * h)];
-      const double2 w1 = tw[ts * p * (N / (2 * h))];
+      const double2 w1 = twid(tw, ts * p * (N / (2 * h)), hq);
       double2 t = cmul(w1, a1);
       a1 = csub(a0, t);
       a0 = cadd(a0, t);
       t = cmul(w1, a3);
       a3 = csub(a2, t);
       a2 = cadd(a2, t);
-      const double2 w2 = tw[ts * p * (N / (4 * h))], w3 = tw[ts * (p + h) * (N / (4 * h))];
+      const double2 w2 = twid(tw, ts * p * (N / (4 * h)), hq), w3 = twid(tw, ts * (p + h) * (N / (4 * h)), hq);
       t = cmul(w2, a2);
       a2 = csub(a0, t);
       a0 = cadd(a0, t);
@@ -457,7 +466,7 @@ __device__ void dct_fft(const Seqs& q, int logN, const double2* tw, int ts, int 
     for (int g = tid; g < total; g += nthreads) {
       const int s = g >> lh, p = g & (h - 1);
       double2* x = q.base + (size_t)s * q.stride;
-      const double2 a0 = x[lpos(p)], t = cmul(tw[ts * p], x[lpos(p + h)]);
+      const double2 a0 = x[lpos(p)], t = cmul(twid(tw, ts * p, hq), x[lpos(p + h)]);
       x[lpos(p + h)] = csub(a0, t);
       x[lpos(p)] = cadd(a0, t);
     }
@@ -519,6 +528,7 @@ __device__ void dct_post(const Seqs& q, int logN, int mout, double scale, const 
 }
 
 constexpr int kThreads = 256;
+constexpr int kMaxTask = 3;  // samples per thread: TP (N + 1) <= 3 * 256 for N <= 512
 
 // The Legendre-Q spectra of near pairs near[near_lo .. near_hi), one thread
 // per pair, into spec[idx - near_lo][n], n = 0..N (N = L/2; the recurrences are
@@ -568,29 +578,26 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
   const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (item >= n_items) return;
   const int stride = seq_stride(N), stride2 = seq_stride(2 * N);
-  // Azimuth tables.  The twiddles live in LDS: near workgroups hold all N of
-  // e^{-2 pi i k / 2N} (the 2N-point synthesis, and every second entry for
-  // the N-point transforms), far ones only the N/2 of e^{-2 pi i k / N}.
-  // cs [N/2 + 1] = (cos, sin)(pi j / N) and s2 [N + 1] = sin^2(pi j / 2N) are
-  // read from the plan's copy in global memory (a few KB, cache-resident):
-  // at L = 512 that leaves room in LDS for a fourth far and a third near
-  // workgroup per CU.
+  // Azimuth tables.  N/2 twiddles live in LDS: near workgroups hold the
+  // quarter turn of e^{-2 pi i k / 2N} (the 2N-point synthesis, and every
+  // second entry for the N-point transforms; twid derives the rest), far
+  // ones the N/2 of e^{-2 pi i k / N}.  cs [N/2 + 1] = (cos, sin)(pi j / N)
+  // and s2 [N + 1] = sin^2(pi j / 2N) are read from the plan's copy in global
+  // memory (a few KB, cache-resident).  With the near pairs' band-limited
+  // samples sharing the LDS of the sequences (below), four workgroups of
+  // either kind fit a CU at L = 512.
   double2* tw = smem2;
   const double2* cs = P.tabs + N;
   const double* s2 = reinterpret_cast<const double*>(P.tabs + N + H + 1);
-  double2* geo2 = tw + (NEAR ? N : H);  // [TP][3]: (rt, dr), (dz, flag), (1/sigma, -)
+  double2* geo2 = tw + H;  // [TP][3]: (rt, dr), (dz, flag), (1/sigma, -)
   double2* f1 = geo2 + 3 * TP;         // [9 TP]
   double2* S = f1 + 10 * TP;           // [TP][9][stride]
-  double2* XS = S + (size_t)TP * kTypes * stride;  // NEAR: [TP][stride2]
-  int* tgt = reinterpret_cast<int*>(NEAR ? XS + (size_t)TP * stride2 : XS);  // [TP] t, [TP] src
+  double2* XS = S;                     // NEAR: [TP][stride2], in the sequences' LDS until sampled
+  int* tgt = reinterpret_cast<int*>(S + (size_t)TP * kTypes * stride);  // [TP] t, [TP] src
   int* srcs = tgt + TP;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kThreads / 64;
-  if constexpr (NEAR) {
-    for (int i = tid; i < N; i += kThreads) tw[i] = P.tabs[i];
-  } else {
-    for (int i = tid; i < H; i += kThreads) tw[i] = P.tabs[2 * i];
-  }
+  for (int i = tid; i < H; i += kThreads) tw[i] = P.tabs[NEAR ? i : 2 * i];
   if (tid < TP) {
     int t, src;
     bool ok;
@@ -663,23 +670,42 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
       XS[(size_t)p * stride2 + lpos((int)rj)] = v;
     }
     __syncthreads();
-    dct_fft(Seqs{XS, stride2, TP}, logN + 1, tw, 1, tid, kThreads);
+    dct_fft(Seqs{XS, stride2, TP}, logN + 1, tw, 1, H, tid, kThreads);
   }
 
   // samples: one thread per (pair, azimuth j = 0..N); phi_j and pi - phi_j
   // share the tables (cos(pi - phi) = -cos phi)
   const double k0 = P.k0;
   const cd k1 = mk(P.k1r, P.k1i);
-  const int ntask = TP * (N + 1);
-  for (int task = tid; task < ntask; task += kThreads) {
+  const int ntask = TP * (N + 1);  // at most kMaxTask per thread
+  // near pairs: every thread takes its band-limited samples into registers
+  // before any integrand is written over them
+  double xn1[kMaxTask], xn3[kMaxTask];
+  if constexpr (NEAR) {
+#pragma unroll
+    for (int r = 0; r < kMaxTask; ++r) {
+      const int task = tid + r * kThreads;
+      xn1[r] = xn3[r] = 0.0;
+      if (task < ntask) {
+        const int p = task / (N + 1), j = task - p * (N + 1);
+        const double2 xl = XS[(size_t)p * stride2 + lpos(j)];
+        xn1[r] = xl.x * 0.15915494309189535;  // 1/(2 pi)
+        xn3[r] = xl.y * geo2[3 * p + 2].x;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kMaxTask; ++r) {
+    const int task = tid + r * kThreads;
+    if (task >= ntask) continue;
     const int p = task / (N + 1), j = task - p * (N + 1);
     if (geo2[3 * p + 1].y != 1.0) continue;
     const Pair g = make_pair(geo2[3 * p].x, geo2[3 * p].y, geo2[3 * p + 1].x);
     double X1, X3;
     if (NEAR) {
-      const double2 xl = XS[(size_t)p * stride2 + lpos(j)];
-      X1 = xl.x * 0.15915494309189535;  // 1/(2 pi)
-      X3 = xl.y * geo2[3 * p + 2].x;
+      X1 = xn1[r];
+      X3 = xn3[r];
     } else {
       const double rho = sqrt(g.d2 + 4.0 * g.rt * g.rs * s2[j]);
       X1 = 1.0 / rho;
@@ -696,7 +722,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
   const Seqs qs{S, stride, kTypes * TP};
   dct_pre(qs, logN, cs, f1, wave, lane, nwaves);
   __syncthreads();
-  dct_fft(qs, logN, tw, NEAR ? 2 : 1, tid, kThreads);
+  dct_fft(qs, logN, tw, NEAR ? 2 : 1, H, tid, kThreads);
   const double scale = 1.0 / (2.0 * L);  // (2 pi / L) / (4 pi)
   dct_post(qs, logN, P.M2, scale, f1, wave, lane, nwaves);
   __syncthreads();
@@ -723,9 +749,9 @@ hipError_t launch_one(const TabParams& P, hipStream_t s) {
   int logTP = 0;
   while ((1 << logTP) < TP) ++logTP;
   const int stride = seq_stride(N);
-  const size_t tables = sizeof(double2) * (size_t)(NEAR ? N : N / 2);
-  const size_t lds = tables + sizeof(double2) * ((size_t)3 * TP + 10 * TP + (size_t)TP * kTypes * stride +
-                                                 (NEAR ? (size_t)TP * seq_stride(2 * N) : 0)) +
+  // the near samples [TP][stride2] share the sequences' [TP][9][stride]
+  if (seq_stride(2 * N) > kTypes * stride || TP * (N + 1) > kMaxTask * kThreads) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double2) * ((size_t)N / 2 + 3 * TP + 10 * TP + (size_t)TP * kTypes * stride) +
                      sizeof(int) * 2 * TP;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tabulate_kernel<NEAR, K1C>),
