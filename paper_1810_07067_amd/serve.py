@@ -321,15 +321,19 @@ class Server:
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------------- run
+    def _new_streams(self):
+        """One HIP stream per slot."""
+        import torch
+        return [torch.cuda.Stream() for _ in range(self.slots)]
+
     def run(self, requests, realtime=True):
         """Serve `requests` (arrival times in seconds from now).  realtime=False
         treats every request as already arrived.  Returns results by rid and
         the wall time."""
         import queue
 
-        import torch
         if self._streams is None:
-            self._streams = [torch.cuda.Stream() for _ in range(self.slots)]
+            self._streams = self._new_streams()
         slot_streams = queue.Queue()
         for s in self._streams:
             slot_streams.put(s)

@@ -1,8 +1,12 @@
 """Host logic of the serving loop (no GPU): footprints, admission in arrival
-order, least-recently-used eviction of idle factorizations only."""
+order with cache hits passing a request that waits for memory, least-recently-
+used eviction of idle factorizations only."""
+import threading
+import time
+
 import numpy as np
 
-from paper_1810_07067_amd.serve import Request, Server, entry_bytes, poisson_arrivals
+from paper_1810_07067_amd.serve import Request, Result, Server, entry_bytes, poisson_arrivals
 from workloads import geometry, incident, rules
 
 
@@ -53,3 +57,58 @@ def test_poisson_arrivals_rate():
     t = poisson_arrivals(np.random.default_rng(5), 4000, 50.0)
     assert np.all(np.diff(t) > 0)
     assert abs(len(t) / t[-1] - 50.0) < 3.0
+
+
+class _StubPlan:
+    def close(self, wait=True):
+        pass
+
+
+class _StubServer(Server):
+    """The scheduler with the GPU work replaced: a build marks the entry ready
+    and gives its table back; every request holds its slot for `hold` s."""
+
+    def __init__(self, budget, hold=0.2):
+        super().__init__(rules=RULES, hbm_budget=budget, slots=2, torch_pool=False)
+        self.hold = hold
+        self.order = []
+        self._order_mu = threading.Lock()
+
+    def _new_streams(self):
+        return [object() for _ in range(self.slots)]
+
+    def _serve_one(self, req, admitted, t0, slot_streams):
+        e, builder, table = admitted
+        stream = slot_streams.get()
+        try:
+            with self._order_mu:
+                self.order.append(req.rid)
+            if builder:
+                e.plan = _StubPlan()
+                with self._mu:
+                    self.used -= table
+                e.ready.set()
+            else:
+                e.ready.wait()
+            time.sleep(self.hold)
+            return Result(req.rid, None, time.perf_counter() - t0 - req.arrival, not builder, 0, 1)
+        finally:
+            with self._mu:
+                e.users -= 1
+                e.last_used = time.perf_counter()
+            slot_streams.put(stream)
+
+
+def test_cache_hits_pass_a_request_waiting_for_memory():
+    """Budget for one body: request 1 (a second body) must wait until body a is
+    idle, and request 2 (body a again, in the cache) goes ahead of it."""
+    a, b = geometry.sphere(4), geometry.spheroid(4, 2.0)
+    keep, table = entry_bytes(a, 4, 64, 1, S)
+    keep_b, table_b = entry_bytes(b, 4, 64, 1, S)
+    srv = _StubServer(budget=max(keep + table, keep_b + table_b) + keep // 4)
+    reqs = [_req(0, a, "a"), _req(1, b, "b"), _req(2, a, "a")]
+    results, _ = srv.run(reqs, realtime=False)
+    assert sorted(results) == [0, 1, 2]
+    assert srv.order == [0, 2, 1], srv.order
+    assert results[2].cached and not results[1].cached
+    assert srv.hits == 1 and srv.misses == 2 and srv.evictions == 1
