@@ -88,15 +88,17 @@ def lu_traffic(config):
 
 def tab_traffic(config):
     """HBM bytes of one tabulation (committed counter summary, while the
-    tabulation source is unchanged), else None."""
+    tabulation kernels and the shared header that sets their launch chunks
+    are unchanged), else None."""
     import hashlib
     import re
+    csrc = os.path.join(ROOT, "paper_1810_07067_amd", "csrc")
     try:
         text = open(os.path.join(ROOT, "profiles", f"tabulate_{config}_counters.md")).read()
-        src = open(os.path.join(ROOT, "paper_1810_07067_amd", "csrc", "tabulate.hip"), "rb").read()
+        src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("tabulate.hip", "msv_internal.h"))
     except OSError:
         return None
-    h = re.search(r"tabulate\.hip sha256 = ([0-9a-f]{64})", text)
+    h = re.search(r"tabulate\.hip \+ msv_internal\.h sha256 = ([0-9a-f]{64})", text)
     b = re.search(r"tabulation traffic bytes = (\d+)", text)
     if not h or not b or h.group(1) != hashlib.sha256(src).hexdigest():
         return None

@@ -140,7 +140,7 @@ int32_t msv_matrix_order(const msv_plan *plan);
  * before any plan exists, on what a plan of n_nodes nodes, n_support support
  * slots and FFT length fft_len holds once n_modes modes are factored
  * (msv_factor) and a solve of n_solve_vectors (mode, right-hand side) vectors
- * at once has run: geometry, the near pairs' spectra scratch (at most 65536
+ * at once has run: geometry, the near pairs' spectra scratch (at most 262144
  * pairs x (fft_len/2 + 1) x 16 bytes), pivots, LU workspace, complex64 factors
  * (precision 1), diagonal-block inverses and the solve workspace.  It counts
  * the near-pair list and the spectra scratch as if every pair were near, so it

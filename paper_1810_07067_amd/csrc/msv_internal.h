@@ -53,7 +53,7 @@ inline size_t tab_doubles(int L) {
   return 2 * N + 2 * (N / 2 + 1) + (N + 2);
 }
 // near pairs whose spectra the scratch holds at once, and its size in bytes
-constexpr int kSpecCap = 65536;
+constexpr int kSpecCap = 262144;  // a launch of this many threads keeps 16 waves on each CU
 inline size_t spec_bytes(int L, int n_near) {
   const size_t cap = (size_t)(n_near < kSpecCap ? n_near : kSpecCap);
   return cap * (size_t)(L / 2 + 1) * sizeof(double2);

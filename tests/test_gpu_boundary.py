@@ -58,7 +58,7 @@ def test_workspace_bytes_bound_allocations(precision):
     held = q.device_bytes
     bound = msv.workspace_bytes(q.N, q.S, L, M + 1, (2 * M + 1) * len(waves), precision)
     print(f"[workspace] held {held} bound {bound} device delta {before - after}", flush=True)
-    spec_max = min(q.N * (q.N + q.S), 65536) * (L // 2 + 1) * 16  # spectra scratch if every pair were near
+    spec_max = min(q.N * (q.N + q.S), 262144) * (L // 2 + 1) * 16  # spectra scratch if every pair were near
     assert held <= bound <= held + 8 * q.N * (q.N + q.S) + spec_max + (M + 1) * 72 + 256
     # the runtime rounds allocations up; each of ~30 buffers by at most 2 MiB
     assert 0.98 * held <= before - after <= held + (64 << 20)
