@@ -68,41 +68,47 @@ def workload(name="cylinder"):
     return curve, rules.load_rules(), waves, cfg
 
 
-def lu_traffic(config):
-    """HBM bytes of one factorization from the committed rocprofv3 counter
-    summary of this workload, while the LU source is the one the counters
-    were taken on (its SHA-256 is recorded there); None otherwise."""
+def _internal_constant(name):
+    """The value of an integer constant of csrc/msv_internal.h (a constexpr,
+    or the default of a macro), as written there."""
+    import re
+    text = open(os.path.join(ROOT, "paper_1810_07067_amd", "csrc", "msv_internal.h")).read()
+    m = re.search(rf"(?:constexpr int {name} =|#define {name}) (\d+)", text)
+    return m.group(1) if m else None
+
+
+def _counted_bytes(profile, source, constant, label):
+    """HBM bytes recorded under `label` in a committed counter summary, while
+    the kernel source (SHA-256) and the launch constant recorded with them
+    are the current ones; None otherwise."""
     import hashlib
     import re
     try:
-        text = open(os.path.join(ROOT, "profiles", f"lu_{config}_traffic.md")).read()
-        src = open(os.path.join(ROOT, "paper_1810_07067_amd", "csrc", "lu.hip"), "rb").read()
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        src = open(os.path.join(ROOT, "paper_1810_07067_amd", "csrc", source), "rb").read()
+        value = _internal_constant(constant)
     except OSError:
         return None
-    h = re.search(r"lu\.hip sha256 = ([0-9a-f]{64})", text)
-    b = re.search(r"lu traffic bytes per factorization = (\d+)", text)
-    if not h or not b or h.group(1) != hashlib.sha256(src).hexdigest():
+    h = re.search(rf"{re.escape(source)} sha256 = ([0-9a-f]{{64}})", text)
+    c = re.search(rf"{constant} = (\d+)", text)
+    b = re.search(rf"{label} = (\d+)", text)
+    if not h or not c or not b or h.group(1) != hashlib.sha256(src).hexdigest() or c.group(1) != value:
         return None
     return int(b.group(1))
+
+
+def lu_traffic(config):
+    """HBM bytes of one factorization (committed rocprofv3 counter summary of
+    this workload, while the LU source and its number of stream groups are
+    the ones counted), else None."""
+    return _counted_bytes(f"lu_{config}_traffic.md", "lu.hip", "MSV_LU_GROUPS", "lu traffic bytes per factorization")
 
 
 def tab_traffic(config):
     """HBM bytes of one tabulation (committed counter summary, while the
-    tabulation kernels and the shared header that sets their launch chunks
-    are unchanged), else None."""
-    import hashlib
-    import re
-    csrc = os.path.join(ROOT, "paper_1810_07067_amd", "csrc")
-    try:
-        text = open(os.path.join(ROOT, "profiles", f"tabulate_{config}_counters.md")).read()
-        src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("tabulate.hip", "msv_internal.h"))
-    except OSError:
-        return None
-    h = re.search(r"tabulate\.hip \+ msv_internal\.h sha256 = ([0-9a-f]{64})", text)
-    b = re.search(r"tabulation traffic bytes = (\d+)", text)
-    if not h or not b or h.group(1) != hashlib.sha256(src).hexdigest():
-        return None
-    return int(b.group(1))
+    tabulation source and its spectra chunk are the ones counted), else
+    None."""
+    return _counted_bytes(f"tabulate_{config}_counters.md", "tabulate.hip", "kSpecCap", "tabulation traffic bytes")
 
 
 # --------------------------------------------------------------------------

@@ -1516,6 +1516,75 @@ hipError_t factor(const Batch<typename V2<R>::T>& b, int NB, hipStream_t s) {
   return hipSuccess;
 }
 
+// G batches of the same order, batch g factored on stream st[g], each one
+// panel phase behind the one before.  A panel factorization runs one
+// workgroup per matrix and is bound by the latency of its column steps,
+// while a trailing update fills the chip's MFMA units; with every panel of
+// batch g waiting for the same panel of batch g - 1, the panels of one batch
+// run while the updates of others do.  The batches share no memory.  ev:
+// kStaggerEvents events, all on the device of the streams.
+template <typename R>
+hipError_t factor_staggered(const Batch<typename V2<R>::T>* bt, int G, int NB, const hipStream_t* st,
+                            hipEvent_t* ev) {
+  using T = typename V2<R>::T;
+  const int n = bt[0].nmax;
+  if (G < 2 || G > kStaggerMax || n > kPanelThreads * kMaxRowsPerThread) return hipErrorInvalidValue;
+  for (int g = 1; g < G; ++g)
+    if (bt[g].nmax != n) return hipErrorInvalidValue;
+  if (NB != 64 && NB != 128 && NB != 256 && NB != 512) return hipErrorInvalidValue;
+  // ev[0]: the fork; ev[g], 0 < g < G: batch g done; then G - 1 per step.
+  // Steps: n / NB full panels plus at most log2(NB) narrower ones at the end.
+  if (G + (n / NB + 10) * (G - 1) > kStaggerEvents) return hipErrorInvalidValue;
+  MSV_TRY(hipEventRecord(ev[0], st[0]));  // the other streams start after the work queued on st[0]
+  for (int g = 0; g < G; ++g) {
+    if (g) MSV_TRY(hipStreamWaitEvent(st[g], ev[0], 0));
+    hipLaunchKernelGGL(zero_info<T>, dim3(1), dim3(256), 0, st[g], bt[g].d, bt[g].nb);
+    MSV_TRY(hipGetLastError());
+  }
+  hipEvent_t* step_ev = ev + G;
+  for (int k = 0; k < n; step_ev += G - 1) {
+    int w = n - k < NB ? n - k : NB;
+    while (w & (w - 1)) w &= w - 1;
+    for (int g = 0; g < G; ++g) {
+      if (g) MSV_TRY(hipStreamWaitEvent(st[g], step_ev[g - 1], 0));
+      MSV_TRY(panel_rec<R>(bt[g], k, w, k, st[g]));
+      if (g + 1 < G) MSV_TRY(hipEventRecord(step_ev[g], st[g]));
+    }
+    for (int g = 0; g < G; ++g) {
+      MSV_TRY(swaps<R>(bt[g], k, k + w, 0, k, st[g]));
+      MSV_TRY(swaps<R>(bt[g], k, k + w, k + w, -1, st[g]));
+      MSV_TRY(trsm<R>(bt[g], k, w, k + w, -1, k, st[g]));
+      MSV_TRY(gemm<R>(bt[g], k + w, -1, k + w, -1, k, w, st[g]));
+    }
+    k += w;
+  }
+  for (int g = 1; g < G; ++g) {  // st[0] continues after every batch
+    MSV_TRY(hipEventRecord(ev[g], st[g]));
+    MSV_TRY(hipStreamWaitEvent(st[0], ev[g], 0));
+  }
+  return hipSuccess;
+}
+
+// A strided batch cut into G consecutive groups (the first nb mod G one
+// matrix larger), each with its part of the workspace, and factored by
+// factor_staggered.
+template <typename R>
+hipError_t factor_groups_staggered(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& lb,
+                                   void* work, int G, int NB, const hipStream_t* st, hipEvent_t* ev) {
+  using T = typename V2<R>::T;
+  Batch<T> bt[kStaggerMax];
+  int off = 0;
+  char* w = static_cast<char*>(work);
+  for (int g = 0; g < G; ++g) {
+    const int cnt = lb.nb / G + (g < lb.nb % G ? 1 : 0);
+    bt[g] = make_batch(Mats<T>{A + off * lb.stride, ipiv + (size_t)off * lb.n, info + off, lb.stride, lb.n, nullptr},
+                       cnt, lb.n, w);
+    off += cnt;
+    w += lu_work_bytes(lb.n, cnt, sizeof(T) == 16);
+  }
+  return factor_staggered<R>(bt, G, NB, st, ev);
+}
+
 }  // namespace
 
 size_t lu_work_bytes(int n, int nb, bool c128) {
@@ -1526,6 +1595,18 @@ hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& 
 }
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s) {
   return factor<float>(make_batch(Mats<float2>{A, ipiv, info, b.stride, b.n, nullptr}, b.nb, b.n, work), 512, s);
+}
+hipError_t lu_factor_staggered_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, int G,
+                                 const hipStream_t* st, hipEvent_t* ev) {
+  if (G > b.nb) G = b.nb;
+  if (G < 2) return lu_factor_z(A, ipiv, info, b, work, st[0]);
+  return factor_groups_staggered<double>(A, ipiv, info, b, work, G, 256, st, ev);
+}
+hipError_t lu_factor_staggered_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, int G,
+                                 const hipStream_t* st, hipEvent_t* ev) {
+  if (G > b.nb) G = b.nb;
+  if (G < 2) return lu_factor_c(A, ipiv, info, b, work, st[0]);
+  return factor_groups_staggered<float>(A, ipiv, info, b, work, G, 512, st, ev);
 }
 hipError_t lu_factor_list_c(const LuMat* d_list, int nb, int nmax, int panel, int plane_min, void* work,
                             hipStream_t s) {

@@ -190,6 +190,23 @@ struct LuMat {
 // work: lu_work_bytes(n, nb, complex128?) bytes
 hipError_t lu_factor_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
 hipError_t lu_factor_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, hipStream_t s);
+// The same factorizations with the batch cut into G <= kStaggerMax
+// consecutive groups (fewer if nb < G), group g on stream st[g], whose
+// panels each wait for the same panel of group g - 1 (one group's panel
+// factorization overlaps the others' trailing updates).  st[1..] wait for
+// the work queued on st[0] before the call, and st[0] for all of their
+// launches after it.  ev: kStaggerEvents events on the device.
+constexpr int kStaggerMax = 4;
+constexpr int kStaggerEvents = 256;
+#ifndef MSV_LU_GROUPS
+#define MSV_LU_GROUPS 2
+#endif
+constexpr int kLuGroups = MSV_LU_GROUPS;  // groups of a plan's own factorization
+static_assert(kLuGroups >= 1 && kLuGroups <= kStaggerMax, "1 to kStaggerMax groups");
+hipError_t lu_factor_staggered_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, int G,
+                                 const hipStream_t* st, hipEvent_t* ev);
+hipError_t lu_factor_staggered_c(float2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, int G,
+                                 const hipStream_t* st, hipEvent_t* ev);
 // complex64 factorization of a listed batch (d_list on the device) with outer
 // panels of `panel` = 64, 128, 256 or 512 columns; nmax is the largest order, every
 // other order a multiple of `panel`.  Trailing updates of at least plane_min

@@ -66,6 +66,11 @@ struct msv_plan {
   size_t inv_bytes = 0;
   void* d_luw = nullptr;       // LU workspace (block inverses, complex64 update planes)
   size_t luw_bytes = 0;
+  // extra streams and events of the staggered factorization (created at the
+  // first factorization of two or more modes)
+  hipStream_t stag_st[msv::kStaggerMax - 1] = {};
+  hipEvent_t stag_ev[msv::kStaggerEvents] = {};
+  bool stag_ready = false;
   size_t ipiv_elems = 0;
   bool info_checked = false;
   // solve workspace (SolveWork, carved from one allocation)
@@ -286,6 +291,10 @@ static void plan_free(msv_plan* p) {
                   p->d_info, p->d_perm, p->d_inv, p->d_luw, p->d_work, p->d_spec, p->d_tabs, p->d_up};
   for (void* b : bufs)
     if (b) dev_free(b, false);
+  for (hipEvent_t e : p->stag_ev)
+    if (e) hipEventDestroy(e);
+  for (hipStream_t q : p->stag_st)
+    if (q) hipStreamDestroy(q);
   delete p;
   live_add(-1);
 }
@@ -756,8 +765,32 @@ msv_status msv_assemble(msv_plan* p, const msv_c128* d_kern, int32_t m_lo, int32
 }
 
 // Factor nb matrices (complex128 at A64 or complex64 at A32) on s.
+// The extra streams and events of the staggered factorization, created once
+// per plan on the current device.
+static hipError_t stagger_init(msv_plan* p) {
+  if (p->stag_ready) return hipSuccess;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i + 1 < msv::kLuGroups && e == hipSuccess; ++i)
+    if (!p->stag_st[i]) e = hipStreamCreateWithFlags(&p->stag_st[i], hipStreamNonBlocking);
+  for (int i = 0; i < msv::kStaggerEvents && e == hipSuccess; ++i)
+    if (!p->stag_ev[i]) e = hipEventCreateWithFlags(&p->stag_ev[i], hipEventDisableTiming);
+  p->stag_ready = e == hipSuccess;
+  return e;
+}
+
+// Every mode's matrix is factored by the same launches; two or more modes are
+// cut into kLuGroups groups on as many streams, staggered by panel phases.
 static hipError_t factor_groups(msv_plan* p, msv_c128* A64, float2* A32, int n, int nb, hipStream_t s) {
   msv::LuBatch b{n, nb, n, (long long)n * n};
+  if (nb >= 2 && msv::kLuGroups >= 2) {
+    hipError_t e = stagger_init(p);
+    if (e != hipSuccess) return e;
+    hipStream_t st[msv::kStaggerMax] = {s};
+    for (int i = 0; i + 1 < msv::kLuGroups; ++i) st[i + 1] = p->stag_st[i];
+    return A64 ? msv::lu_factor_staggered_z(reinterpret_cast<double2*>(A64), p->d_ipiv, p->d_info, b, p->d_luw,
+                                            msv::kLuGroups, st, p->stag_ev)
+               : msv::lu_factor_staggered_c(A32, p->d_ipiv, p->d_info, b, p->d_luw, msv::kLuGroups, st, p->stag_ev);
+  }
   return A64 ? msv::lu_factor_z(reinterpret_cast<double2*>(A64), p->d_ipiv, p->d_info, b, p->d_luw, s)
              : msv::lu_factor_c(A32, p->d_ipiv, p->d_info, b, p->d_luw, s);
 }

@@ -10,6 +10,8 @@
               both precisions, the residual of each solve and the two
               solutions against each other; N = 3088 is refused.
   (4N = 8192 and the full-size workloads are in test_gpu_fullsize.py.)
+  staggered   five modes factored by one call (two halves on two streams)
+              against one mode per call.
   errors      invalid calls return EINVAL and leave the plan usable.
 """
 import numpy as np
@@ -159,6 +161,35 @@ def test_orders_past_8192(n_nodes):
     print(f"[order {n}] complex128: residual {r0:.3e}; the solutions differ by {d:.3e}", flush=True)
     assert r1 < 1e-12 and r0 < 1e-12, (r1, r0)
     assert d < 1e-10, d
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_staggered_factorization_matches_one_mode_at_a_time(precision):
+    """Five seeded matrices of order 576 factored by one call (two halves of 3
+    and 2 on two streams, the second half's panels after the first's, the
+    last outer panel narrower than the others) and one mode per call (one
+    stream): complex128 solutions bit-identical, complex64 + refinement within
+    1e-12 of each other."""
+    curve = geometry.sphere(9)
+    plan = make_plan(curve, 1.0, 2.0, 1.0, 4, 64, precision=precision)
+    n = plan.n
+    assert n == 576
+    mats, rhs = zip(*(_seeded_system(n, seed=20 + m) for m in range(5)))
+    A = torch.cat(mats)
+    b = torch.cat(rhs)
+    A_all = A.clone()  # the complex128 LU factors in place; the plan keeps the buffer
+    plan.factor(A_all, 0, 4)
+    x_all = plan.solve(0, 4, b)
+    for m in range(5):
+        A_one = A[m:m + 1].clone()
+        plan.factor(A_one, m, m)
+        x_one = plan.solve(m, m, b[m:m + 1])
+        d = (torch.linalg.vector_norm(x_one[0] - x_all[m]) / torch.linalg.vector_norm(x_all[m])).item()
+        print(f"[stagger] precision {precision} mode {m}: difference {d:.3e}", flush=True)
+        if precision == 0:
+            assert torch.equal(x_one[0], x_all[m]), (m, d)
+        else:
+            assert d < 1e-12, (m, d)
 
 
 def test_order_past_12288_is_refused():
