@@ -51,17 +51,18 @@ def workload(name="cylinder"):
     from workloads import geometry, incident, rules
     if name == "cylinder":
         curve = geometry.cylinder(24)
-        cfg = dict(name=name, k0=20.0, eps1=4.0 + 0.1j, mu1=1.0, M=128, L=512, rows_per_block=512,
+        cfg = dict(name=name, k0=20.0, eps1=4.0 + 0.1j, mu1=1.0, M=128, L=512, rows_per_block=128,
                    desc="finite cylinder r=1, h=2, corner panels refined 24 times toward the edges "
                         "(128 panels x 16 nodes, N=2048, 8192 unknowns/mode), |m|<=128, L=512, k0=20, "
                         "eps=4+0.1i, mu=1, 1 plane wave at the paper's default angles, complex64 LU + "
-                        "complex128 refinement, table streamed in 512-row blocks")
+                        "complex128 refinement, table streamed in 128-row blocks")
         waves = [incident.paper_default_direction()]
     elif name == "spheroid":
         curve = geometry.spheroid(64, 3.0)
-        cfg = dict(name=name, k0=10.0, eps1=4.0, mu1=1.0, M=64, L=256, rows_per_block=None,
+        cfg = dict(name=name, k0=10.0, eps1=4.0, mu1=1.0, M=64, L=256, rows_per_block=128,
                    desc="prolate spheroid 1:3, 64 panels x 16 nodes (N=1024, 4096 unknowns/mode), |m|<=64, "
-                        "L=256, k0=10, eps=4, mu=1, 8 plane waves seed 2, complex64 LU + complex128 refinement")
+                        "L=256, k0=10, eps=4, mu=1, 8 plane waves seed 2, complex64 LU + complex128 refinement, "
+                        "table streamed in 128-row blocks")
         waves = incident.random_directions(2, 8)
     else:
         raise ValueError(name)
@@ -77,10 +78,10 @@ def _internal_constant(name):
     return m.group(1) if m else None
 
 
-def _counted_bytes(profile, source, constant, label):
+def _counted_bytes(profile, source, constant, label, rows=None):
     """HBM bytes recorded under `label` in a committed counter summary, while
-    the kernel source (SHA-256) and the launch constant recorded with them
-    are the current ones; None otherwise."""
+    the kernel source (SHA-256), the launch constant and (if given) the table
+    rows per block recorded with them are the current ones; None otherwise."""
     import hashlib
     import re
     try:
@@ -94,6 +95,10 @@ def _counted_bytes(profile, source, constant, label):
     b = re.search(rf"{label} = (\d+)", text)
     if not h or not c or not b or h.group(1) != hashlib.sha256(src).hexdigest() or c.group(1) != value:
         return None
+    if rows is not None:
+        r = re.search(r"rows per block = (\d+)", text)
+        if not r or int(r.group(1)) != rows:
+            return None
     return int(b.group(1))
 
 
@@ -106,9 +111,11 @@ def lu_traffic(config):
 
 def tab_traffic(config):
     """HBM bytes of one tabulation (committed counter summary, while the
-    tabulation source and its spectra chunk are the ones counted), else
-    None."""
-    return _counted_bytes(f"tabulate_{config}_counters.md", "tabulate.hip", "kSpecCap", "tabulation traffic bytes")
+    tabulation source, its spectra chunk and the workload's table rows per
+    block are the ones counted), else None."""
+    rows = workload(config)[3]["rows_per_block"]
+    return _counted_bytes(f"tabulate_{config}_counters.md", "tabulate.hip", "kSpecCap", "tabulation traffic bytes",
+                          rows=rows)
 
 
 # --------------------------------------------------------------------------

@@ -95,7 +95,7 @@ def bench_batching_random_bodies(rules, M=64, budget=200e9, seed=4, n_bodies=64)
     """Batching form at the stated size: all modes |m| <= M of every body.
     The bodies do not fit in HBM together, so they stream through in groups
     whose matrices and plan memory fit `budget`; each group is tabulated and
-    assembled body by body (row blocks of at most 8 GB of table), then
+    assembled body by body (row blocks as the serving form takes them), then
     factored one body after another and again as one batch (one captured
     launch sequence over all (body, mode) matrices, outer panel width tuned),
     and solved for one plane wave.  Per group the faster of the two schedules
@@ -106,6 +106,7 @@ def bench_batching_random_bodies(rules, M=64, budget=200e9, seed=4, n_bodies=64)
     not converge is refactored with the complex128 LU, timed apart."""
     import torch
     import paper_1810_07067_amd as msv
+    from paper_1810_07067_amd import serve
     from workloads import incident
     bodies = random_bodies(seed, n_bodies)
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -141,7 +142,7 @@ def bench_batching_random_bodies(rules, M=64, budget=200e9, seed=4, n_bodies=64)
             except msv.MsvError:
                 skipped += 1  # a tip whose panels grade too steeply, or L beyond 1024
                 continue
-            nb = max(16, min(curve.n, int(8e9 // ((M + 2) * 9 * (curve.n + S) * 16))))
+            nb = serve.table_block_rows(curve, M, S) or curve.n
             mats.append(p.assemble_streamed(0, M, rows_per_block=nb))
             plans.append(p)
             meta.append((curve, k0, eps1, L))

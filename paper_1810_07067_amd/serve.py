@@ -64,15 +64,19 @@ MAX_WAVES = 32  # plane waves per request
 # a modal-kernel table larger than this is never resident: the body is
 # tabulated and assembled in target-row blocks through one reused block
 TABLE_BLOCK_BYTES = 8 << 30
+# The tabulation runs faster in blocks of ~128 target rows than of 512 or of
+# the whole table (each block's table is [mode][type][row][source], and its
+# per-(mode, type) planes lie closer together in memory)
+TABLE_BLOCK_ROWS = 128
 MAX_SPLIT_MB = 2048  # cached allocator blocks above this are never split
 
 
 def table_block_rows(curve, m_max, n_support):
-    """Target rows per tabulate/assemble block, or None for the whole table."""
+    """Target rows per tabulate/assemble block, or None for the whole table:
+    TABLE_BLOCK_ROWS, fewer where that many rows exceed TABLE_BLOCK_BYTES."""
     row = (m_max + 2) * 9 * (curve.n + n_support) * 16
-    if row * curve.n <= TABLE_BLOCK_BYTES:
-        return None
-    return max(16, TABLE_BLOCK_BYTES // row)
+    rows = min(TABLE_BLOCK_ROWS, max(16, TABLE_BLOCK_BYTES // row))
+    return None if rows >= curve.n else rows
 
 
 def entry_bytes(curve, m_max, fft_len, precision, n_support):

@@ -8,7 +8,7 @@ times.
              matrices (currents and far field); power balance of the lossless
              body.
   cylinder   the dyadic cylinder (N = 2048, 128 panels, |m| <= 128, L = 512,
-             k0 = 20, eps1 = 4 + 0.1i), tabulated and assembled in 512-row
+             k0 = 20, eps1 = 4 + 0.1i), tabulated and assembled in 128-row
              blocks as the benchmark does: table rows and assembled rows of
              targets next to the axis and on the 7.45e-9 panels at a corner
              against the oracle; all 129 modes factored (complex64 LU +
@@ -138,11 +138,11 @@ def full_step(plan, cfg, curve, waves, A, block_rows):
     return plan.solve(-M, M, rhs).cpu().numpy(), rhs
 
 
-def compare_precisions(name, block_rows):
+def compare_precisions(name):
     p1, curve, waves, cfg = make_plan(name, 1)
     M = cfg["M"]
     A = torch.empty((M + 1, p1.n, p1.n), dtype=torch.complex128, device="cuda")
-    x1, rhs = full_step(p1, cfg, curve, waves, A, block_rows)
+    x1, rhs = full_step(p1, cfg, curve, waves, A, cfg["rows_per_block"])
     it = p1.last_ir_iterations()
     p1.close()
     torch.cuda.empty_cache()
@@ -170,7 +170,7 @@ def test_spheroid_rows_against_oracle():
 
 
 def test_spheroid_full_size():
-    curve, x = compare_precisions("spheroid", None)
+    curve, x = compare_precisions("spheroid")
     pb = max(abs(absorbed_power(curve, x[:, i])) for i in range(x.shape[1]))
     print(f"[spheroid] power balance {pb:.3e}", flush=True)
     assert pb < 1e-6, pb
@@ -186,7 +186,7 @@ def test_cylinder_corner_and_axis_rows_against_oracle():
 
 
 def test_cylinder_full_size():
-    curve, x = compare_precisions("cylinder", 512)
+    curve, x = compare_precisions("cylinder")
     pa = absorbed_power(curve, x[:, 0])
     print(f"[cylinder] absorbed power (relative) {pa:.3e}", flush=True)
     assert pa > 1e-4  # eps1 = 4 + 0.1i absorbs
