@@ -78,23 +78,27 @@ def _internal_constant(name):
     return m.group(1) if m else None
 
 
-def _counted_bytes(profile, source, constant, label, rows=None):
+def _counted_bytes(profile, source, constants, label, rows=None):
     """HBM bytes recorded under `label` in a committed counter summary, while
-    the kernel source (SHA-256), the launch constant and (if given) the table
-    rows per block recorded with them are the current ones; None otherwise."""
+    the kernel source (SHA-256), the launch constants and (if given) the
+    table rows per block recorded with them are the current ones; None
+    otherwise."""
     import hashlib
     import re
     try:
         text = open(os.path.join(ROOT, "profiles", profile)).read()
         src = open(os.path.join(ROOT, "paper_1810_07067_amd", "csrc", source), "rb").read()
-        value = _internal_constant(constant)
+        values = {c: _internal_constant(c) for c in constants}
     except OSError:
         return None
     h = re.search(rf"{re.escape(source)} sha256 = ([0-9a-f]{{64}})", text)
-    c = re.search(rf"{constant} = (\d+)", text)
     b = re.search(rf"{label} = (\d+)", text)
-    if not h or not c or not b or h.group(1) != hashlib.sha256(src).hexdigest() or c.group(1) != value:
+    if not h or not b or h.group(1) != hashlib.sha256(src).hexdigest():
         return None
+    for c, v in values.items():
+        m = re.search(rf"{c} = (\d+)", text)
+        if not m or m.group(1) != v:
+            return None
     if rows is not None:
         r = re.search(r"rows per block = (\d+)", text)
         if not r or int(r.group(1)) != rows:
@@ -104,9 +108,10 @@ def _counted_bytes(profile, source, constant, label, rows=None):
 
 def lu_traffic(config):
     """HBM bytes of one factorization (committed rocprofv3 counter summary of
-    this workload, while the LU source and its number of stream groups are
-    the ones counted), else None."""
-    return _counted_bytes(f"lu_{config}_traffic.md", "lu.hip", "MSV_LU_GROUPS", "lu traffic bytes per factorization")
+    this workload, while the LU source, its number of stream groups and the
+    smallest order it staggers are the ones counted), else None."""
+    return _counted_bytes(f"lu_{config}_traffic.md", "lu.hip", ("MSV_LU_GROUPS", "kStaggerMinOrder"),
+                          "lu traffic bytes per factorization")
 
 
 def tab_traffic(config):
@@ -114,7 +119,7 @@ def tab_traffic(config):
     tabulation source, its spectra chunk and the workload's table rows per
     block are the ones counted), else None."""
     rows = workload(config)[3]["rows_per_block"]
-    return _counted_bytes(f"tabulate_{config}_counters.md", "tabulate.hip", "kSpecCap", "tabulation traffic bytes",
+    return _counted_bytes(f"tabulate_{config}_counters.md", "tabulate.hip", ("kSpecCap",), "tabulation traffic bytes",
                           rows=rows)
 
 

@@ -282,12 +282,14 @@ class Plan:
 
     def assemble_streamed(self, m_lo, m_hi, out=None, rows_per_block=None, block=None, stream=None):
         """Tabulate and assemble in target-row blocks through one reused table
-        block, so the whole table is never resident."""
+        block, so the whole table is never resident.  Blocks of 128 rows by
+        default: the tabulation's stores into a block's [mode][type][row]
+        [source] table merge better than into larger blocks."""
         import torch
         nm = m_hi - m_lo + 1
         if out is None:
             out = torch.empty((nm, self.n, self.n), dtype=torch.complex128, device="cuda")
-        nb = int(rows_per_block or self.N)
+        nb = min(int(rows_per_block or 128), self.N)
         if block is None:
             block = torch.empty(self.table_rows_shape(nb), dtype=torch.complex128, device="cuda")
         for t0 in range(0, self.N, nb):

@@ -202,6 +202,10 @@ constexpr int kStaggerEvents = 256;
 #define MSV_LU_GROUPS 2
 #endif
 constexpr int kLuGroups = MSV_LU_GROUPS;  // groups of a plan's own factorization
+// A plan staggers its factorization only above this order: at 8192 it gains
+// 8%, at 4096 nothing, and below that the extra waits cost more than the
+// overlap saves (orders 512..2048 factored one body at a time: 1.5x slower).
+constexpr int kStaggerMinOrder = 4097;
 static_assert(kLuGroups >= 1 && kLuGroups <= kStaggerMax, "1 to kStaggerMax groups");
 hipError_t lu_factor_staggered_z(double2* A, int32_t* ipiv, int32_t* info, const LuBatch& b, void* work, int G,
                                  const hipStream_t* st, hipEvent_t* ev);

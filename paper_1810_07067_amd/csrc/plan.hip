@@ -778,11 +778,12 @@ static hipError_t stagger_init(msv_plan* p) {
   return e;
 }
 
-// Every mode's matrix is factored by the same launches; two or more modes are
-// cut into kLuGroups groups on as many streams, staggered by panel phases.
+// Every mode's matrix is factored by the same launches; two or more modes of
+// an order of at least kStaggerMinOrder are cut into kLuGroups groups on as
+// many streams, staggered by panel phases.
 static hipError_t factor_groups(msv_plan* p, msv_c128* A64, float2* A32, int n, int nb, hipStream_t s) {
   msv::LuBatch b{n, nb, n, (long long)n * n};
-  if (nb >= 2 && msv::kLuGroups >= 2) {
+  if (nb >= 2 && msv::kLuGroups >= 2 && n >= msv::kStaggerMinOrder) {
     hipError_t e = stagger_init(p);
     if (e != hipSuccess) return e;
     hipStream_t st[msv::kStaggerMax] = {s};

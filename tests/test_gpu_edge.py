@@ -10,8 +10,8 @@
               both precisions, the residual of each solve and the two
               solutions against each other; N = 3088 is refused.
   (4N = 8192 and the full-size workloads are in test_gpu_fullsize.py.)
-  staggered   five modes factored by one call (two halves on two streams)
-              against one mode per call.
+  staggered   five modes of order 4416 factored by one call (two halves on
+              two streams) against one mode per call.
   errors      invalid calls return EINVAL and leave the plan usable.
 """
 import numpy as np
@@ -165,15 +165,16 @@ def test_orders_past_8192(n_nodes):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_staggered_factorization_matches_one_mode_at_a_time(precision):
-    """Five seeded matrices of order 576 factored by one call (two halves of 3
-    and 2 on two streams, the second half's panels after the first's, the
-    last outer panel narrower than the others) and one mode per call (one
+    """Five seeded matrices of order 4416 (above the order from which a plan
+    staggers its factorization) factored by one call (two halves of 3 and 2
+    on two streams, the second half's panels after the first's, the last
+    outer panels narrower than the others) and one mode per call (one
     stream): complex128 solutions bit-identical, complex64 + refinement within
     1e-12 of each other."""
-    curve = geometry.sphere(9)
+    curve = geometry.sphere(69)
     plan = make_plan(curve, 1.0, 2.0, 1.0, 4, 64, precision=precision)
     n = plan.n
-    assert n == 576
+    assert n == 4416
     mats, rhs = zip(*(_seeded_system(n, seed=20 + m) for m in range(5)))
     A = torch.cat(mats)
     b = torch.cat(rhs)
