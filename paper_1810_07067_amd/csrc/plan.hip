@@ -292,9 +292,9 @@ static void plan_free(msv_plan* p) {
   for (void* b : bufs)
     if (b) dev_free(b, false);
   for (hipEvent_t e : p->stag_ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (hipStream_t q : p->stag_st)
-    if (q) hipStreamDestroy(q);
+    if (q) (void)hipStreamDestroy(q);
   delete p;
   live_add(-1);
 }
@@ -1321,7 +1321,7 @@ msv_status field_common(msv_plan* p, int32_t m_lo, int32_t m_hi, int32_t n_vec, 
     return fail(p, MSV_EINVAL, "too many vectors x nodes or vectors x points for one launch");
   const size_t bytes = (grid_elems + T + extra_elems) * sizeof(double2);
   if (hipMallocAsync(buf, bytes, s) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();  // clear the sticky error of the failed allocation
     return fail(p, MSV_ENOMEM, "surface-grid workspace allocation failed");
   }
   F.N = p->N * U;
@@ -1408,7 +1408,7 @@ static msv_status ensure_upsampled(msv_plan* p, int U, hipStream_t s) {
   p->up_bytes = 0;
   p->up_U = 0;
   if (dev_alloc((void**)&p->d_up, h.size() * sizeof(double)) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();  // clear the sticky error of the failed allocation
     p->d_up = nullptr;
     return fail(p, MSV_ENOMEM, "sub-panel geometry allocation failed");
   }

@@ -310,8 +310,11 @@ class Server:
             e.bytes = keep
             self.fallbacks += 1
 
-    def close(self):
-        """Release every cache entry (plans and matrices) back to the device."""
+    def close(self, release=False):
+        """Drop every cache entry (plans and matrices).  Their memory stays in
+        torch's caching allocator for the next server or tensor of the
+        process; release=True also returns it to the driver (memory returned
+        and taken again has made the next builds several times slower)."""
         import torch
         with self._mu:
             for e in self.cache.values():
@@ -322,7 +325,8 @@ class Server:
             self.cache.clear()
             self.used = 0
         torch.cuda.synchronize()
-        torch.cuda.empty_cache()
+        if release:
+            torch.cuda.empty_cache()
 
     # ------------------------------------------------------------------- run
     def _new_streams(self):
