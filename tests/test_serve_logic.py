@@ -112,3 +112,31 @@ def test_cache_hits_pass_a_request_waiting_for_memory():
     assert srv.order == [0, 2, 1], srv.order
     assert results[2].cached and not results[1].cached
     assert srv.hits == 1 and srv.misses == 2 and srv.evictions == 1
+
+
+def test_close_keeps_the_memory_in_torchs_cache_unless_asked(monkeypatch):
+    """close() drops every entry and closes its plan; the memory goes back to
+    the driver only with release=True (memory returned and taken again by the
+    next server of the process made its builds slower)."""
+    import torch
+    calls = []
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: calls.append("sync"))
+    monkeypatch.setattr(torch.cuda, "empty_cache", lambda *a, **k: calls.append("empty"))
+    closed = []
+
+    class _Plan:
+        def close(self, wait=True):
+            closed.append(wait)
+
+    for release, expect in ((False, ["sync"]), (True, ["sync", "empty"])):
+        calls.clear()
+        closed.clear()
+        srv = Server(rules=RULES, hbm_budget=1 << 30, slots=1, torch_pool=False)
+        e, built, _ = srv._try_admit(_req(0, geometry.sphere(4), "a"))
+        e.plan, e.A = _Plan(), object()
+        if release:
+            srv.close(release=True)
+        else:
+            srv.close()  # the default keeps the cache
+        assert calls == expect and closed == [True]
+        assert not srv.cache and srv.used == 0 and e.plan is None and e.A is None
