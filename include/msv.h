@@ -210,7 +210,14 @@ msv_status msv_assemble_rows(msv_plan *plan, const msv_c128 *d_kern, int32_t t0,
  * (the first solve after a factorization reads the flags, which waits for the
  * factorization).  The plan allocates its factor storage on the first call
  * and whenever the mode count grows; while a batch holds the plan (see below)
- * it refuses, with MSV_EINVAL, a mode count larger than the batch's. */
+ * it refuses, with MSV_EINVAL, a mode count larger than the batch's.
+ * Streams: two or more modes of an order above 4096 are factored in two
+ * halves, the second on a stream the plan owns, each of its panels after the
+ * same panel of the first half (one half's panel factorization overlaps the
+ * other's trailing update).  That stream waits for the work queued on
+ * `stream` before the call, and `stream` for all of it after, so the call is
+ * ordered on `stream` like any other; the factors are bitwise those of one
+ * mode per call. */
 msv_status msv_factor(msv_plan *plan, msv_c128 *d_A, int32_t m_lo, int32_t m_hi, void *stream);
 
 /* Solve A_m x = b for modes m in [m_lo, m_hi] with -M <= m, |m| factored:
