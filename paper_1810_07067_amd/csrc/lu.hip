@@ -1572,6 +1572,7 @@ template <typename R>
 hipError_t factor_groups_staggered(typename V2<R>::T* A, int32_t* ipiv, int32_t* info, const LuBatch& lb,
                                    void* work, int G, int NB, const hipStream_t* st, hipEvent_t* ev) {
   using T = typename V2<R>::T;
+  if (G < 2 || G > kStaggerMax) return hipErrorInvalidValue;
   Batch<T> bt[kStaggerMax];
   int off = 0;
   char* w = static_cast<char*>(work);
