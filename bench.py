@@ -362,7 +362,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the complex128-path comparison and the secondary workload")
     ap.add_argument("--form", choices=["batching", "serving", "extinction"],
-                    help="measure one AI-systems form instead of the step (separate JSON line)")
+                    help="measure the batching, serving or extinction form instead of the step (separate JSON line)")
     ap.add_argument("--modes", type=int, default=None,
                     help="with --profile-target lu: factor modes 0..modes-1 only")
     ap.add_argument("--profile-target", choices=["lu", "tabulate", "copy"],

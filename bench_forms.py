@@ -1,12 +1,13 @@
-"""The two AI-systems forms measured beside the step, and single pieces of
-the step for hardware counters (see bench.py).
+"""The forms measured beside the step (batching, serving, and the paper's
+extinction experiment), and single pieces of the step for hardware counters
+(see bench.py).
 
   batching  the per-mode LUs of many bodies of uneven order in one captured
             launch sequence, against the same bodies factored one at a time
   serving   a request stream of mixed bodies, wavenumbers and plane-wave
             counts through the continuous-batching server (paper_1810_07067_amd.serve)
   extinction the accuracy experiment of Section 6 (indirect system, current
-            loop) at the sizes of Tables 1 and 2, with the tables' phases
+            loop) at the sizes of Tables 1-4, with the tables' phases
 """
 from __future__ import annotations
 
