@@ -56,7 +56,7 @@ inline size_t tab_doubles(int L) {
 constexpr int kSpecCap = 262144;  // a launch of this many threads keeps 16 waves on each CU
 inline size_t spec_bytes(int L, int n_near) {
   const size_t cap = (size_t)(n_near < kSpecCap ? n_near : kSpecCap);
-  return cap * (size_t)(L / 2 + 1) * sizeof(double2);
+  return (cap + 63) / 64 * 64 * (size_t)(L / 2 + 1) * sizeof(double2);  // pairs in groups of 64
 }
 
 // Support-slot record (doubles): offset from the target, the source geometry

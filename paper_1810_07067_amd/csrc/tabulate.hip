@@ -535,6 +535,16 @@ constexpr int kMaxTask = 3;  // samples per thread: TP (N + 1) <= 3 * 256 for N 
 // serial in n).  The exponent e that scales the 1/rho^3 spectrum to the size
 // of the 1/rho one (their transform is shared; see below) is stored in place
 // of the zero entry n = N.
+// Entry n of pair i (counted from the chunk's first pair) in the spectra
+// scratch: pairs in groups of 64, [i / 64][n][i % 64], so that the 64 pairs
+// of a wave, one per thread, store and load each n as one contiguous 1 KB
+// (with a pair's N + 1 entries kept together, every such instruction touched
+// 64 lines).  A workgroup reading one pair's spectrum takes lines that the
+// workgroups of its neighbouring pairs, resident on the same XCD, read too.
+__device__ __forceinline__ size_t spec_at(long long i, int n, int N) {
+  return ((size_t)(i >> 6) * (size_t)(N + 1) + (size_t)n) * 64 + (size_t)(i & 63);
+}
+
 __global__ __launch_bounds__(kThreads) void near_spectra_kernel(TabParams P) {
   const long long idx = (long long)P.near_lo + (long long)blockIdx.x * kThreads + threadIdx.x;
   if (idx >= P.near_hi) return;
@@ -552,17 +562,18 @@ __global__ __launch_bounds__(kThreads) void near_spectra_kernel(TabParams P) {
     dz = sp[kSupDz];
   }
   const Pair g = make_pair(rt, dr, dz);
-  double2* xs = P.spec + (size_t)(idx - P.near_lo) * (N + 1);
-  near_spectra(g, P, [xs](int n) -> double2& { return xs[n]; });
+  double2* spec = P.spec;
+  const long long i = idx - P.near_lo;
+  near_spectra(g, P, [spec, i, N](int n) -> double2& { return spec[spec_at(i, n, N)]; });
   double m1 = 0.0, m3 = 0.0;
   for (int n = 0; n < N; ++n) {
-    const double2 v = xs[n];
+    const double2 v = spec[spec_at(i, n, N)];
     m1 = fmax(m1, fabs(v.x));
     m3 = fmax(m3, fabs(v.y));
   }
   int e = 0;
   if (m1 > 0.0 && m3 > 0.0) e = ilogb(m1) - ilogb(m3);
-  xs[N] = make_double2((double)e, 0.0);
+  spec[spec_at(i, N, N)] = make_double2((double)e, 0.0);
 }
 
 // One workgroup = TP pairs (TP = max(1, 256 / N)), all L/2 + 1 = N + 1
@@ -639,7 +650,7 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
     double isig = 0.15915494309189535;
     if (NEAR && flag == 1.0) {
       const long long idx = (long long)P.near_lo + (long long)item * TP + tid;
-      isig = ldexp(isig, -(int)P.spec[(size_t)(idx - P.near_lo) * (N + 1) + N].x);
+      isig = ldexp(isig, -(int)P.spec[spec_at(idx - P.near_lo, N, N)].x);
     }
     geo2[3 * tid + 2] = make_double2(isig, 0.0);
     tgt[tid] = t;
@@ -660,11 +671,11 @@ __global__ __launch_bounds__(kThreads) void tabulate_kernel(TabParams P, int log
     for (int e = tid; e < (TP << (logN + 1)); e += kThreads) {
       const int p = e >> (logN + 1), j = e & (2 * N - 1);
       const int n = j <= N ? j : 2 * N - j;
-      const double2* xs = P.spec + ((size_t)item * TP + p) * (N + 1);
+      const long long i = (long long)item * TP + p;
       double2 v = make_double2(0.0, 0.0);
       if (n < N && geo2[3 * p + 1].y == 1.0) {
-        v = xs[n];
-        v.y = ldexp(v.y, (int)xs[N].x);
+        v = P.spec[spec_at(i, n, N)];
+        v.y = ldexp(v.y, (int)P.spec[spec_at(i, N, N)].x);
       }
       const unsigned rj = __brev((unsigned)j) >> (31 - logN);
       XS[(size_t)p * stride2 + lpos((int)rj)] = v;
