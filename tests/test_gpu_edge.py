@@ -71,6 +71,21 @@ def test_ragged_sizes_and_mode_ranges(precision):
         assert err < 1e-10, (lo, hi, err)
 
 
+def test_ragged_row_blocks_reproduce_the_table_and_matrices():
+    """Row blocks of 48 target rows (the last one 16) tabulate the same table,
+    and assemble the same matrices, bit for bit as the whole table."""
+    curve = geometry.sphere(7)
+    plan = make_plan(curve, 1.5, 2.0 + 0.05j, 1.0, 5, 64, precision=1)
+    full = plan.tabulate()
+    parts = [plan.tabulate_rows(t0, min(48, curve.n - t0)) for t0 in range(0, curve.n, 48)]
+    assert torch.equal(torch.cat(parts, dim=2), full)
+    A_full = plan.assemble(full, 0, 5)
+    A_blocks = plan.assemble_streamed(0, 5, rows_per_block=48)
+    assert torch.equal(A_blocks, A_full)
+    A_default = plan.assemble_streamed(0, 5)  # 128-row blocks: one block for 112 nodes
+    assert torch.equal(A_default, A_full)
+
+
 def test_single_mode():
     curve, k0, eps1, M, L = geometry.sphere(7), 0.5, 3.0, 0, 32
     sup, kp = oracle_setup(curve, k0, eps1, M, L)

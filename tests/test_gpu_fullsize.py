@@ -185,6 +185,21 @@ def test_cylinder_corner_and_axis_rows_against_oracle():
         check_rows(plan, curve, cfg, t0, nt, [0, 1, 64, 128])
 
 
+def test_cylinder_block_of_two_spectra_chunks_matches_small_block():
+    """A 512-row block of the cylinder holds more near pairs than one chunk
+    of the near-pair spectra scratch (262144 pairs), so its tabulation runs
+    two chunks; its last rows 510, 511 (near pairs in the second chunk) equal
+    bit for bit the first two rows of the 4-row block 510..513 (one chunk),
+    which the test above checks against the oracle."""
+    plan, curve, _, cfg = make_plan("cylinder", 1)
+    big = plan.tabulate_rows(0, 512)
+    small = plan.tabulate_rows(510, 4)
+    assert big.shape[2] == 512 and small.shape[2] == 4
+    assert torch.equal(big[:, :, 510:512], small[:, :, 0:2])
+    del big, small
+    torch.cuda.empty_cache()
+
+
 def test_cylinder_full_size():
     curve, x = compare_precisions("cylinder")
     pa = absorbed_power(curve, x[:, 0])
